@@ -1,0 +1,170 @@
+"""Seeded synthetic inputs shaped like the paper's workloads.
+
+This module holds input generation only -- none of the eigensolver's arithmetic -- and is the
+single place that both the CPU oracle's tests and the GPU tests/bench draw inputs from.
+
+The paper's matrices (DFT sequences NaCl and AuAg, BSE problems; Sec. 6, Table 3) are not
+available; these generators stand in for them:
+
+  * H = Q diag(lam) Q^H with Q a Haar-random unitary (QR of a complex Gaussian with the phase
+    fix Q diag(R_ii/|R_ii|)) and a prescribed spectrum lam, symmetrised as (H + H^H)/2;
+  * "uniform" spectrum: i.i.d. U[-1, 1], sorted (isolated problem of order 1000);
+  * "clustered" spectrum: 6 Gaussian clusters (standard deviation 1e-3) centred at
+    -1.0, -0.9, ..., -0.5, the rest i.i.d. U[-0.4, 2.0], sorted; the number of clustered values
+    is a parameter (600 for the order-10000/20000 problems, 2400 for order 60000);
+  * sequences: H_{k+1} = H_k + eps * ||H_k||_2 * E_k with E_k = (G + G^H)/2 of a complex
+    Gaussian G, scaled to unit spectral norm;
+  * start blocks and Lanczos start vectors: complex Gaussian (real and imaginary parts N(0, 1)).
+
+Seeds: NumPy Generator(PCG64(seed)).  Large matrices can be generated on a torch device
+(``hermitian_torch``) with the same recipe; those bytes differ from the CPU ones but the
+spectrum is the same prescribed lam.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+
+CLUSTER_CENTRES = (-1.0, -0.9, -0.8, -0.7, -0.6, -0.5)
+
+
+def rng(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def complex_gaussian(g: np.random.Generator, *shape) -> np.ndarray:
+    return g.standard_normal(shape) + 1j * g.standard_normal(shape)
+
+
+def spectrum_uniform(n: int, g: np.random.Generator, lo: float = -1.0, hi: float = 1.0):
+    return np.sort(g.uniform(lo, hi, size=n))
+
+
+def spectrum_clustered(n: int, g: np.random.Generator, n_clustered: int = 600,
+                       width: float = 1e-3, bulk=(-0.4, 2.0)):
+    per = n_clustered // len(CLUSTER_CENTRES)
+    parts = [c + width * g.standard_normal(per) for c in CLUSTER_CENTRES]
+    rest = n - per * len(CLUSTER_CENTRES)
+    parts.append(g.uniform(bulk[0], bulk[1], size=rest))
+    return np.sort(np.concatenate(parts))
+
+
+def haar_unitary(n: int, g: np.random.Generator) -> np.ndarray:
+    Z = complex_gaussian(g, n, n) / np.sqrt(2.0)
+    Q, R = np.linalg.qr(Z)
+    d = np.diag(R)
+    return Q * (d / np.abs(d))[None, :]
+
+
+def hermitian_from(Q: np.ndarray, lam: np.ndarray) -> np.ndarray:
+    H = (Q * lam[None, :]) @ Q.conj().T
+    return 0.5 * (H + H.conj().T)
+
+
+def hermitian(n: int, lam: np.ndarray, seed: int) -> np.ndarray:
+    """Column-major-ready (Fortran order) complex128 H with spectrum lam."""
+    Q = haar_unitary(n, rng(seed))
+    return np.asfortranarray(hermitian_from(Q, lam))
+
+
+def start_block(n: int, b: int, seed: int) -> np.ndarray:
+    return np.asfortranarray(complex_gaussian(rng(seed), n, b))
+
+
+def perturbation(n: int, seed: int, power_iters: int = 60) -> np.ndarray:
+    """Hermitian complex Gaussian (G + G^H)/2 scaled to unit spectral norm."""
+    g = rng(seed)
+    G = complex_gaussian(g, n, n)
+    E = 0.5 * (G + G.conj().T)
+    if n <= 3000:
+        nrm = float(np.max(np.abs(np.linalg.eigvalsh(E))))
+    else:
+        x = complex_gaussian(g, n)
+        for _ in range(power_iters):
+            x = E @ x
+            x /= np.linalg.norm(x)
+        nrm = float(np.linalg.norm(E @ x))
+    return E / nrm
+
+
+def sequence(n: int, lam: np.ndarray, n_problems: int, eps: float, seed: int):
+    """List of H_1..H_K (host, complex128, Fortran order).  ||H_k||_2 is taken as max|lam| for
+    k = 1 and tracked by the triangle bound thereafter (the perturbations are 1e-3 relative)."""
+    H = hermitian(n, lam, seed)
+    out = [H]
+    norm = float(np.max(np.abs(lam)))
+    for k in range(1, n_problems):
+        E = perturbation(n, seed + 100 + k)
+        H = np.asfortranarray(H + eps * norm * E)
+        norm = norm * (1.0 + eps)
+        out.append(H)
+    return out
+
+
+# ----------------------------------------------------------------------------- configs
+# The five synthetic workloads (order n, nev, nex, spectrum).  Seeds: 1000 * id + problem.
+
+CONFIGS = {
+    1: dict(n=1000, nev=50, nex=20, spectrum="uniform", tol=1e-10),
+    2: dict(n=10000, nev=500, nex=100, spectrum="clustered", n_clustered=600, tol=1e-10),
+    3: dict(n=20000, nev=1000, nex=200, spectrum="clustered", n_clustered=600, tol=1e-10,
+            problems=10, eps=1e-3),
+    4: dict(sizes=(2000, 4000, 8000, 16000), sequences=16, problems=8, eps=1e-3, tol=1e-10),
+    5: dict(n=60000, nev=2000, nex=400, spectrum="clustered", n_clustered=2400, tol=1e-10,
+            problems=5, eps=5e-4),
+}
+
+
+def spectrum_for(cfg: int, n: int | None = None, seed: int | None = None) -> np.ndarray:
+    c = CONFIGS[cfg]
+    n = n or c["n"]
+    g = rng(seed if seed is not None else 1000 * cfg)
+    if c.get("spectrum", "clustered") == "uniform":
+        return spectrum_uniform(n, g)
+    return spectrum_clustered(n, g, n_clustered=c.get("n_clustered", 600))
+
+
+def serving_size(n_choices, n_seq: int, seed: int):
+    """N for each serving sequence, drawn uniformly from n_choices."""
+    g = rng(seed)
+    return [int(n_choices[i]) for i in g.integers(0, len(n_choices), size=n_seq)]
+
+
+def optimized_degree_profile(b: int, deg_max: int = 36) -> np.ndarray:
+    """A sorted, even degree array spread uniformly over 2..deg_max, the shape Alg. 5 produces
+    when residuals span many decades (used to time the filter with a realistic active-range
+    schedule)."""
+    levels = deg_max // 2
+    d = 2 + 2 * ((np.arange(b) * levels) // b)
+    return np.sort(d).astype(np.int32)
+
+
+# ----------------------------------------------------------------------------- torch (device)
+
+def hermitian_torch(n: int, lam: np.ndarray, seed: int, device: str = "cuda",
+                    dtype=None):
+    """Same recipe on a torch device (for orders where the host QR is too slow).
+
+    Returns a complex128 device tensor laid out column-major: the tensor ``T`` with
+    ``T.shape == (n, n)`` whose storage is H in column-major order (i.e. ``T = H^T`` in
+    row-major terms; since H is Hermitian this is conj(H))."""
+    import torch
+
+    dtype = dtype or torch.complex128
+    gen = torch.Generator(device=device)
+    gen.manual_seed(seed)
+    re = torch.randn((n, n), generator=gen, device=device, dtype=torch.float64)
+    im = torch.randn((n, n), generator=gen, device=device, dtype=torch.float64)
+    Z = torch.complex(re, im) / np.sqrt(2.0)
+    del re, im
+    Q, R = torch.linalg.qr(Z)
+    del Z
+    d = torch.diagonal(R)
+    Q = Q * (d / d.abs())[None, :]
+    del R
+    lam_t = torch.as_tensor(lam, device=device, dtype=torch.float64).to(dtype)
+    H = (Q * lam_t[None, :]) @ Q.conj().T
+    del Q
+    H = 0.5 * (H + H.conj().T)
+    # column-major storage of H == row-major storage of H^T
+    return H.transpose(0, 1).contiguous()

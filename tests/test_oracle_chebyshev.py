@@ -1,0 +1,130 @@
+"""Pins of the oracle's Chebyshev filter against facts fixed by the mathematics (no GPU).
+
+Independent sources used here: NumPy's Chebyshev-series evaluator ``chebval`` (a library
+routine for C_m), closed-form eigen-decompositions (diagonal H; H = Q diag(lam) Q^H), and the
+normalisation p_m(mu_1) = 1 of Eq. (5).
+"""
+
+import numpy as np
+import pytest
+from numpy.polynomial import chebyshev as npcheb
+
+from oracle import chebyshev as ch
+from paper_1805_10121_amd import workloads as wl
+
+
+def C_lib(m, t):
+    coef = np.zeros(m + 1)
+    coef[m] = 1.0
+    return npcheb.chebval(np.asarray(t, dtype=np.float64), coef)
+
+
+def p_lib(x, m, b_sup, mu_1, mu_b):
+    c, e = 0.5 * (b_sup + mu_b), 0.5 * (b_sup - mu_b)
+    return C_lib(m, (np.asarray(x) - c) / e) / C_lib(m, (mu_1 - c) / e)
+
+
+@pytest.mark.parametrize("m", [0, 1, 2, 3, 7, 20, 36])
+def test_cheb_closed_vs_library(m):
+    t = np.concatenate([np.linspace(-1, 1, 41), np.linspace(-3, -1.0001, 9), np.linspace(1.0001, 3, 9)])
+    ref = C_lib(m, t)
+    got = ch.cheb_closed(m, t)
+    assert np.allclose(got, ref, rtol=1e-11, atol=1e-12)
+
+
+@pytest.mark.parametrize("k", [1, 2, 5, 10, 36])
+def test_cos_k_theta(k):
+    th = np.linspace(0, np.pi, 101)
+    assert np.allclose(C_lib(k, np.cos(th)), np.cos(k * th), atol=1e-12)
+    assert np.allclose(ch.cheb_closed(k, np.cos(th)), np.cos(k * th), atol=1e-12)
+
+
+def test_sigma_is_ratio_of_chebyshev_values():
+    b_sup, mu_1, mu_b = 2.1, -1.05, -0.3
+    c, e = 0.5 * (b_sup + mu_b), 0.5 * (b_sup - mu_b)
+    s = (mu_1 - c) / e                     # 1/sigma_1
+    sig = ch.sigma(20, b_sup, mu_1, mu_b)
+    for m in range(1, 21):
+        assert sig[m - 1] == pytest.approx(C_lib(m - 1, s) / C_lib(m, s), rel=1e-13)
+
+
+def test_filter_scalars_reproduce_the_polynomial():
+    # Applying the per-product coefficients to a scalar x must give p_m(x) (Eq. (5)).
+    b_sup, mu_1, mu_b = 1.7, -1.2, -0.1
+    rows = ch.filter_scalars(30, b_sup, mu_1, mu_b)
+    xs = np.array([-1.2, -1.0, -0.5, -0.1, 0.4, 1.7])
+    prev = np.ones_like(xs)
+    a, b, g = rows[0]
+    cur = a * xs + g * prev
+    for m in range(2, 31):
+        a, b, g = rows[m - 1]
+        prev, cur = cur, a * xs * cur + g * cur + b * prev
+        assert np.allclose(cur, p_lib(xs, m, b_sup, mu_1, mu_b), rtol=1e-12, atol=1e-14)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_filter_on_diagonal_matrix(seed):
+    g = wl.rng(seed)
+    n, nb = 60, 12
+    b_sup, mu_1, mu_b = 2.05, -1.0, -0.4
+    lam = np.sort(g.uniform(-1.0, 2.0, n))
+    lam[0] = mu_1                          # p_m(mu_1) = 1: that component is left unchanged
+    A = np.diag(lam).astype(np.complex128)
+    V = wl.complex_gaussian(g, n, nb)
+    deg = np.sort(2 * g.integers(1, 19, nb))
+    out = ch.filter_columns(A, V, deg, b_sup, mu_1, mu_b)
+    for a in range(nb):
+        ref = p_lib(lam, int(deg[a]), b_sup, mu_1, mu_b) * V[:, a]
+        assert np.linalg.norm(out[:, a] - ref) <= 1e-13 * np.linalg.norm(ref)
+        assert abs(out[0, a] - V[0, a]) <= 1e-13 * abs(V[0, a])
+
+
+def test_filter_on_prescribed_spectrum():
+    n, nb = 120, 9
+    g = wl.rng(7)
+    lam = wl.spectrum_uniform(n, g)
+    Q = wl.haar_unitary(n, g)
+    A = wl.hermitian_from(Q, lam)
+    V = wl.complex_gaussian(g, n, nb)
+    b_sup, mu_1, mu_b = 1.02, lam[0], lam[20]
+    deg = np.array([2, 2, 4, 8, 10, 10, 20, 30, 36])
+    out = ch.filter_columns(A, V, deg, b_sup, mu_1, mu_b)
+    for a in range(nb):
+        ref = Q @ (p_lib(lam, int(deg[a]), b_sup, mu_1, mu_b) * (Q.conj().T @ V[:, a]))
+        assert np.linalg.norm(out[:, a] - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
+def test_filter_rejects_transposed_operand():
+    # A^T = conj(A) differs from A for complex Hermitian A; the prescribed-spectrum pin must see it.
+    n = 40
+    g = wl.rng(3)
+    lam = wl.spectrum_uniform(n, g)
+    Q = wl.haar_unitary(n, g)
+    A = wl.hermitian_from(Q, lam)
+    V = wl.complex_gaussian(g, n, 2)
+    deg = np.array([4, 4])
+    good = ch.filter_columns(A, V, deg, 1.1, lam[0], lam[8])
+    bad = ch.filter_columns(A.T, V, deg, 1.1, lam[0], lam[8])
+    assert np.linalg.norm(good - bad) > 1e-3 * np.linalg.norm(good)
+
+
+@pytest.mark.parametrize("seed", [0, 5])
+def test_alg4_double_buffer_equals_per_column(seed):
+    g = wl.rng(seed)
+    n, nb = 80, 17
+    lam = wl.spectrum_uniform(n, g)
+    A = wl.hermitian_from(wl.haar_unitary(n, g), lam)
+    V = wl.complex_gaussian(g, n, nb)
+    deg = np.sort(2 * g.integers(1, 19, nb))
+    a = ch.filter_alg4(A, V, deg, 1.05, lam[0], lam[10])
+    b = ch.filter_columns(A, V, deg, 1.05, lam[0], lam[10])
+    assert np.linalg.norm(a - b) <= 1e-13 * np.linalg.norm(b)
+
+
+def test_alg4_rejects_odd_or_unsorted():
+    A = np.eye(4, dtype=np.complex128)
+    V = np.ones((4, 2), dtype=np.complex128)
+    with pytest.raises(ValueError):
+        ch.filter_alg4(A, V, [3, 4], 2.0, -1.0, 0.0)
+    with pytest.raises(ValueError):
+        ch.filter_alg4(A, V, [4, 2], 2.0, -1.0, 0.0)

@@ -1,0 +1,179 @@
+"""Pins of the oracle's outer loop (Algorithms 1, 2, 3, 5) -- no GPU.
+
+Sources of truth: the prescribed spectrum of H = Q diag(lam) Q^H, brute-force ``eigh``,
+Sylvester's law of inertia through an LDL^H factorisation (``scipy.linalg.ldl``), and
+hand-computed cases for Alg. 3 and Alg. 5.
+"""
+
+import json
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+from oracle import chase
+from paper_1805_10121_amd import workloads as wl
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------- Alg. 5 hand-computed cases
+
+@pytest.mark.parametrize(
+    "res,t,deg_max,expected",
+    [
+        # t = -3: |rho| = 3 + sqrt(8) = 5.8284; log(1e6)/log(5.8284) = 13.8155/1.7627 = 7.84 -> 8; +2 = 10
+        (1e-4, -3.0, 36, 10),
+        # t = -1.5: |rho| = 2.6180; 13.8155/0.96242 = 14.355 -> 15; +2 = 17 -> even 18
+        (1e-4, -1.5, 36, 18),
+        # t = -1.1: |rho| = 1.5583; log(1e10)/0.44357 = 51.9 -> 52; +2 = 54 -> capped at 36
+        (1.0, -1.1, 36, 36),
+        # |t| < 1: |rho| = 1, the division by log 1 = 0 gives DEGMAX
+        (1e-3, 0.3, 36, 36),
+        # odd DEGMAX: min(.., 35) = 35, made even -> 36 (literal reading of line 6)
+        (1.0, -1.1, 35, 36),
+        # Res < tol: |log(1e-2)|/1.7627 = 2.61 -> 3; +2 = 5 -> even 6
+        (1e-12, -3.0, 36, 6),
+    ],
+)
+def test_degrees_hand_computed(res, t, deg_max, expected):
+    c, e = 0.5, 1.5
+    ritz = c + t * e
+    got = chase.degrees(1e-10, [res], [ritz], c, e, 2, deg_max)
+    assert int(got[0]) == expected
+
+
+def test_degrees_are_even_and_bounded():
+    g = wl.rng(4)
+    res = 10.0 ** g.uniform(-12, 0, 200)
+    ritz = g.uniform(-1.5, 1.0, 200)
+    d = chase.degrees(1e-10, res, ritz, 0.9, 1.1, 2, 36)
+    assert np.all(d % 2 == 0) and np.all(d >= 2) and np.all(d <= 36)
+
+
+# ---------------------------------------------------------------- Alg. 3 unit cases
+
+def test_lock_only_leading_consecutive_run():
+    ritz = np.array([0.3, -1.0, -0.5, 0.1])
+    res = np.array([1e-12, 1e-12, 1e-3, 1e-12])     # ascending order: -1.0 ok, -0.5 not -> stop
+    n_new, order = chase.lock(ritz, res, None, 1e-10)
+    assert n_new == 1 and list(order[:1]) == [1]
+
+
+def test_lock_all_and_equality():
+    ritz = np.array([2.0, 1.0])
+    res = np.array([1e-10, 5e-11])
+    n_new, order = chase.lock(ritz, res, None, 1e-10)
+    assert n_new == 2 and list(order) == [1, 0]
+
+
+def test_lock_stable_on_ties():
+    ritz = np.array([1.0, 1.0, 0.0])
+    res = np.array([0.0, 1.0, 0.0])
+    n_new, order = chase.lock(ritz, res, None, 1e-10)
+    assert list(order) == [2, 0, 1] and n_new == 2
+
+
+def test_table1_defaults():
+    with open(os.path.join(GOLDEN, "table1_defaults.json")) as f:
+        t1 = json.load(f)["double"]
+    p = chase.ChaseParams(nev=1, nex=1)
+    assert p.tol == t1["tol"] and p.max_iter == t1["max_iter"] and p.optim == t1["optim"]
+    assert p.deg_extra == t1["deg_extra"] and p.deg_max == t1["deg_max"] and p.deg == t1["deg"]
+    assert p.lanczos_iter == t1["lanczos_iter"] and p.num_lanczos == t1["num_lanczos"]
+
+
+# ---------------------------------------------------------------- whole solves
+
+def _problem(n, seed, kind="uniform"):
+    g = wl.rng(seed)
+    lam = wl.spectrum_uniform(n, g) if kind == "uniform" else wl.spectrum_clustered(n, g, n // 10)
+    Q = wl.haar_unitary(n, g)
+    return lam, Q, wl.hermitian_from(Q, lam), g
+
+
+def _inertia_count(A, sigma):
+    L, D, _ = scipy.linalg.ldl(A - sigma * np.eye(A.shape[0]), hermitian=True)
+    return int(np.sum(np.linalg.eigvalsh(D) < 0))
+
+
+def _check_solution(A, lam_true, r, nev, tol_rel=1e-10):
+    normA = np.max(np.abs(lam_true))
+    assert r["status"] == 0
+    got = r["ritzv"][:nev]
+    assert np.max(np.abs(got - lam_true[:nev])) <= tol_rel * normA
+    Y = r["V"][:, :nev]
+    assert np.linalg.norm(Y.conj().T @ Y - np.eye(nev)) <= 1e-12
+    R = A @ Y - Y * got[None, :]                    # fresh product, not the solver's A V
+    assert np.max(np.linalg.norm(R, axis=0)) <= tol_rel * normA * 1.0001
+
+
+@pytest.mark.parametrize("optim", [True, False])
+def test_solve_small_against_eigh(optim):
+    n, nev, nex = 200, 12, 6
+    lam, Q, A, g = _problem(n, 31)
+    p = chase.ChaseParams(nev=nev, nex=nex, optim=optim)
+    V0 = wl.complex_gaussian(g, n, nev + nex)
+    starts = wl.complex_gaussian(g, n, 5)
+    r = chase.solve(A, p, V0, starts)
+    ev = np.linalg.eigvalsh(A)
+    _check_solution(A, ev, r, nev)
+    # subspace agreement with eigh's eigenvectors of the lowest nev (gap after nev assumed)
+    _, U = np.linalg.eigh(A)
+    s = np.linalg.svd(U[:, :nev].conj().T @ r["V"][:, :nev], compute_uv=False)
+    assert np.min(s) > 1 - 1e-9
+    # Sylvester inertia: exactly nev eigenvalues below the midpoint to the next Ritz value
+    sigma = 0.5 * (r["ritzv"][nev - 1] + r["ritzv"][nev])
+    assert _inertia_count(A, sigma) == nev
+
+
+def test_solve_config1_prescribed_spectrum():
+    c = wl.CONFIGS[1]
+    n, nev, nex = c["n"], c["nev"], c["nex"]
+    lam = wl.spectrum_for(1)
+    A = wl.hermitian(n, lam, 1001)
+    p = chase.ChaseParams(nev=nev, nex=nex, optim=True)
+    V0 = wl.start_block(n, nev + nex, 1500)
+    starts = wl.start_block(n, 5, 1600)
+    r = chase.solve(A, p, V0, starts)
+    _check_solution(A, lam, r, nev)
+    assert r["b_sup"] >= lam.max()
+
+
+def test_warm_start_with_exact_vectors_converges_in_one_iteration():
+    n, nev, nex = 150, 8, 4
+    lam, Q, A, g = _problem(n, 41)
+    p = chase.ChaseParams(nev=nev, nex=nex, optim=True)
+    V0 = Q[:, : nev + nex]
+    r = chase.solve(A, p, V0, wl.complex_gaussian(g, n, 5), approx=True, ritzv0=lam[: nev + nex])
+    assert r["iterations"] == 1
+    _check_solution(A, lam, r, nev)
+
+
+def test_max_iter_returns_partial():
+    n, nev, nex = 200, 20, 4
+    lam, Q, A, g = _problem(n, 51)
+    p = chase.ChaseParams(nev=nev, nex=nex, optim=True, max_iter=1, deg=4)
+    r = chase.solve(A, p, wl.complex_gaussian(g, n, nev + nex), wl.complex_gaussian(g, n, 5))
+    assert r["status"] == 1 and r["nconv"] < nev and r["iterations"] == 1
+    assert r["ritzv"].shape == (nev + nex,) and r["V"].shape == (n, nev + nex)
+
+
+def test_sequence_warm_start_and_weyl():
+    n, nev, nex = 160, 10, 4
+    g = wl.rng(61)
+    lam = wl.spectrum_clustered(n, g, 30)
+    As = wl.sequence(n, lam, 3, 1e-3, 61)
+    p = chase.ChaseParams(nev=nev, nex=nex, optim=True)
+    V0 = wl.complex_gaussian(g, n, nev + nex)
+    starts = [wl.complex_gaussian(g, n, 5) for _ in As]
+    res = chase.solve_sequence(As, p, V0, starts)
+    prev = None
+    for A, r in zip(As, res):
+        ev = np.linalg.eigvalsh(A)
+        _check_solution(A, ev, r, nev)
+        if prev is not None:                       # Weyl: |lam_i(H_k+1) - lam_i(H_k)| <= ||eps E||
+            assert np.max(np.abs(r["ritzv"][:nev] - prev)) <= 1.01e-3 * np.max(np.abs(lam)) * 1.01
+        prev = r["ritzv"][:nev]
+    assert res[-1]["iterations"] <= res[0]["iterations"]
