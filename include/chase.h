@@ -1,0 +1,201 @@
+/*
+ * chase.h -- C ABI of an MI355X (gfx950) implementation of ChASE, the Chebyshev Accelerated
+ * Subspace iteration Eigensolver (Winkelmann, Springer, Di Napoli, arXiv:1805.10121).
+ *
+ * The library finds the nev smallest eigenpairs of a dense complex Hermitian matrix H of order n
+ * with a search space of nev+nex vectors (Algorithm 1 of the paper).  Its hot path is the
+ * Chebyshev filter (Algorithm 4, Eq. (7)), run as hand-written gfx950 kernels.
+ *
+ * Conventions shared by every call
+ *   - Matrices are column-major.  "complex128" is two IEEE doubles (re, im) per element, the
+ *     layout of C99 double complex / std::complex<double>; "complex64" is two floats.
+ *   - "device" pointers are HIP device memory on the context's device; "host" pointers are
+ *     ordinary host memory.  The caller owns every buffer it passes; the library never frees,
+ *     reallocates or keeps them after the call returns, and never writes to H.
+ *   - Every call returns a chase_status.  On a negative status a message is available from
+ *     chase_last_error(ctx).  Argument checks are done before any device work is enqueued, so
+ *     a CHASE_EINVAL return leaves every buffer untouched.
+ *   - Work is ordered on the context's HIP stream.  chase_filter and the conversion calls only
+ *     enqueue (they return before the GPU finishes); chase_solve and the sequence calls
+ *     return after the GPU work has completed.
+ *   - A context must not be used from two host threads at once.
+ */
+#ifndef CHASE_MI355X_H
+#define CHASE_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  CHASE_OK = 0,
+  CHASE_NOT_CONVERGED = 1,  /* maxIter reached: the current approximations are returned (Sec. 5.3) */
+  CHASE_EINVAL = -1,        /* invalid argument; nothing was enqueued                            */
+  CHASE_ENOMEM = -2,        /* device workspace could not be allocated                           */
+  CHASE_EDEVICE = -3,       /* a HIP / rocBLAS / rocSOLVER call failed                           */
+  CHASE_ENUMERIC = -4,      /* NaN/Inf, or orthonormalisation broke down even after fallback      */
+  CHASE_EBUSY = -5          /* server: request does not fit the memory budget right now           */
+} chase_status;
+
+typedef enum {
+  CHASE_FP64 = 0,   /* complex128 buffers, FP64 MFMA with FP64 accumulation                     */
+  CHASE_FP32 = 1,   /* complex64 buffers, FP32 MFMA with FP32 accumulation                      */
+  CHASE_MIXED = 2   /* chase_solve only: FP32 filter while a vector's relative residual exceeds
+                       switch_resid, FP64 afterwards; everything outside the filter stays FP64 */
+} chase_precision;
+
+/*
+ * Solver parameters.  The first block is Table 1 of the paper (Sec. 5.3) with its
+ * double-precision defaults; chase_config_init fills them.  The second block holds settings the
+ * paper leaves open.
+ */
+typedef struct chase_config {
+  int64_t n;             /* order of H (Alg. 1 input A)                                          */
+  int64_t nev;           /* wanted eigenpairs, 1 <= nev                                          */
+  int64_t nex;           /* extra search vectors, nev + nex <= n                                 */
+  int32_t approx;        /* 0: cold start (Lanczos DoS estimates, Alg. 6); 1: warm start from V
+                            and ritzv (Sec. 3.3)                                     default 0   */
+  double tol;            /* residual threshold (Alg. 1, Alg. 3)                      1e-10       */
+  int32_t max_iter;      /* outer-loop cap (Sec. 5.3)                                25          */
+  int32_t optim;         /* per-vector degrees (Alg. 5) instead of constant deg      0           */
+  int32_t deg_extra;     /* DEGEXTRA of Alg. 5                                        2           */
+  int32_t deg_max;       /* DEGMAX of Alg. 5                                          36          */
+  int32_t deg;           /* initial / constant degree (Alg. 1 line 1), rounded up to even 20     */
+  int32_t lanczos_iter;  /* k of Alg. 6                                               25          */
+  int32_t num_lanczos;   /* n_vec of Alg. 6                                           4           */
+
+  int32_t precision;     /* chase_precision, FP64 or MIXED                            FP64        */
+  double switch_resid;   /* MIXED: relative residual below which a vector is filtered in FP64
+                                                                                      1e-6        */
+  int32_t deg_max_fp32;  /* MIXED: DEGMAX for FP32-filtered vectors (Table 1 SP value) 18         */
+  int32_t resid_relative;/* 1: converged iff Res <= tol * ||H||_est, where ||H||_est is the
+                            largest |Ritz value| of the b_sup Lanczos run (a lower bound of
+                            ||H||_2); 0: absolute Res <= tol as in the paper's experiments  1   */
+  int32_t intersperse;   /* cold start: put Lanczos Ritz vectors below mu_{nev+nex} into the
+                            leading columns of the start block (Alg. 6 line 13)      1           */
+  double dos_sigma;      /* Gaussian width of the DoS (Sec. 4.2), on the [-1, 1] scale 0.25      */
+  uint64_t seed;         /* seed of the counter-based generator for Lanczos start vectors   0    */
+  const void* lanczos_start; /* optional device complex128 n x (1 + num_lanczos) block (ld = n)
+                            of Lanczos start vectors; NULL: drawn from seed                NULL  */
+  int32_t have_mu;       /* cold start only: 1 = use mu_1 / mu_nevnex below instead of the DoS
+                            estimates (Alg. 1 input "estimates mu_1 and mu_{nev+nex}")    0     */
+  double mu_1, mu_nevnex;
+} chase_config;
+
+/* Counters and timings of one solve (Sec. 6 reports iterations, matvecs and filter time). */
+typedef struct chase_stats {
+  int32_t status;          /* chase_status of the solve                                       */
+  int32_t iterations;      /* outer-loop iterations                                           */
+  int32_t nconv;           /* locked (converged) pairs                                        */
+  int32_t fp32_iterations; /* iterations in which some columns were filtered in FP32          */
+  int32_t qr_fallbacks;    /* Householder fallbacks taken by the orthonormalisation           */
+  int32_t reserved;
+  int64_t matvecs;         /* products of H with one vector, all phases                      */
+  int64_t filter_matvecs;  /* sum over filter calls of the active degrees                    */
+  double filter_flops;     /* 8 n^2 * filter_matvecs: algorithmic filter flops               */
+  double filter_ms, lanczos_ms, ortho_ms, rr_ms, resid_ms, total_ms;
+  double b_sup, mu_1, mu_nevnex, norm_est;
+} chase_stats;
+
+typedef struct chase_ctx chase_ctx;
+
+/* Fill cfg with the Table 1 defaults for the given sizes.  No device work. */
+void chase_config_init(chase_config* cfg, int64_t n, int64_t nev, int64_t nex);
+
+/* Create a context on HIP device `device`.  hip_stream: a hipStream_t to order all work on, or
+   NULL for a stream owned by the context.  Allocates no large memory. */
+int chase_create(chase_ctx** out, int device, void* hip_stream);
+void chase_destroy(chase_ctx* ctx);
+
+/* Text of the last error on this context ("" if none).  Valid until the next call on ctx. */
+const char* chase_last_error(const chase_ctx* ctx);
+
+/* Device bytes chase_solve will hold for cfg (H itself excluded).  No device work. */
+size_t chase_workspace_bytes(const chase_config* cfg);
+
+/*
+ * The Chebyshev filter of Algorithm 4 with the scaled three-term recurrence of Eq. (7).
+ *
+ * For every column a of the n x ncols block V, replaces V[:, a] by p_{m_a}(H) V[:, a], where p_m
+ * is the degree-m Chebyshev polynomial of Eq. (5) for the interval [mu_nevnex, b_sup] scaled so
+ * that p_m(mu_1) = 1.  Product i of the recurrence (i = 1 .. max m) is one kernel launch
+ * over the columns with m_a >= i (Alg. 4 lines 7-14); the two buffers swap after every
+ * product.  Because all m_a are even, every column's last product lands in the buffer that
+ * held the input, so the result is returned in V and W is scratch (Sec. 4.1.3).
+ *
+ *   precision  CHASE_FP64: H, V, W are complex128.  CHASE_FP32: H, V, W are complex64 (use the
+ *              conversion calls below to stage them); the recurrence coefficients are computed
+ *              in FP64 and rounded to FP32 per launch.
+ *   H          device, n x n, column-major, leading dimension ldh >= n, full Hermitian storage
+ *              (both triangles are read).  Read only.
+ *   V          device, n x ncols, leading dimension ld >= n.  In: the block.  Out: the result.
+ *   W          device, n x ncols, leading dimension ld, must not overlap V or H.  Scratch.
+ *   degrees    host, ncols int32, sorted ascending, even, 2 <= m_a <= 64 (Alg. 1 line 15 and
+ *              Alg. 5 line 6 establish these properties).
+ *   b_sup, mu_1, mu_nevnex   the spectral bounds of Alg. 4 line 1; need mu_1 < mu_nevnex < b_sup.
+ * ncols == 0 is a no-op.  Enqueues only.
+ */
+int chase_filter(chase_ctx* ctx, int precision, const void* H, int64_t ldh, int64_t n, void* V,
+                 void* W, int64_t ld, int64_t ncols, const int32_t* degrees, double b_sup,
+                 double mu_1, double mu_nevnex);
+
+/*
+ * One fused product of the filter (the kernel behind every launch of chase_filter):
+ *     OUT[:, j] <- alpha * H X[:, j] + gamma * X[:, j] + beta * OUT[:, j],   j < ncols
+ * With beta == 0 the old OUT is not read (it may hold NaN).  Also serves the other products of
+ * the outer loop: H Q for Rayleigh-Ritz (Alg. 2 line 2) and the Lanczos block (Alg. 6).
+ * X and OUT: device, n x ncols, leading dimensions ldx, ldo >= n; must not overlap each other
+ * or H.  Types as in chase_filter.  Enqueues only.
+ */
+int chase_hemm_step(chase_ctx* ctx, int precision, const void* H, int64_t ldh, int64_t n,
+                    const void* X, int64_t ldx, void* OUT, int64_t ldo, int64_t ncols,
+                    double alpha, double beta, double gamma);
+
+/* Precision staging of the mixed filter: dst = (complex64) src / (complex128) src on a
+   rows x cols column-major block.  Device pointers; enqueues only. */
+int chase_convert_c128_to_c64(chase_ctx* ctx, const void* src, int64_t ld_src, void* dst,
+                              int64_t ld_dst, int64_t rows, int64_t cols);
+int chase_convert_c64_to_c128(chase_ctx* ctx, const void* src, int64_t ld_src, void* dst,
+                              int64_t ld_dst, int64_t rows, int64_t cols);
+
+/*
+ * Algorithm 1: the nev smallest eigenpairs of H.
+ *
+ *   H      device complex128, n x n, ldh >= n, full Hermitian storage, read only.
+ *   V      device complex128, n x (nev+nex), ldv >= n.
+ *          In, approx = 0: the random start block (Alg. 1 input V-hat).
+ *          In, approx = 1: approximate eigenvectors, e.g. the previous solution in a sequence.
+ *          Out: columns [0, nev) eigenvectors of ritzv[0..nev) (ascending), then the remaining
+ *          nex Ritz vectors -- the warm start of the next problem.
+ *   ritzv  host, nev+nex doubles.  In (approx = 1): previous eigenvalues; their min and max are
+ *          mu_1 and mu_{nev+nex} (Sec. 3.3).  Out: Ritz values, ascending within the locked and
+ *          the active parts.
+ *   resid  host, nev+nex doubles.  Out: residual norms ||H v - lambda v||_2.
+ *   stats  host, may be NULL.
+ * Returns CHASE_OK, or CHASE_NOT_CONVERGED with the outputs filled when maxIter was reached.
+ * Blocks until done.
+ */
+int chase_solve(chase_ctx* ctx, const chase_config* cfg, const void* H, int64_t ldh, void* V,
+                int64_t ldv, double* ritzv, double* resid, chase_stats* stats);
+
+/*
+ * Sequences of correlated problems (Sec. 2, Sec. 6.1): the state -- the nev+nex vectors, the
+ * Ritz values and the last degrees -- stays resident in device memory between problems.  The
+ * first problem is solved cold, every later one warm (approx = 1) from the previous solution.
+ */
+typedef struct chase_seq chase_seq;
+int chase_seq_create(chase_ctx* ctx, const chase_config* cfg, chase_seq** out);
+/* Solve the next problem H (device complex128, ldh >= n).  ritzv / resid: host, nev+nex. */
+int chase_seq_solve(chase_seq* seq, const void* H, int64_t ldh, double* ritzv, double* resid,
+                    chase_stats* stats);
+/* Borrowed device pointer to the current n x (nev+nex) vectors (valid until the next call). */
+int chase_seq_vectors(chase_seq* seq, void** V, int64_t* ldv);
+void chase_seq_destroy(chase_seq* seq);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CHASE_MI355X_H */

@@ -133,3 +133,12 @@ def filter_alg4(A, V, degrees, b_sup: float, mu_1: float, mu_nevnex: float):
         while s < nb and m[s] <= i:
             s += 1
     return Wb
+
+
+def product(A, X, Y, alpha: float, beta: float, gamma: float):
+    """One product of the recurrence written out: alpha*A@X + gamma*X + beta*Y (Eq. (7) with the
+    shift (A - cI) expanded, as in Alg. 4 lines 4 and 9).  ``Y`` is ignored when beta == 0."""
+    out = alpha * (np.asarray(A) @ np.asarray(X)) + gamma * np.asarray(X)
+    if beta != 0.0:
+        out = out + beta * np.asarray(Y)
+    return out

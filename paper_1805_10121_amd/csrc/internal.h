@@ -1,0 +1,61 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/chase.h"
+
+namespace chase {
+
+// ----------------------------------------------------------------------------- kernels
+// One fused complex product  OUT <- alpha*H*X + gamma*X + beta*OUT  on ncols columns.
+// T = double (complex128 data) or float (complex64 data); pointers address interleaved
+// (re, im) pairs, leading dimensions count complex elements.
+template <typename T>
+hipError_t launch_hemm_step(const T* H, int64_t ldh, int64_t n, const T* X, int64_t ldx, T* OUT,
+                            int64_t ldo, int64_t ncols, T alpha, T beta, T gamma,
+                            hipStream_t stream);
+
+hipError_t launch_convert_c128_to_c64(const double* src, int64_t lds, float* dst, int64_t ldd,
+                                      int64_t rows, int64_t cols, hipStream_t stream);
+hipError_t launch_convert_c64_to_c128(const float* src, int64_t lds, double* dst, int64_t ldd,
+                                      int64_t rows, int64_t cols, hipStream_t stream);
+
+// ----------------------------------------------------------------------------- filter driver
+// Algorithm 4 on an n x ncols block with sorted even degrees (validated by the caller).  The
+// result ends in V.  scalars: the per-product (alpha, beta, gamma) in FP64.
+template <typename T>
+hipError_t run_filter(const T* H, int64_t ldh, int64_t n, T* V, T* W, int64_t ld, int64_t ncols,
+                      const int32_t* degrees, double b_sup, double mu_1, double mu_nevnex,
+                      hipStream_t stream, int64_t* matvecs_out);
+
+}  // namespace chase
+
+struct chase_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  rocblas_handle blas = nullptr;
+  std::string last_error;
+  // device workspace, grown monotonically
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+};
+
+namespace chase {
+int set_error(chase_ctx* ctx, int code, const std::string& msg);
+int ensure_workspace(chase_ctx* ctx, size_t bytes);
+}  // namespace chase
+
+#define CHASE_HIP_TRY(ctx, expr)                                                            \
+  do {                                                                                      \
+    hipError_t _e = (expr);                                                                 \
+    if (_e != hipSuccess)                                                                   \
+      return ::chase::set_error((ctx), CHASE_EDEVICE,                                       \
+                                std::string(#expr) + ": " + hipGetErrorString(_e));         \
+  } while (0)

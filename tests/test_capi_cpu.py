@@ -1,0 +1,98 @@
+"""The C ABI without a GPU: the library loads, exports every symbol the header declares, the
+ctypes structures match the C layout, and chase_config_init fills Table 1's defaults."""
+
+import ctypes
+import json
+import os
+import re
+import subprocess
+import tempfile
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "chase.h")
+
+
+def _declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"\b(chase_[a-z0-9_]+)\s*\(", src)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1805_10121_amd import capi
+
+    L = capi.lib()
+    declared = _declared_functions()
+    assert len(declared) >= 10
+    for name in declared:
+        assert hasattr(L, name), name
+    assert sorted(declared) == sorted(capi.exported_symbols())
+
+
+def test_struct_layout_matches_c():
+    from paper_1805_10121_amd import capi
+
+    prog = r"""
+#include <stdio.h>
+#include <stddef.h>
+#include "chase.h"
+#define F(T, m) printf("%s %zu\n", #m, offsetof(T, m));
+int main(void) {
+  printf("sizeof_config %zu\nsizeof_stats %zu\n", sizeof(chase_config), sizeof(chase_stats));
+  F(chase_config, approx) F(chase_config, tol) F(chase_config, precision)
+  F(chase_config, switch_resid) F(chase_config, dos_sigma) F(chase_config, seed)
+  F(chase_config, lanczos_start) F(chase_config, have_mu) F(chase_config, mu_nevnex)
+  F(chase_stats, matvecs) F(chase_stats, filter_flops) F(chase_stats, norm_est)
+  return 0;
+}
+"""
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "t.c")
+        exe = os.path.join(d, "t")
+        open(c, "w").write(prog)
+        subprocess.run(["gcc", "-std=c99", "-Wall", "-Werror", "-I", os.path.dirname(HEADER), c, "-o", exe], check=True)
+        out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout
+    vals = dict(line.split() for line in out.strip().splitlines())
+    assert int(vals["sizeof_config"]) == ctypes.sizeof(capi.chase_config)
+    assert int(vals["sizeof_stats"]) == ctypes.sizeof(capi.chase_stats)
+    for f in ["approx", "tol", "precision", "switch_resid", "dos_sigma", "seed", "lanczos_start",
+              "have_mu", "mu_nevnex"]:
+        assert int(vals[f]) == getattr(capi.chase_config, f).offset, f
+    for f in ["matvecs", "filter_flops", "norm_est"]:
+        assert int(vals[f]) == getattr(capi.chase_stats, f).offset, f
+
+
+def test_config_defaults_are_table1():
+    from paper_1805_10121_amd import capi
+
+    with open(os.path.join(ROOT, "tests", "golden", "table1_defaults.json")) as f:
+        t1 = json.load(f)["double"]
+    cfg = capi.config(1000, 50, 20)
+    assert (cfg.n, cfg.nev, cfg.nex) == (1000, 50, 20)
+    assert cfg.approx == int(t1["approx"]) and cfg.tol == t1["tol"]
+    assert cfg.max_iter == t1["max_iter"] and cfg.optim == int(t1["optim"])
+    assert cfg.deg_extra == t1["deg_extra"] and cfg.deg_max == t1["deg_max"] and cfg.deg == t1["deg"]
+    assert cfg.lanczos_iter == t1["lanczos_iter"] and cfg.num_lanczos == t1["num_lanczos"]
+    assert cfg.deg_max_fp32 == 18 and cfg.dos_sigma == 0.25 and cfg.precision == capi.CHASE_FP64
+
+
+def test_workspace_bytes_is_pure_host():
+    from paper_1805_10121_amd import capi
+
+    cfg = capi.config(10000, 500, 100)
+    b = capi.lib().chase_workspace_bytes(ctypes.byref(cfg))
+    assert b >= 3 * 10000 * 600 * 16
+
+
+def test_create_without_gpu_fails_cleanly():
+    import torch
+    from paper_1805_10121_amd import capi
+
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    h = ctypes.c_void_p()
+    assert capi.lib().chase_create(ctypes.byref(h), 0, None) == capi.CHASE_EDEVICE
+    assert not h.value
