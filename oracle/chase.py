@@ -158,7 +158,7 @@ def solve(A, p: ChaseParams, V0, lanczos_starts, approx: bool = False, ritzv0=No
         filter_mv += int(m.sum())
         Qt = orthogonalize(Y, Vf)                                         # lines 5-6
         ritz, V, AV = rayleigh_ritz(A, Qt)                                # line 7
-        matvecs += 2 * nact
+        matvecs += nact                                                   # H Q (A V = (H Q) W)
         res = np.linalg.norm(AV - V * ritz[None, :], axis=0)             # line 8
         n_new, order = lock(ritz, res, V, tol_eff)                       # line 9
         ritz, res, V = ritz[order], res[order], V[:, order]

@@ -26,6 +26,20 @@ hipError_t launch_convert_c128_to_c64(const double* src, int64_t lds, float* dst
 hipError_t launch_convert_c64_to_c128(const float* src, int64_t lds, double* dst, int64_t ldd,
                                       int64_t rows, int64_t cols, hipStream_t stream);
 
+// Outer-loop helpers (loop_kernels.hip); complex128 data as interleaved doubles.
+hipError_t launch_lanczos_step(const double* U, const double* Up, double* W, double* Un, int64_t n,
+                               int64_t ld, int64_t nv, const double* beta_prev, double* alpha_out,
+                               double* beta_out, hipStream_t s);
+hipError_t launch_normalize(double* X, int64_t n, int64_t ld, int64_t cols, hipStream_t s);
+hipError_t launch_resid(const double* AV, const double* V, const double* lam, int64_t n, int64_t ld,
+                        int64_t cols, double* out, hipStream_t s);
+hipError_t launch_gather(const double* src, int64_t lds, double* dst, int64_t ldd, int64_t n,
+                         const int* perm, int64_t cols, hipStream_t s);
+hipError_t launch_herm_sym(double* G, int64_t ld, int64_t m, hipStream_t s);
+hipError_t launch_add_diag(double* G, int64_t ld, int64_t m, double v, hipStream_t s);
+hipError_t launch_gaussian(double* X, int64_t n, int64_t ld, int64_t cols, uint64_t seed,
+                           hipStream_t s);
+
 // ----------------------------------------------------------------------------- filter driver
 // Algorithm 4 on an n x ncols block with sorted even degrees (validated by the caller).  The
 // result ends in V.  scalars: the per-product (alpha, beta, gamma) in FP64.
@@ -50,6 +64,7 @@ struct chase_ctx {
 namespace chase {
 int set_error(chase_ctx* ctx, int code, const std::string& msg);
 int ensure_workspace(chase_ctx* ctx, size_t bytes);
+int hip_ok(chase_ctx* ctx);  // hipSetDevice(ctx->device) with error reporting
 }  // namespace chase
 
 #define CHASE_HIP_TRY(ctx, expr)                                                            \

@@ -1,28 +1,869 @@
-// Placeholder for the outer loop; replaced by the device-resident solver.
+// The device-resident outer loop of ChASE (Algorithm 1) and the sequence driver (Sec. 3.3).
+//
+// Per iteration, all block data stay in device memory:
+//   FILTER            Alg. 4 on the active columns, FP64 or (mixed mode) FP32 per column group
+//   ORTHOGONALIZE     Alg. 1 lines 5-6: block Gram-Schmidt against the locked vectors, column
+//                     scaling, shifted Cholesky QR + two Cholesky QR passes; Householder QR of
+//                     [Y V] (rocSOLVER) if a Cholesky factorisation breaks down
+//   RAYLEIGH-RITZ     Alg. 2: H Q with the filter's product kernel, G = Q^H (H Q) (rocBLAS),
+//                     TSOLVE = rocSOLVER zheevd, V = Q Z, H V = (H Q) Z
+//   residuals         Alg. 1 line 8, one fused kernel, then Ritz values and residual norms go to
+//                     the host (the only per-iteration device-to-host transfer of results)
+//   host              Alg. 3 (locking), Alg. 1 lines 10-11 (interval), Alg. 5 (degrees), line 15
+//                     (sort); the new column order is applied on the device by one gather.
+// LANCZOS (Alg. 6) runs first: the b_sup run and the n_vec DoS runs are independent, so they
+// advance together as one block product per step.
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include <rocsolver/rocsolver.h>
+
 #include "internal.h"
+
+namespace chase {
+namespace {
+
+constexpr double kEps = 1.1102230246251565e-16;  // 2^-53
+
+struct Layout {
+  size_t V, W, AQ, X, G, T, lam, res, evE, perm, info, U, Wl, lal, lbe, zero, Z, tau, H32, V32, W32;
+  size_t total;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
+
+Layout make_layout(int64_t n, int64_t nb, int64_t nv, int64_t k, bool mixed) {
+  Layout L{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align256(off + bytes);
+    return o;
+  };
+  const size_t blk = static_cast<size_t>(n) * nb * 16;
+  L.V = take(blk);
+  L.W = take(blk);
+  L.AQ = take(blk);
+  L.X = take(blk);
+  L.G = take(static_cast<size_t>(nb) * nb * 16);
+  L.T = take(static_cast<size_t>(nb) * nb * 16);
+  L.lam = take(nb * 8);
+  L.res = take(nb * 8);
+  L.evE = take(nb * 8);
+  L.perm = take(nb * 4);
+  L.info = take(64);
+  L.U = take(static_cast<size_t>(n) * nv * (k + 1) * 16);
+  L.Wl = take(static_cast<size_t>(n) * nv * 16);
+  L.lal = take(static_cast<size_t>(nv) * k * 8);
+  L.lbe = take(static_cast<size_t>(nv) * k * 8);
+  L.zero = take(static_cast<size_t>(nv) * 8);
+  L.Z = take(static_cast<size_t>(k) * nb * 16);
+  L.tau = take(nb * 16);
+  if (mixed) {
+    L.H32 = take(static_cast<size_t>(n) * n * 8);
+    L.V32 = take(static_cast<size_t>(n) * nb * 8);
+    L.W32 = take(static_cast<size_t>(n) * nb * 8);
+  }
+  L.total = off;
+  return L;
+}
+
+// Symmetric eigen-decomposition of a small dense matrix by cyclic Jacobi rotations (used for the
+// k x k Lanczos tridiagonals; k is a few dozen).  a: row-major k x k, destroyed.  On return
+// evals ascending and evecs[:, i] (row-major, column i) the matching eigenvectors.
+void jacobi_eigh(int k, std::vector<double>& a, std::vector<double>& evals,
+                 std::vector<double>& evecs) {
+  std::vector<double> v(static_cast<size_t>(k) * k, 0.0);
+  for (int i = 0; i < k; ++i) v[i * k + i] = 1.0;
+  double fro = 0.0;
+  for (double x : a) fro += x * x;
+  fro = std::sqrt(fro);
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0;
+    for (int p = 0; p < k; ++p)
+      for (int q = p + 1; q < k; ++q) off += a[p * k + q] * a[p * k + q];
+    if (std::sqrt(off) <= 1e-17 * fro) break;
+    for (int p = 0; p < k; ++p)
+      for (int q = p + 1; q < k; ++q) {
+        const double apq = a[p * k + q];
+        if (apq == 0.0) continue;
+        const double theta = (a[q * k + q] - a[p * k + p]) / (2.0 * apq);
+        const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+        const double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+        for (int r = 0; r < k; ++r) {  // columns p, q
+          const double arp = a[r * k + p], arq = a[r * k + q];
+          a[r * k + p] = c * arp - s * arq;
+          a[r * k + q] = s * arp + c * arq;
+        }
+        for (int r = 0; r < k; ++r) {  // rows p, q
+          const double apr = a[p * k + r], aqr = a[q * k + r];
+          a[p * k + r] = c * apr - s * aqr;
+          a[q * k + r] = s * apr + c * aqr;
+        }
+        for (int r = 0; r < k; ++r) {
+          const double vrp = v[r * k + p], vrq = v[r * k + q];
+          v[r * k + p] = c * vrp - s * vrq;
+          v[r * k + q] = s * vrp + c * vrq;
+        }
+      }
+  }
+  std::vector<int> idx(k);
+  std::iota(idx.begin(), idx.end(), 0);
+  std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return a[x * k + x] < a[y * k + y]; });
+  evals.resize(k);
+  evecs.assign(static_cast<size_t>(k) * k, 0.0);
+  for (int i = 0; i < k; ++i) {
+    evals[i] = a[idx[i] * k + idx[i]];
+    for (int r = 0; r < k; ++r) evecs[r * k + i] = v[r * k + idx[i]];
+  }
+}
+
+struct LanczosRun {
+  std::vector<double> ritz, evecs;  // evecs row-major k x k, column i = eigenvector i
+  int k = 0;
+  double beta_last = 0.0;
+};
+
+LanczosRun tridiag_eig(const std::vector<double>& al, const std::vector<double>& be, int nv, int c,
+                       int k) {
+  // truncate at the first vanishing beta (invariant subspace)
+  int kk = k;
+  for (int j = 0; j < k; ++j)
+    if (!(be[j * nv + c] > 0.0)) {
+      kk = j + 1;
+      break;
+    }
+  std::vector<double> T(static_cast<size_t>(kk) * kk, 0.0);
+  for (int j = 0; j < kk; ++j) {
+    T[j * kk + j] = al[j * nv + c];
+    if (j + 1 < kk) T[j * kk + j + 1] = T[(j + 1) * kk + j] = be[j * nv + c];
+  }
+  LanczosRun r;
+  r.k = kk;
+  r.beta_last = be[(kk - 1) * nv + c];
+  jacobi_eigh(kk, T, r.ritz, r.evecs);
+  return r;
+}
+
+// mu_{nev+nex} from the Gaussian-smoothed spectral density of the DoS runs (Sec. 4.2, Eq. (10)):
+// bisection on sum_i w_i Phi((t - lambda_i)/s) = (nev+nex)/n.
+double dos_mu(const std::vector<LanczosRun>& runs, double lo, double b_sup, double sigma,
+              double target) {
+  const double half = b_sup > lo ? 0.5 * (b_sup - lo) : 1.0;
+  const double s = sigma * half;
+  auto cdf = [&](double t) {
+    double acc = 0.0;
+    for (const auto& r : runs)
+      for (int i = 0; i < r.k; ++i) {
+        const double w = r.evecs[0 * r.k + i] * r.evecs[0 * r.k + i];
+        acc += w * 0.5 * (1.0 + std::erf((t - r.ritz[i]) / (s * std::sqrt(2.0))));
+      }
+    return acc / static_cast<double>(runs.size());
+  };
+  double a = lo - 8.0 * s, b = b_sup + 8.0 * s;
+  for (int it = 0; it < 200; ++it) {
+    const double mid = 0.5 * (a + b);
+    if (cdf(mid) < target)
+      a = mid;
+    else
+      b = mid;
+  }
+  return 0.5 * (a + b);
+}
+
+// Algorithm 5 for one vector.
+int degree_of(double tol, double res, double ritz, double c, double e, int deg_extra, int deg_max) {
+  const double t = (ritz - c) / e;
+  double rho;
+  if (std::fabs(t) <= 1.0) {
+    rho = 1.0;
+  } else {
+    const double r = std::sqrt(t * t - 1.0);
+    rho = std::max(std::fabs(t - r), std::fabs(t + r));
+  }
+  const double lr = std::log(rho);
+  int d;
+  if (!(lr > 0.0) || !(res > 0.0)) {
+    d = deg_max;
+  } else {
+    const double q = std::fabs(std::log(res / tol) / lr);
+    const double dd = std::ceil(q) + deg_extra;
+    d = dd > deg_max ? deg_max : static_cast<int>(dd);
+  }
+  return d + (d & 1);
+}
+
+struct Timer {
+  hipEvent_t a = nullptr, b = nullptr;
+  ~Timer() {
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+  }
+};
+
+class Solver {
+ public:
+  Solver(chase_ctx* ctx, const chase_config& cfg) : ctx_(ctx), cfg_(cfg) {}
+  int run(const void* H, int64_t ldh, void* Vuser, int64_t ldv, double* ritzv, double* resid,
+          chase_stats* stats);
+
+ private:
+  chase_ctx* ctx_;
+  chase_config cfg_;
+  Layout L_{};
+  char* base_ = nullptr;
+  int64_t n_ = 0, nb_ = 0;
+  hipStream_t s_ = nullptr;
+  chase_stats st_{};
+  int fallbacks_ = 0;
+
+  template <typename P> P* at(size_t off) { return reinterpret_cast<P*>(base_ + off); }
+  double* col(size_t off, int64_t c) { return at<double>(off) + 2 * c * n_; }
+
+  int blas(rocblas_status s, const char* what) {
+    if (s != rocblas_status_success)
+      return set_error(ctx_, CHASE_EDEVICE, std::string(what) + ": rocBLAS/rocSOLVER status " +
+                                                std::to_string(static_cast<int>(s)));
+    return CHASE_OK;
+  }
+  int hip(hipError_t e, const char* what) {
+    if (e != hipSuccess)
+      return set_error(ctx_, CHASE_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+    return CHASE_OK;
+  }
+  int zgemm(rocblas_operation ta, rocblas_operation tb, int64_t m, int64_t nn, int64_t k,
+            double ar, const double* A, int64_t lda, const double* B, int64_t ldb, double br,
+            double* C, int64_t ldc) {
+    const rocblas_double_complex al(ar, 0.0), be(br, 0.0);
+    return blas(rocblas_zgemm(ctx_->blas, ta, tb, static_cast<rocblas_int>(m),
+                              static_cast<rocblas_int>(nn), static_cast<rocblas_int>(k), &al,
+                              reinterpret_cast<const rocblas_double_complex*>(A),
+                              static_cast<rocblas_int>(lda),
+                              reinterpret_cast<const rocblas_double_complex*>(B),
+                              static_cast<rocblas_int>(ldb), &be,
+                              reinterpret_cast<rocblas_double_complex*>(C),
+                              static_cast<rocblas_int>(ldc)),
+                "zgemm");
+  }
+  int lanczos(const double* H, int64_t ldh, double* V);
+  int cgs(int64_t nlock, int64_t nact);
+  int cholqr(int64_t nact, bool shift, bool* ok);
+  int householder(int64_t nlock, int64_t nact);
+  int orthogonalize(int64_t nlock, int64_t nact);
+  int filter(const double* H, int64_t ldh, int64_t nlock, int64_t nact,
+             const std::vector<int>& m, const std::vector<int>& prec);
+  int read_info(int* out) {
+    int rc = hip(hipMemcpyAsync(out, at<int>(L_.info), sizeof(int), hipMemcpyDeviceToHost, s_),
+                 "info");
+    if (rc) return rc;
+    return hip(hipStreamSynchronize(s_), "sync");
+  }
+
+  double b_sup_ = 0, mu_1_ = 0, mu_b_ = 0, norm_est_ = 0;
+};
+
+int Solver::lanczos(const double* H, int64_t ldh, double* V) {
+  const bool need_dos = !cfg_.approx && !cfg_.have_mu;
+  const int64_t nv = need_dos ? 1 + cfg_.num_lanczos : 1;
+  const int k = static_cast<int>(std::min<int64_t>(cfg_.lanczos_iter, n_));
+  double* U = at<double>(L_.U);
+  int rc;
+  if (cfg_.lanczos_start) {
+    rc = hip(hipMemcpyAsync(U, cfg_.lanczos_start, static_cast<size_t>(n_) * nv * 16,
+                            hipMemcpyDeviceToDevice, s_),
+             "copy lanczos start");
+  } else {
+    rc = hip(launch_gaussian(U, n_, n_, nv, cfg_.seed, s_), "gaussian");
+  }
+  if (rc) return rc;
+  if ((rc = hip(launch_normalize(U, n_, n_, nv, s_), "normalize"))) return rc;
+  if ((rc = hip(hipMemsetAsync(at<double>(L_.zero), 0, nv * 8, s_), "memset"))) return rc;
+  double* Wl = at<double>(L_.Wl);
+  for (int j = 0; j < k; ++j) {
+    double* Uj = U + 2 * static_cast<int64_t>(j) * nv * n_;
+    const double* Up = j > 0 ? U + 2 * static_cast<int64_t>(j - 1) * nv * n_ : Uj;
+    const double* bp = j > 0 ? at<double>(L_.lbe) + (j - 1) * nv : at<double>(L_.zero);
+    if ((rc = hip(launch_hemm_step<double>(H, ldh, n_, Uj, n_, Wl, n_, nv, 1.0, 0.0, 0.0, s_),
+                  "lanczos product")))
+      return rc;
+    if ((rc = hip(launch_lanczos_step(Uj, Up, Wl, Uj + 2 * nv * n_, n_, n_, nv, bp,
+                                      at<double>(L_.lal) + j * nv, at<double>(L_.lbe) + j * nv, s_),
+                  "lanczos step")))
+      return rc;
+  }
+  std::vector<double> al(static_cast<size_t>(nv) * k), be(static_cast<size_t>(nv) * k);
+  if ((rc = hip(hipMemcpyAsync(al.data(), at<double>(L_.lal), al.size() * 8, hipMemcpyDeviceToHost,
+                               s_), "d2h")))
+    return rc;
+  if ((rc = hip(hipMemcpyAsync(be.data(), at<double>(L_.lbe), be.size() * 8, hipMemcpyDeviceToHost,
+                               s_), "d2h")))
+    return rc;
+  if ((rc = hip(hipStreamSynchronize(s_), "sync"))) return rc;
+  st_.matvecs += static_cast<int64_t>(k) * nv;
+  for (double x : al)
+    if (!std::isfinite(x)) return set_error(ctx_, CHASE_ENUMERIC, "Lanczos produced NaN/Inf");
+
+  LanczosRun r0 = tridiag_eig(al, be, static_cast<int>(nv), 0, k);
+  b_sup_ = r0.beta_last + r0.ritz.back();                      // Alg. 6 line 3
+  norm_est_ = std::max(std::fabs(r0.ritz.front()), std::fabs(r0.ritz.back()));
+  if (!need_dos) return CHASE_OK;
+
+  std::vector<LanczosRun> runs;
+  double lo = INFINITY;
+  for (int c = 1; c < nv; ++c) {
+    runs.push_back(tridiag_eig(al, be, static_cast<int>(nv), c, k));
+    lo = std::min(lo, runs.back().ritz.front());
+  }
+  mu_1_ = lo;                                                   // Alg. 6 line 12
+  mu_b_ = dos_mu(runs, lo, b_sup_, cfg_.dos_sigma,
+                 static_cast<double>(nb_) / static_cast<double>(n_));
+  if (cfg_.intersperse) {                                       // Alg. 6 line 13
+    const LanczosRun& r1 = runs.front();
+    std::vector<int> sel;
+    for (int i = 0; i < r1.k; ++i)
+      if (r1.ritz[i] < mu_b_) sel.push_back(i);
+    if (static_cast<int64_t>(sel.size()) > nb_) sel.resize(nb_);
+    const int64_t r = static_cast<int64_t>(sel.size());
+    if (r > 0) {
+      std::vector<double> Zh(static_cast<size_t>(r1.k) * r * 2, 0.0);  // k x r complex, col-major
+      for (int64_t q = 0; q < r; ++q)
+        for (int j = 0; j < r1.k; ++j) Zh[2 * (j + q * r1.k)] = r1.evecs[j * r1.k + sel[q]];
+      if ((rc = hip(hipMemcpyAsync(at<double>(L_.Z), Zh.data(), Zh.size() * 8,
+                                   hipMemcpyHostToDevice, s_), "h2d")))
+        return rc;
+      // basis of DoS run 1: columns U_j[:, 1], j < k, stride nv*n between consecutive j
+      if ((rc = zgemm(rocblas_operation_none, rocblas_operation_none, n_, r, r1.k, 1.0,
+                      U + 2 * n_, nv * n_, at<double>(L_.Z), r1.k, 0.0, V, n_)))
+        return rc;
+      if ((rc = hip(hipStreamSynchronize(s_), "sync"))) return rc;
+    }
+  }
+  return CHASE_OK;
+}
+
+// Block classical Gram-Schmidt of the active block against the locked prefix Y = V[:, :nlock].
+int Solver::cgs(int64_t nlock, int64_t nact) {
+  if (nlock == 0) return CHASE_OK;
+  double* Y = at<double>(L_.V);
+  double* A = col(L_.V, nlock);
+  double* T = at<double>(L_.T);
+  int rc = zgemm(rocblas_operation_conjugate_transpose, rocblas_operation_none, nlock, nact, n_, 1.0,
+                 Y, n_, A, n_, 0.0, T, nb_);
+  if (rc) return rc;
+  return zgemm(rocblas_operation_none, rocblas_operation_none, n_, nact, nlock, -1.0, Y, n_, T, nb_,
+               1.0, A, n_);
+}
+
+// One (optionally shifted) Cholesky QR pass on the active block: G = A^H A (+ s I) = R^H R,
+// A <- A R^-1.  Shift as in shifted CholeskyQR3 (Fukaya et al.) with ||A||_2^2 <= nact for
+// unit columns.
+int Solver::cholqr(int64_t nact, bool shift, bool* ok) {
+  double* A = col(L_.V, n_ == 0 ? 0 : (nb_ - nact));
+  double* G = at<double>(L_.G);
+  const double one = 1.0, zero = 0.0;
+  int rc = blas(rocblas_zherk(ctx_->blas, rocblas_fill_upper, rocblas_operation_conjugate_transpose,
+                              static_cast<rocblas_int>(nact), static_cast<rocblas_int>(n_), &one,
+                              reinterpret_cast<const rocblas_double_complex*>(A),
+                              static_cast<rocblas_int>(n_), &zero,
+                              reinterpret_cast<rocblas_double_complex*>(G),
+                              static_cast<rocblas_int>(nb_)),
+                "zherk");
+  if (rc) return rc;
+  if (shift) {
+    const double s = 11.0 * (static_cast<double>(n_) * nact + static_cast<double>(nact) * (nact + 1)) *
+                     kEps * static_cast<double>(nact);
+    if ((rc = hip(launch_add_diag(G, nb_, nact, s, s_), "add_diag"))) return rc;
+  }
+  if ((rc = blas(rocsolver_zpotrf(ctx_->blas, rocblas_fill_upper, static_cast<rocblas_int>(nact),
+                                  reinterpret_cast<rocblas_double_complex*>(G),
+                                  static_cast<rocblas_int>(nb_), at<rocblas_int>(L_.info)),
+                 "zpotrf")))
+    return rc;
+  int info = 0;
+  if ((rc = read_info(&info))) return rc;
+  if (info != 0) {
+    *ok = false;
+    return CHASE_OK;
+  }
+  const rocblas_double_complex al(1.0, 0.0);
+  rc = blas(rocblas_ztrsm(ctx_->blas, rocblas_side_right, rocblas_fill_upper, rocblas_operation_none,
+                          rocblas_diagonal_non_unit, static_cast<rocblas_int>(n_),
+                          static_cast<rocblas_int>(nact), &al,
+                          reinterpret_cast<const rocblas_double_complex*>(G),
+                          static_cast<rocblas_int>(nb_), reinterpret_cast<rocblas_double_complex*>(A),
+                          static_cast<rocblas_int>(n_)),
+            "ztrsm");
+  *ok = true;
+  return rc;
+}
+
+// Householder QR of [Y V] (the paper's ORTHOGONALIZE), keeping the columns after Y.
+int Solver::householder(int64_t nlock, int64_t nact) {
+  ++fallbacks_;
+  const int64_t ncol = nlock + nact;
+  double* Wb = at<double>(L_.W);
+  int rc = hip(hipMemcpyAsync(Wb, at<double>(L_.V), static_cast<size_t>(n_) * ncol * 16,
+                              hipMemcpyDeviceToDevice, s_),
+               "copy");
+  if (rc) return rc;
+  auto* tau = at<rocblas_double_complex>(L_.tau);
+  if ((rc = blas(rocsolver_zgeqrf(ctx_->blas, static_cast<rocblas_int>(n_),
+                                  static_cast<rocblas_int>(ncol),
+                                  reinterpret_cast<rocblas_double_complex*>(Wb),
+                                  static_cast<rocblas_int>(n_), tau),
+                 "zgeqrf")))
+    return rc;
+  if ((rc = blas(rocsolver_zungqr(ctx_->blas, static_cast<rocblas_int>(n_),
+                                  static_cast<rocblas_int>(ncol), static_cast<rocblas_int>(ncol),
+                                  reinterpret_cast<rocblas_double_complex*>(Wb),
+                                  static_cast<rocblas_int>(n_), tau),
+                 "zungqr")))
+    return rc;
+  return hip(hipMemcpyAsync(col(L_.V, nlock), Wb + 2 * nlock * n_,
+                            static_cast<size_t>(n_) * nact * 16, hipMemcpyDeviceToDevice, s_),
+             "copy");
+}
+
+int Solver::orthogonalize(int64_t nlock, int64_t nact) {
+  int rc;
+  double* A = col(L_.V, nlock);
+  if ((rc = cgs(nlock, nact))) return rc;
+  if ((rc = hip(launch_normalize(A, n_, n_, nact, s_), "normalize"))) return rc;
+  bool ok = true;
+  if ((rc = cholqr(nact, true, &ok))) return rc;
+  if (ok) {
+    if ((rc = cgs(nlock, nact))) return rc;
+    if ((rc = cholqr(nact, false, &ok))) return rc;
+  }
+  if (ok && (rc = cholqr(nact, false, &ok))) return rc;
+  if (!ok) return householder(nlock, nact);
+  return CHASE_OK;
+}
+
+int Solver::filter(const double* H, int64_t ldh, int64_t nlock, int64_t nact,
+                   const std::vector<int>& m, const std::vector<int>& prec) {
+  int64_t n32 = 0;
+  while (n32 < nact && prec[n32] == 1) ++n32;
+  int rc;
+  int64_t mv = 0;
+  if (n32 > 0) {
+    float* V32 = at<float>(L_.V32);
+    if ((rc = hip(launch_convert_c128_to_c64(col(L_.V, nlock), n_, V32, n_, n_, n32, s_), "cvt")))
+      return rc;
+    if ((rc = hip(run_filter<float>(at<float>(L_.H32), n_, n_, V32, at<float>(L_.W32), n_, n32,
+                                    m.data(), b_sup_, mu_1_, mu_b_, s_, &mv),
+                  "filter fp32")))
+      return rc;
+    st_.filter_matvecs += mv;
+    if ((rc = hip(launch_convert_c64_to_c128(V32, n_, col(L_.V, nlock), n_, n_, n32, s_), "cvt")))
+      return rc;
+  }
+  if (nact - n32 > 0) {
+    if ((rc = hip(run_filter<double>(H, ldh, n_, col(L_.V, nlock + n32), col(L_.W, nlock + n32),
+                                     n_, nact - n32, m.data() + n32, b_sup_, mu_1_, mu_b_, s_, &mv),
+                  "filter fp64")))
+      return rc;
+    st_.filter_matvecs += mv;
+  }
+  return CHASE_OK;
+}
+
+int Solver::run(const void* Hv, int64_t ldh, void* Vuser, int64_t ldv, double* ritzv, double* resid,
+                chase_stats* stats) {
+  const double* H = static_cast<const double*>(Hv);
+  n_ = cfg_.n;
+  nb_ = cfg_.nev + cfg_.nex;
+  s_ = ctx_->stream;
+  const bool mixed = cfg_.precision == CHASE_MIXED;
+  const bool need_dos = !cfg_.approx && !cfg_.have_mu;
+  const int64_t nv = need_dos ? 1 + cfg_.num_lanczos : 1;
+  const int64_t k = std::min<int64_t>(cfg_.lanczos_iter, n_);
+  L_ = make_layout(n_, nb_, nv, k, mixed);
+  int rc = ensure_workspace(ctx_, L_.total);
+  if (rc) return rc;
+  base_ = static_cast<char*>(ctx_->ws);
+  std::memset(&st_, 0, sizeof(st_));
+
+  hipEvent_t ev[8];
+  for (auto& e : ev)
+    if ((rc = hip(hipEventCreate(&e), "event"))) return rc;
+  struct EvGuard {
+    hipEvent_t* e;
+    ~EvGuard() {
+      for (int i = 0; i < 8; ++i) (void)hipEventDestroy(e[i]);
+    }
+  } guard{ev};
+  auto elapsed = [&](int a, int b) {
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, ev[a], ev[b]);
+    return static_cast<double>(ms);
+  };
+
+  (void)hipEventRecord(ev[6], s_);
+  // state: V (ld n) <- user block
+  if ((rc = hip(hipMemcpy2DAsync(at<double>(L_.V), n_ * 16, Vuser, ldv * 16, n_ * 16, nb_,
+                                 hipMemcpyDeviceToDevice, s_),
+                "copy V")))
+    return rc;
+  if (mixed && (rc = hip(launch_convert_c128_to_c64(H, ldh, at<float>(L_.H32), n_, n_, n_, s_),
+                         "convert H")))
+    return rc;
+
+  // ---------------------------------------------------------------- LANCZOS (Alg. 1 line 2)
+  (void)hipEventRecord(ev[0], s_);
+  if ((rc = lanczos(H, ldh, at<double>(L_.V)))) return rc;
+  (void)hipEventRecord(ev[1], s_);
+  if (cfg_.approx) {
+    double lo = ritzv[0], hi = ritzv[0];
+    for (int64_t i = 1; i < nb_; ++i) {
+      lo = std::min(lo, ritzv[i]);
+      hi = std::max(hi, ritzv[i]);
+    }
+    mu_1_ = lo;
+    mu_b_ = hi;
+  } else if (cfg_.have_mu) {
+    mu_1_ = cfg_.mu_1;
+    mu_b_ = cfg_.mu_nevnex;
+  }
+  if (!(mu_1_ < mu_b_ && mu_b_ < b_sup_)) {
+    // degenerate bounds (e.g. a warm start whose Ritz values all coincide): widen minimally
+    if (!(mu_b_ < b_sup_)) mu_b_ = 0.5 * (mu_1_ + b_sup_);
+    if (!(mu_1_ < mu_b_)) mu_1_ = mu_b_ - 1e-3 * (b_sup_ - mu_b_);
+  }
+  (void)hipEventSynchronize(ev[1]);
+  st_.lanczos_ms = elapsed(0, 1);
+  const double tol_eff = cfg_.resid_relative ? cfg_.tol * norm_est_ : cfg_.tol;
+  const double tol32 = cfg_.resid_relative ? cfg_.switch_resid * norm_est_ : cfg_.switch_resid;
+  const int deg0 = cfg_.deg + (cfg_.deg & 1);
+  const int deg32max = cfg_.deg_max_fp32 + (cfg_.deg_max_fp32 & 1);
+
+  // ---------------------------------------------------------------- main loop (Alg. 1 line 3)
+  int64_t nlock = 0;
+  std::vector<int> m(nb_, mixed ? std::min(deg0, deg32max) : deg0);
+  std::vector<int> prec(nb_, mixed ? 1 : 0);
+  std::vector<double> lam_act(nb_, 0.0), res_act(nb_, 0.0), lam_lock, res_lock;
+  std::vector<int> perm(nb_);
+  int it = 0;
+  while (nlock < cfg_.nev && it < cfg_.max_iter) {
+    ++it;
+    const int64_t nact = nb_ - nlock;
+    bool any32 = false;
+    for (int64_t a = 0; a < nact; ++a) any32 |= prec[a] == 1;
+    if (any32) ++st_.fp32_iterations;
+    (void)hipEventRecord(ev[0], s_);
+    if ((rc = filter(H, ldh, nlock, nact, m, prec))) return rc;             // line 4
+    (void)hipEventRecord(ev[1], s_);
+    if ((rc = orthogonalize(nlock, nact))) return rc;                       // lines 5-6
+    (void)hipEventRecord(ev[2], s_);
+    // RAYLEIGH-RITZ (line 7, Alg. 2)
+    double* Q = col(L_.V, nlock);
+    double* AQ = at<double>(L_.AQ);
+    double* G = at<double>(L_.G);
+    if ((rc = hip(launch_hemm_step<double>(H, ldh, n_, Q, n_, AQ, n_, nact, 1.0, 0.0, 0.0, s_),
+                  "H Q")))
+      return rc;
+    st_.matvecs += nact;
+    if ((rc = zgemm(rocblas_operation_conjugate_transpose, rocblas_operation_none, nact, nact, n_,
+                    1.0, Q, n_, AQ, n_, 0.0, G, nb_)))
+      return rc;
+    if ((rc = hip(launch_herm_sym(G, nb_, nact, s_), "sym"))) return rc;
+    if ((rc = blas(rocsolver_zheevd(ctx_->blas, rocblas_evect_original, rocblas_fill_upper,
+                                    static_cast<rocblas_int>(nact),
+                                    reinterpret_cast<rocblas_double_complex*>(G),
+                                    static_cast<rocblas_int>(nb_), at<double>(L_.lam),
+                                    at<double>(L_.evE), at<rocblas_int>(L_.info)),
+                   "zheevd")))
+      return rc;
+    double* Wb = at<double>(L_.W);
+    double* Xb = at<double>(L_.X);
+    if ((rc = zgemm(rocblas_operation_none, rocblas_operation_none, n_, nact, nact, 1.0, Q, n_, G,
+                    nb_, 0.0, Wb, n_)))
+      return rc;
+    if ((rc = zgemm(rocblas_operation_none, rocblas_operation_none, n_, nact, nact, 1.0, AQ, n_, G,
+                    nb_, 0.0, Xb, n_)))
+      return rc;
+    (void)hipEventRecord(ev[3], s_);
+    // residuals (line 8)
+    if ((rc = hip(launch_resid(Xb, Wb, at<double>(L_.lam), n_, n_, nact, at<double>(L_.res), s_),
+                  "resid")))
+      return rc;
+    if ((rc = hip(hipMemcpyAsync(Q, Wb, static_cast<size_t>(n_) * nact * 16,
+                                 hipMemcpyDeviceToDevice, s_),
+                  "copy")))
+      return rc;
+    int info = 0;
+    if ((rc = hip(hipMemcpyAsync(lam_act.data(), at<double>(L_.lam), nact * 8,
+                                 hipMemcpyDeviceToHost, s_), "d2h")))
+      return rc;
+    if ((rc = hip(hipMemcpyAsync(res_act.data(), at<double>(L_.res), nact * 8,
+                                 hipMemcpyDeviceToHost, s_), "d2h")))
+      return rc;
+    if ((rc = hip(hipMemcpyAsync(&info, at<int>(L_.info), sizeof(int), hipMemcpyDeviceToHost, s_),
+                  "d2h")))
+      return rc;
+    (void)hipEventRecord(ev[4], s_);
+    if ((rc = hip(hipStreamSynchronize(s_), "sync"))) return rc;
+    st_.filter_ms += elapsed(0, 1);
+    st_.ortho_ms += elapsed(1, 2);
+    st_.rr_ms += elapsed(2, 3);
+    st_.resid_ms += elapsed(3, 4);
+    if (info != 0) return set_error(ctx_, CHASE_ENUMERIC, "zheevd did not converge");
+    for (int64_t a = 0; a < nact; ++a)
+      if (!std::isfinite(lam_act[a]) || !std::isfinite(res_act[a]))
+        return set_error(ctx_, CHASE_ENUMERIC, "NaN/Inf in Ritz values or residuals");
+
+    // DEFLATION & LOCKING (line 9, Alg. 3): Ritz values arrive ascending from zheevd.
+    std::vector<int> order(nact);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int x, int y) { return lam_act[x] < lam_act[y]; });
+    int64_t n_new = 0;
+    while (n_new < nact && res_act[order[n_new]] <= tol_eff) ++n_new;
+    for (int64_t q = 0; q < n_new; ++q) {
+      lam_lock.push_back(lam_act[order[q]]);
+      res_lock.push_back(res_act[order[q]]);
+    }
+    // interval update (lines 10-11)
+    double lo = INFINITY, hi = -INFINITY;
+    for (double x : lam_lock) lo = std::min(lo, x), hi = std::max(hi, x);
+    for (int64_t a = 0; a < nact; ++a) lo = std::min(lo, lam_act[a]), hi = std::max(hi, lam_act[a]);
+    mu_1_ = lo;
+    mu_b_ = hi;
+    if (!(mu_b_ < b_sup_)) mu_b_ = b_sup_ - 1e-12 * std::fabs(b_sup_) - 1e-300;
+    const double c = 0.5 * (b_sup_ + mu_b_), e = 0.5 * (b_sup_ - mu_b_);
+    // degrees (lines 12-14, Alg. 5) and precision groups
+    const int64_t rem = nact - n_new;
+    std::vector<int> mnew(rem), pnew(rem), idx(rem);
+    for (int64_t q = 0; q < rem; ++q) {
+      const int a = order[n_new + q];
+      const bool fp32 = mixed && res_act[a] > tol32;
+      pnew[q] = fp32 ? 1 : 0;
+      if (cfg_.optim)
+        mnew[q] = fp32 ? degree_of(tol32, res_act[a], lam_act[a], c, e, cfg_.deg_extra, deg32max)
+                       : degree_of(tol_eff, res_act[a], lam_act[a], c, e, cfg_.deg_extra,
+                                   cfg_.deg_max);
+      else
+        mnew[q] = fp32 ? std::min(deg0, deg32max) : deg0;
+      idx[q] = static_cast<int>(q);
+    }
+    // sort (line 15): key (precision group: FP32 first, degree)
+    std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) {
+      if (pnew[x] != pnew[y]) return pnew[x] > pnew[y];
+      return mnew[x] < mnew[y];
+    });
+    std::vector<double> la2(nb_), re2(nb_);
+    for (int64_t q = 0; q < n_new; ++q) perm[q] = order[q];
+    for (int64_t q = 0; q < rem; ++q) {
+      perm[n_new + q] = order[n_new + idx[q]];
+      m[q] = mnew[idx[q]];
+      prec[q] = pnew[idx[q]];
+      la2[q] = lam_act[order[n_new + idx[q]]];
+      re2[q] = res_act[order[n_new + idx[q]]];
+    }
+    for (int64_t q = 0; q < rem; ++q) lam_act[q] = la2[q], res_act[q] = re2[q];
+    // apply the order on the device: W <- V[:, perm], V <- W
+    if ((rc = hip(hipMemcpyAsync(at<int>(L_.perm), perm.data(), nact * 4, hipMemcpyHostToDevice, s_),
+                  "h2d")))
+      return rc;
+    if ((rc = hip(launch_gather(Q, n_, Wb, n_, n_, at<int>(L_.perm), nact, s_), "gather"))) return rc;
+    if ((rc = hip(hipMemcpyAsync(Q, Wb, static_cast<size_t>(n_) * nact * 16,
+                                 hipMemcpyDeviceToDevice, s_),
+                  "copy")))
+      return rc;
+    nlock += n_new;
+  }
+
+  // ---------------------------------------------------------------- output
+  const int64_t nact = nb_ - nlock;
+  std::vector<int> lo_idx(nlock), ac_idx(nact);
+  std::iota(lo_idx.begin(), lo_idx.end(), 0);
+  std::iota(ac_idx.begin(), ac_idx.end(), 0);
+  std::stable_sort(lo_idx.begin(), lo_idx.end(), [&](int x, int y) { return lam_lock[x] < lam_lock[y]; });
+  std::stable_sort(ac_idx.begin(), ac_idx.end(), [&](int x, int y) { return lam_act[x] < lam_act[y]; });
+  for (int64_t q = 0; q < nlock; ++q) {
+    perm[q] = lo_idx[q];
+    ritzv[q] = lam_lock[lo_idx[q]];
+    resid[q] = res_lock[lo_idx[q]];
+  }
+  for (int64_t q = 0; q < nact; ++q) {
+    perm[nlock + q] = static_cast<int>(nlock) + ac_idx[q];
+    ritzv[nlock + q] = lam_act[ac_idx[q]];
+    resid[nlock + q] = res_act[ac_idx[q]];
+  }
+  if ((rc = hip(hipMemcpyAsync(at<int>(L_.perm), perm.data(), nb_ * 4, hipMemcpyHostToDevice, s_),
+                "h2d")))
+    return rc;
+  if ((rc = hip(launch_gather(at<double>(L_.V), n_, at<double>(L_.W), n_, n_, at<int>(L_.perm), nb_,
+                              s_),
+                "gather")))
+    return rc;
+  if ((rc = hip(hipMemcpy2DAsync(Vuser, ldv * 16, at<double>(L_.W), n_ * 16, n_ * 16, nb_,
+                                 hipMemcpyDeviceToDevice, s_),
+                "copy out")))
+    return rc;
+  (void)hipEventRecord(ev[7], s_);
+  if ((rc = hip(hipStreamSynchronize(s_), "sync"))) return rc;
+  st_.total_ms = elapsed(6, 7);
+  st_.iterations = it;
+  st_.nconv = static_cast<int32_t>(nlock);
+  st_.qr_fallbacks = fallbacks_;
+  st_.matvecs += st_.filter_matvecs;
+  st_.filter_flops = 8.0 * static_cast<double>(n_) * static_cast<double>(n_) *
+                     static_cast<double>(st_.filter_matvecs);
+  st_.b_sup = b_sup_;
+  st_.mu_1 = mu_1_;
+  st_.mu_nevnex = mu_b_;
+  st_.norm_est = norm_est_;
+  st_.status = nlock >= cfg_.nev ? CHASE_OK : CHASE_NOT_CONVERGED;
+  if (stats) *stats = st_;
+  return st_.status;
+}
+
+int check_config(chase_ctx* ctx, const chase_config* cfg) {
+  if (!cfg) return set_error(ctx, CHASE_EINVAL, "cfg is NULL");
+  if (cfg->n < 1 || cfg->nev < 1 || cfg->nex < 0 || cfg->nev + cfg->nex > cfg->n)
+    return set_error(ctx, CHASE_EINVAL, "need n >= 1, nev >= 1, nex >= 0, nev + nex <= n");
+  if (cfg->n > 0x7fffffffLL) return set_error(ctx, CHASE_EINVAL, "n must fit in int32");
+  if (!(cfg->tol > 0.0) || !std::isfinite(cfg->tol))
+    return set_error(ctx, CHASE_EINVAL, "tol must be positive");
+  if (cfg->deg < 1 || cfg->deg > 64 || cfg->deg_max < 2 || cfg->deg_max > 64 || cfg->deg_extra < 0)
+    return set_error(ctx, CHASE_EINVAL, "deg in [1, 64], deg_max in [2, 64], deg_extra >= 0");
+  if (cfg->max_iter < 1) return set_error(ctx, CHASE_EINVAL, "max_iter must be >= 1");
+  if (cfg->lanczos_iter < 1 || cfg->num_lanczos < 1)
+    return set_error(ctx, CHASE_EINVAL, "lanczos_iter and num_lanczos must be >= 1");
+  if (cfg->precision != CHASE_FP64 && cfg->precision != CHASE_MIXED)
+    return set_error(ctx, CHASE_EINVAL, "precision must be CHASE_FP64 or CHASE_MIXED");
+  if (cfg->precision == CHASE_MIXED &&
+      (!(cfg->switch_resid > 0.0) || cfg->deg_max_fp32 < 2 || cfg->deg_max_fp32 > 64))
+    return set_error(ctx, CHASE_EINVAL, "switch_resid > 0 and deg_max_fp32 in [2, 64]");
+  if (!(cfg->dos_sigma > 0.0)) return set_error(ctx, CHASE_EINVAL, "dos_sigma must be positive");
+  if (cfg->have_mu && !cfg->approx &&
+      !(std::isfinite(cfg->mu_1) && std::isfinite(cfg->mu_nevnex) && cfg->mu_1 < cfg->mu_nevnex))
+    return set_error(ctx, CHASE_EINVAL, "need finite mu_1 < mu_nevnex");
+  return CHASE_OK;
+}
+
+int solve_impl(chase_ctx* ctx, const chase_config* cfg, const void* H, int64_t ldh, void* V,
+               int64_t ldv, double* ritzv, double* resid, chase_stats* stats) {
+  if (!ctx) return CHASE_EINVAL;
+  ctx->last_error.clear();
+  int rc = check_config(ctx, cfg);
+  if (rc) return rc;
+  if (!H || !V || !ritzv || !resid) return set_error(ctx, CHASE_EINVAL, "NULL buffer");
+  if (ldh < cfg->n || ldv < cfg->n) return set_error(ctx, CHASE_EINVAL, "leading dimension < n");
+  const int64_t nb = cfg->nev + cfg->nex;
+  if (cfg->approx)
+    for (int64_t i = 0; i < nb; ++i)
+      if (!std::isfinite(ritzv[i])) return set_error(ctx, CHASE_EINVAL, "ritzv must be finite");
+  const char* ph = static_cast<const char*>(H);
+  const char* pv = static_cast<const char*>(V);
+  const size_t hb = (static_cast<size_t>(cfg->n - 1) * ldh + cfg->n) * 16;
+  const size_t vb = (static_cast<size_t>(nb - 1) * ldv + cfg->n) * 16;
+  if (ph < pv + vb && pv < ph + hb) return set_error(ctx, CHASE_EINVAL, "H and V overlap");
+  if ((rc = hip_ok(ctx))) return rc;
+  Solver s(ctx, *cfg);
+  return s.run(H, ldh, V, ldv, ritzv, resid, stats);
+}
+
+}  // namespace
+
+int hip_ok(chase_ctx* ctx) {
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess)
+    return set_error(ctx, CHASE_EDEVICE, std::string("hipSetDevice: ") + hipGetErrorString(e));
+  return CHASE_OK;
+}
+
+}  // namespace chase
+
+struct chase_seq {
+  chase_ctx* ctx = nullptr;
+  chase_config cfg{};
+  double* V = nullptr;  // n x (nev + nex), ld n, device resident between problems
+  std::vector<double> ritzv;
+  int64_t solved = 0;
+};
 
 using namespace chase;
 
 extern "C" {
 
 size_t chase_workspace_bytes(const chase_config* cfg) {
-  if (!cfg || cfg->n <= 0) return 0;
-  const size_t nb = static_cast<size_t>(cfg->nev + cfg->nex);
-  return 4 * static_cast<size_t>(cfg->n) * nb * 16;
+  if (!cfg || cfg->n <= 0 || cfg->nev <= 0) return 0;
+  const int64_t nb = cfg->nev + cfg->nex;
+  const int64_t nv = cfg->approx ? 1 : 1 + std::max<int64_t>(cfg->num_lanczos, 1);
+  const int64_t k = std::min<int64_t>(std::max(cfg->lanczos_iter, 1), cfg->n);
+  return make_layout(cfg->n, nb, nv, k, cfg->precision == CHASE_MIXED).total;
 }
 
-int chase_solve(chase_ctx* ctx, const chase_config*, const void*, int64_t, void*, int64_t, double*,
-                double*, chase_stats*) {
-  return set_error(ctx, CHASE_EINVAL, "chase_solve: not built");
+int chase_solve(chase_ctx* ctx, const chase_config* cfg, const void* H, int64_t ldh, void* V,
+                int64_t ldv, double* ritzv, double* resid, chase_stats* stats) {
+  return solve_impl(ctx, cfg, H, ldh, V, ldv, ritzv, resid, stats);
 }
 
-int chase_seq_create(chase_ctx* ctx, const chase_config*, chase_seq**) {
-  return set_error(ctx, CHASE_EINVAL, "chase_seq_create: not built");
+int chase_seq_create(chase_ctx* ctx, const chase_config* cfg, chase_seq** out) {
+  if (!ctx || !out) return CHASE_EINVAL;
+  *out = nullptr;
+  int rc = check_config(ctx, cfg);
+  if (rc) return rc;
+  if ((rc = hip_ok(ctx))) return rc;
+  chase_seq* s = new chase_seq();
+  s->ctx = ctx;
+  s->cfg = *cfg;
+  const int64_t nb = cfg->nev + cfg->nex;
+  if (hipMalloc(&s->V, static_cast<size_t>(cfg->n) * nb * 16) != hipSuccess) {
+    (void)hipGetLastError();
+    delete s;
+    return set_error(ctx, CHASE_ENOMEM, "sequence state allocation failed");
+  }
+  // start block of problem 1: counter-based Gaussian from the seed
+  hipError_t e = launch_gaussian(s->V, cfg->n, cfg->n, nb, cfg->seed ^ 0x5eedULL, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) {
+    (void)hipFree(s->V);
+    delete s;
+    return set_error(ctx, CHASE_EDEVICE, std::string("sequence init: ") + hipGetErrorString(e));
+  }
+  s->ritzv.assign(nb, 0.0);
+  *out = s;
+  return CHASE_OK;
 }
-int chase_seq_solve(chase_seq*, const void*, int64_t, double*, double*, chase_stats*) {
-  return CHASE_EINVAL;
+
+int chase_seq_solve(chase_seq* seq, const void* H, int64_t ldh, double* ritzv, double* resid,
+                    chase_stats* stats) {
+  if (!seq) return CHASE_EINVAL;
+  chase_config cfg = seq->cfg;
+  cfg.approx = seq->solved > 0 ? 1 : seq->cfg.approx;
+  if (cfg.approx) cfg.have_mu = 0;
+  std::vector<double> rv = seq->ritzv;
+  const int64_t nb = cfg.nev + cfg.nex;
+  std::vector<double> rs(nb, 0.0);
+  if (seq->solved == 0 && seq->cfg.approx && ritzv) rv.assign(ritzv, ritzv + nb);
+  int rc = solve_impl(seq->ctx, &cfg, H, ldh, seq->V, cfg.n, rv.data(), rs.data(), stats);
+  if (rc < 0) return rc;
+  seq->ritzv = rv;
+  ++seq->solved;
+  if (ritzv) std::copy(rv.begin(), rv.end(), ritzv);
+  if (resid) std::copy(rs.begin(), rs.end(), resid);
+  return rc;
 }
-int chase_seq_vectors(chase_seq*, void**, int64_t*) { return CHASE_EINVAL; }
-void chase_seq_destroy(chase_seq*) {}
+
+int chase_seq_vectors(chase_seq* seq, void** V, int64_t* ldv) {
+  if (!seq || !V || !ldv) return CHASE_EINVAL;
+  *V = seq->V;
+  *ldv = seq->cfg.n;
+  return CHASE_OK;
+}
+
+void chase_seq_destroy(chase_seq* seq) {
+  if (!seq) return;
+  (void)hipSetDevice(seq->ctx->device);
+  (void)hipStreamSynchronize(seq->ctx->stream);
+  if (seq->V) (void)hipFree(seq->V);
+  delete seq;
+}
 
 }  // extern "C"

@@ -1,0 +1,222 @@
+"""GPU solve (chase_solve, chase_seq_*) against the oracle and the prescribed spectra.
+
+Bars (the benchmark spec): eigenvalues within 1e-10 * ||H|| of the FP64 oracle / the known spectrum;
+orthonormal eigenvectors; ||H y - lambda y|| <= tol * ||H|| recomputed with a fresh product.
+Iteration and matvec counts are never compared between implementations (Sec. 6.2 notes that
+rounding and randomisation change them).
+"""
+
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import chase as och
+from paper_1805_10121_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_1805_10121_amd import capi
+
+    c = capi.Context(0)
+    yield c
+    c.close()
+
+
+def _gpu_solve(ctx, H, V0, starts, **kw):
+    import torch
+    from paper_1805_10121_amd import capi
+
+    n, nb = V0.shape
+    nev = kw.pop("nev")
+    ritz_in = kw.pop("ritzv", None)
+    cfg = capi.config(n, nev, nb - nev, **kw)
+    dS = capi.to_device(starts) if starts is not None else None
+    if dS is not None:
+        cfg.lanczos_start = dS.data_ptr()
+    dH = H if isinstance(H, torch.Tensor) else capi.to_device(H)
+    dV = capi.to_device(V0)
+    ritzv = np.zeros(nb) if ritz_in is None else np.array(ritz_in, dtype=np.float64)
+    resid = np.zeros(nb)
+    rc, st = ctx.chase_solve(cfg, dH, n, dV, n, ritzv, resid)
+    return rc, st, ritzv, resid, capi.from_device(dV)
+
+
+def _check(H, lam_true, ritzv, Y, nev, tol=1e-10):
+    normH = np.max(np.abs(lam_true))
+    assert np.max(np.abs(ritzv[:nev] - lam_true[:nev])) <= tol * normH
+    Yn = Y[:, :nev]
+    assert np.linalg.norm(Yn.conj().T @ Yn - np.eye(nev)) <= 1e-12 * max(1, nev ** 0.5)
+    R = H @ Yn - Yn * ritzv[None, :nev]
+    assert np.max(np.linalg.norm(R, axis=0)) <= tol * normH * 1.0001
+
+
+@pytest.mark.parametrize("optim", [1, 0])
+def test_small_solve_vs_oracle(ctx, optim):
+    n, nev, nex = 200, 12, 6
+    g = wl.rng(31)
+    lam = wl.spectrum_uniform(n, g)
+    H = wl.hermitian_from(wl.haar_unitary(n, g), lam)
+    V0 = wl.complex_gaussian(g, n, nev + nex)
+    starts = wl.complex_gaussian(g, n, 5)
+    rc, st, ritzv, resid, Y = _gpu_solve(ctx, H, V0, starts, nev=nev, optim=optim)
+    assert rc == 0 and st.nconv >= nev
+    ev = np.linalg.eigvalsh(H)
+    _check(H, ev, ritzv, Y, nev)
+    ref = och.solve(H, och.ChaseParams(nev=nev, nex=nex, optim=bool(optim)), V0, starts)
+    assert np.max(np.abs(ritzv[:nev] - ref["ritzv"][:nev])) <= 1e-10 * np.max(np.abs(lam))
+    assert st.b_sup == pytest.approx(ref["b_sup"], rel=1e-10)
+    assert st.norm_est == pytest.approx(ref["norm_est"], rel=1e-10)
+    print(f"gpu iterations {st.iterations}, oracle {ref['iterations']}")
+
+
+def test_config1_cold_start_dos(ctx):
+    c = wl.CONFIGS[1]
+    n, nev, nex = c["n"], c["nev"], c["nex"]
+    lam = wl.spectrum_for(1)
+    H = wl.hermitian(n, lam, 1001)
+    V0 = wl.start_block(n, nev + nex, 1500)
+    starts = wl.start_block(n, 5, 1600)
+    rc, st, ritzv, resid, Y = _gpu_solve(ctx, H, V0, starts, nev=nev, optim=1)
+    assert rc == 0
+    _check(H, lam, ritzv, Y, nev)
+    ref = och.solve(H, och.ChaseParams(nev=nev, nex=nex, optim=True), V0, starts)
+    assert np.max(np.abs(ritzv[:nev] - ref["ritzv"][:nev])) <= 1e-10
+    # the DoS estimates are the same heuristic on both sides (same start vectors)
+    print(f"gpu: it={st.iterations} mv={st.matvecs} filter_mv={st.filter_matvecs}; "
+          f"oracle: it={ref['iterations']} mv={ref['matvecs']}")
+
+
+def test_config1_mixed_precision(ctx):
+    from paper_1805_10121_amd import capi
+
+    c = wl.CONFIGS[1]
+    n, nev, nex = c["n"], c["nev"], c["nex"]
+    lam = wl.spectrum_for(1)
+    H = wl.hermitian(n, lam, 1001)
+    V0 = wl.start_block(n, nev + nex, 1500)
+    starts = wl.start_block(n, 5, 1600)
+    rc, st, ritzv, resid, Y = _gpu_solve(ctx, H, V0, starts, nev=nev, optim=1,
+                                         precision=capi.CHASE_MIXED)
+    assert rc == 0 and st.fp32_iterations >= 1
+    _check(H, lam, ritzv, Y, nev)
+
+
+def test_injected_bounds_and_ragged_sizes(ctx):
+    n, nev, nex = 333, 20, 9
+    g = wl.rng(71)
+    lam = wl.spectrum_clustered(n, g, 60)
+    H = wl.hermitian_from(wl.haar_unitary(n, g), lam)
+    V0 = wl.complex_gaussian(g, n, nev + nex)
+    starts = wl.complex_gaussian(g, n, 5)
+    rc, st, ritzv, resid, Y = _gpu_solve(ctx, H, V0, starts, nev=nev, optim=1, have_mu=1,
+                                         mu_1=float(lam[0]), mu_nevnex=float(lam[nev + nex - 1]))
+    assert rc == 0
+    _check(H, lam, ritzv, Y, nev)
+    ref = och.solve(H, och.ChaseParams(nev=nev, nex=nex, optim=True), V0, starts,
+                    mu=(lam[0], lam[nev + nex - 1]))
+    assert np.max(np.abs(ritzv[:nev] - ref["ritzv"][:nev])) <= 1e-10 * np.max(np.abs(lam))
+
+
+def test_warm_start_exact_vectors_one_iteration(ctx):
+    n, nev, nex = 150, 8, 4
+    g = wl.rng(41)
+    lam = wl.spectrum_uniform(n, g)
+    Q = wl.haar_unitary(n, g)
+    H = wl.hermitian_from(Q, lam)
+    rc, st, ritzv, resid, Y = _gpu_solve(ctx, H, Q[:, : nev + nex], wl.complex_gaussian(g, n, 1),
+                                         nev=nev, optim=1, approx=1, ritzv=lam[: nev + nex])
+    assert rc == 0 and st.iterations == 1
+    _check(H, lam, ritzv, Y, nev)
+
+
+def test_max_iter_partial(ctx):
+    from paper_1805_10121_amd import capi
+
+    n, nev, nex = 200, 20, 4
+    g = wl.rng(51)
+    lam = wl.spectrum_uniform(n, g)
+    H = wl.hermitian_from(wl.haar_unitary(n, g), lam)
+    rc, st, ritzv, resid, Y = _gpu_solve(ctx, H, wl.complex_gaussian(g, n, nev + nex),
+                                         wl.complex_gaussian(g, n, 5), nev=nev, optim=1,
+                                         max_iter=1, deg=4)
+    assert rc == capi.CHASE_NOT_CONVERGED and st.nconv < nev and st.iterations == 1
+    assert np.all(np.isfinite(ritzv)) and np.all(np.isfinite(Y))
+
+
+def test_invalid_config(ctx):
+    import torch
+    from paper_1805_10121_amd import capi
+
+    n = 64
+    dH = torch.zeros((n, n), dtype=torch.complex128, device="cuda")
+    dV = torch.zeros((8, n), dtype=torch.complex128, device="cuda")
+    r, s = np.zeros(8), np.zeros(8)
+    for kw in [dict(nev=0, nex=8), dict(nev=60, nex=8), dict(nev=4, nex=4, tol=-1.0),
+               dict(nev=4, nex=4, deg_max=100), dict(nev=4, nex=4, precision=7)]:
+        nev, nex = kw.pop("nev"), kw.pop("nex")
+        cfg = capi.config(n, nev, nex, **kw)
+        with pytest.raises(capi.ChaseError) as ei:
+            ctx.chase_solve(cfg, dH, n, dV, n, r, s)
+        assert ei.value.code == capi.CHASE_EINVAL
+
+
+def test_sequence_resident_state(ctx):
+    import torch
+    from paper_1805_10121_amd import capi
+
+    n, nev, nex = 300, 16, 6
+    g = wl.rng(61)
+    lam = wl.spectrum_clustered(n, g, 60)
+    Hs = wl.sequence(n, lam, 3, 1e-3, 61)
+    cfg = capi.config(n, nev, nex, optim=1, seed=9)
+    seq = capi.Sequence(ctx, cfg)
+    its = []
+    for H in Hs:
+        ritzv, resid = np.zeros(nev + nex), np.zeros(nev + nex)
+        rc, st = seq.chase_seq_solve(capi.to_device(H), n, ritzv, resid)
+        assert rc == 0
+        ptr, ld = seq.chase_seq_vectors()
+        assert ld == n and ptr
+        ev = np.linalg.eigvalsh(H)
+        assert np.max(np.abs(ritzv[:nev] - ev[:nev])) <= 1e-10 * np.max(np.abs(ev))
+        its.append(st.iterations)
+    assert its[-1] <= its[0]
+    seq.close()
+    torch.cuda.synchronize()
+
+
+def test_config2_full_size(ctx):
+    """n = 10000, nev = 500, nex = 100, clustered spectrum, cold start: eigenvalues against the
+    prescribed spectrum, residuals recomputed on a column sample with a fresh product."""
+    import torch
+    from paper_1805_10121_amd import capi
+
+    c = wl.CONFIGS[2]
+    n, nev, nex = c["n"], c["nev"], c["nex"]
+    lam = wl.spectrum_for(2)
+    print("config2: generating H", flush=True)
+    dH = wl.hermitian_torch(n, lam, seed=2001)
+    V0 = wl.start_block(n, nev + nex, 2500)
+    cfg = capi.config(n, nev, nex, optim=1, seed=2600)
+    dV = capi.to_device(V0)
+    ritzv, resid = np.zeros(nev + nex), np.zeros(nev + nex)
+    print("config2: solving", flush=True)
+    rc, st = ctx.chase_solve(cfg, dH, n, dV, n, ritzv, resid)
+    print(f"config2: rc={rc} it={st.iterations} total_ms={st.total_ms:.1f} "
+          f"filter_ms={st.filter_ms:.1f} filter TF/s={st.filter_flops / st.filter_ms / 1e9:.2f}",
+          flush=True)
+    assert rc == 0
+    normH = np.max(np.abs(lam))
+    assert np.max(np.abs(ritzv[:nev] - lam[:nev])) <= 1e-10 * normH
+    Y = capi.from_device(dV[:nev])
+    G = Y.conj().T @ Y
+    assert np.linalg.norm(G - np.eye(nev)) <= 1e-11
+    H = capi.from_device(dH)
+    cols = [0, 99, 100, 250, 499]
+    R = H @ Y[:, cols] - Y[:, cols] * ritzv[None, cols]
+    assert np.max(np.linalg.norm(R, axis=0)) <= 1e-10 * normH
