@@ -144,9 +144,25 @@ int chase_create(chase_ctx** out, int device, void* hip_stream) {
     }
     ctx->own_stream = true;
   }
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
+      cus <= 0) {
+    if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+    return CHASE_EDEVICE;
+  }
+  ctx->prod.cus = cus;
+  ctx->prod.bytes = product_scratch_bytes(cus);
+  if (hipMalloc(&ctx->prod.ptr, ctx->prod.bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+    return CHASE_ENOMEM;
+  }
   if (rocblas_create_handle(&ctx->blas) != rocblas_status_success ||
       rocblas_set_stream(ctx->blas, ctx->stream) != rocblas_status_success) {
     if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+    (void)hipFree(ctx->prod.ptr);
     delete ctx;
     return CHASE_EDEVICE;
   }
@@ -159,6 +175,7 @@ void chase_destroy(chase_ctx* ctx) {
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
   if (ctx->ws) (void)hipFree(ctx->ws);
+  if (ctx->prod.ptr) (void)hipFree(ctx->prod.ptr);
   if (ctx->blas) rocblas_destroy_handle(ctx->blas);
   if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
@@ -183,11 +200,11 @@ int chase_filter(chase_ctx* ctx, int precision, const void* H, int64_t ldh, int6
   if (precision == CHASE_FP64)
     e = run_filter<double>(static_cast<const double*>(H), ldh, n, static_cast<double*>(V),
                            static_cast<double*>(W), ld, ncols, degrees, b_sup, mu_1, mu_nevnex,
-                           ctx->stream, nullptr);
+                           ctx->prod, ctx->stream, nullptr);
   else
     e = run_filter<float>(static_cast<const float*>(H), ldh, n, static_cast<float*>(V),
                           static_cast<float*>(W), ld, ncols, degrees, b_sup, mu_1, mu_nevnex,
-                          ctx->stream, nullptr);
+                          ctx->prod, ctx->stream, nullptr);
   if (e != hipSuccess)
     return set_error(ctx, CHASE_EDEVICE, std::string("filter launch: ") + hipGetErrorString(e));
   return CHASE_OK;
@@ -208,12 +225,12 @@ int chase_hemm_step(chase_ctx* ctx, int precision, const void* H, int64_t ldh, i
   if (precision == CHASE_FP64)
     e = launch_hemm_step<double>(static_cast<const double*>(H), ldh, n,
                                  static_cast<const double*>(X), ldx, static_cast<double*>(OUT),
-                                 ldo, ncols, alpha, beta, gamma, ctx->stream);
+                                 ldo, ncols, alpha, beta, gamma, ctx->prod, ctx->stream);
   else
     e = launch_hemm_step<float>(static_cast<const float*>(H), ldh, n,
                                 static_cast<const float*>(X), ldx, static_cast<float*>(OUT), ldo,
                                 ncols, static_cast<float>(alpha), static_cast<float>(beta),
-                                static_cast<float>(gamma), ctx->stream);
+                                static_cast<float>(gamma), ctx->prod, ctx->stream);
   if (e != hipSuccess)
     return set_error(ctx, CHASE_EDEVICE, std::string("product launch: ") + hipGetErrorString(e));
   return CHASE_OK;

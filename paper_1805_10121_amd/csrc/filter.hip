@@ -14,7 +14,7 @@ namespace chase {
 template <typename T>
 hipError_t run_filter(const T* H, int64_t ldh, int64_t n, T* V, T* W, int64_t ld, int64_t ncols,
                       const int32_t* degrees, double b_sup, double mu_1, double mu_nevnex,
-                      hipStream_t stream, int64_t* matvecs_out) {
+                      const ProductScratch& ps, hipStream_t stream, int64_t* matvecs_out) {
   int64_t matvecs = 0;
   if (ncols <= 0 || n <= 0) {
     if (matvecs_out) *matvecs_out = 0;
@@ -28,7 +28,7 @@ hipError_t run_filter(const T* H, int64_t ldh, int64_t n, T* V, T* W, int64_t ld
   // product 1, every column: W <- a1 H V + g1 V
   double alpha = sigma1 / e;
   hipError_t err = launch_hemm_step<T>(H, ldh, n, V, ld, W, ld, ncols, static_cast<T>(alpha),
-                                       T(0), static_cast<T>(-alpha * c), stream);
+                                       T(0), static_cast<T>(-alpha * c), ps, stream);
   if (err != hipSuccess) return err;
   matvecs += ncols;
 
@@ -45,7 +45,7 @@ hipError_t run_filter(const T* H, int64_t ldh, int64_t n, T* V, T* W, int64_t ld
     const int64_t act = ncols - s;
     err = launch_hemm_step<T>(H, ldh, n, cur_in + 2 * s * ld, ld, cur_out + 2 * s * ld, ld, act,
                               static_cast<T>(alpha), static_cast<T>(beta),
-                              static_cast<T>(gamma), stream);
+                              static_cast<T>(gamma), ps, stream);
     if (err != hipSuccess) return err;
     matvecs += act;
     T* tmp = cur_in;
@@ -61,9 +61,9 @@ hipError_t run_filter(const T* H, int64_t ldh, int64_t n, T* V, T* W, int64_t ld
 
 template hipError_t run_filter<double>(const double*, int64_t, int64_t, double*, double*, int64_t,
                                        int64_t, const int32_t*, double, double, double,
-                                       hipStream_t, int64_t*);
+                                       const ProductScratch&, hipStream_t, int64_t*);
 template hipError_t run_filter<float>(const float*, int64_t, int64_t, float*, float*, int64_t,
                                       int64_t, const int32_t*, double, double, double,
-                                      hipStream_t, int64_t*);
+                                      const ProductScratch&, hipStream_t, int64_t*);
 
 }  // namespace chase

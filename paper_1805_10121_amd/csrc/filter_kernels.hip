@@ -13,9 +13,9 @@
 // and the epilogue combines Re(HX) = ReH ReX - ImH ImX, Im(HX) = ReH ImX + ImH ReX.
 // Exactly 8 n^2 ncols real flops; H is read in place, never reformatted.
 //
-// Tiling: 256 threads (4 waves of 64) own a 64 x 64 complex output tile (128 x 128 real); each
-// wave owns 32 x 32 complex = 4 x 4 MFMA 16x16 tiles.  K advances 16 at a time through a
-// double-buffered LDS stage fed by a register prefetch of the next stage.
+// Tiling: 256 threads (4 waves of 64) own a BMC x BNC complex output tile; each wave owns a
+// sub-tile of 16x16 MFMA tiles.  K advances KT at a time through a double-buffered LDS stage
+// fed by a register prefetch of the next stage.
 //
 // MFMA lane layouts used (16x16x4, checked on gfx950): A operand lane l holds A[l%16][l/16],
 // B operand lane l holds B[l/16][l%16].  The accumulator's register r of lane l holds column
@@ -25,6 +25,7 @@
 
 #include "internal.h"
 
+#include <algorithm>
 #include <type_traits>
 
 namespace chase {
@@ -58,37 +59,53 @@ template <> __device__ __forceinline__ int c_row<double>(int g, int p) { return 
 template <> __device__ __forceinline__ int c_row<float>(int g, int p) { return 2 * g + p; }
 
 constexpr int kThreads = 256;
-constexpr int BMC = 64;   // complex rows per workgroup tile
-constexpr int BNC = 64;   // complex columns per workgroup tile
-constexpr int KT = 16;    // K per LDS stage
 
-template <typename T>
-__global__ __launch_bounds__(kThreads, 2) void hemm_step_kernel(
-    const T* __restrict__ H, int64_t ldh, int n, const T* __restrict__ X, int64_t ldx,
-    T* __restrict__ OUT, int64_t ldo, int ncols, T alpha, T beta, T gamma, int tiles_m) {
+// Workgroup tile: BMC complex rows x BNC complex columns, K staged KT at a time; the four
+// waves form a WR x WC grid, each owning (BMC/WR) x (BNC/WC) complex outputs, i.e. RT row
+// slabs of 8 complex (16 real) rows times CG column groups of 16, each group an (Re X, Im X)
+// pair of MFMA tiles.
+template <typename T, int BMC_, int BNC_, int KT_, int WR_, int WC_>
+struct Tile {
+  static constexpr int BMC = BMC_, BNC = BNC_, KT = KT_, WR = WR_, WC = WC_;
+  static constexpr int RT = BMC / WR / 8;
+  static constexpr int CG = BNC / WC / 16;
+  static constexpr int AR = 2 * BMC + 2;  // padded real rows per A stage row (k fixed)
+  static constexpr int BR = 2 * BNC + 2;  // padded real columns per B stage row (k fixed)
+  static constexpr int A_PER = BMC * KT / kThreads;
+  static constexpr int B_PER = BNC * KT / kThreads;
+  static_assert(WR * WC == 4, "four waves");
+  static_assert(RT >= 1 && CG >= 1, "wave tile too small");
+  static_assert(A_PER * kThreads == BMC * KT && B_PER * kThreads == BNC * KT, "load split");
   using acc_t = typename Acc<T>::type;
   using v2 = typename Acc<T>::v2;
-  constexpr int AR = 2 * BMC + 2;  // padded real rows per A stage row (k fixed)
-  constexpr int BR = 2 * BNC + 2;  // padded real columns per B stage row (k fixed)
-  __shared__ T As[2][KT][AR];
-  __shared__ T Bs[2][KT][BR];
+  struct Smem {
+    T As[2][KT][AR];
+    T Bs[2][KT][BR];
+  };
+  struct Frag {
+    acc_t acc[RT][CG][2];
+  };
+};
 
+// acc <- R[i0.., k] [Re X | Im X][k, j0..] summed over the K stages ka <= kt < kb.
+template <typename T, class C>
+__device__ __forceinline__ void tile_mainloop(typename C::Smem& sm, typename C::Frag& f,
+                                              const T* __restrict__ H, int64_t ldh, int n,
+                                              const T* __restrict__ X, int64_t ldx, int ncols,
+                                              int i0, int j0, int ka, int kb) {
+  using v2 = typename C::v2;
+  using acc_t = typename C::acc_t;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, li = lane & 15;
-  const int wr = wave >> 1, wc = wave & 1;
-  const int tile_m = blockIdx.x % tiles_m, tile_n = blockIdx.x / tiles_m;
-  const int i0 = tile_m * BMC, j0 = tile_n * BNC;
-
-  constexpr int A_PER = BMC * KT / kThreads;
-  constexpr int B_PER = BNC * KT / kThreads;
-  v2 ra[A_PER], rb[B_PER];
+  const int wr = wave / C::WC, wc = wave % C::WC;
+  v2 ra[C::A_PER], rb[C::B_PER];
 
   auto load_tiles = [&](int k0) {
 #pragma unroll
-    for (int q = 0; q < A_PER; ++q) {
+    for (int q = 0; q < C::A_PER; ++q) {
       const int idx = tid + kThreads * q;
-      const int kk = idx / BMC, ci = idx % BMC;
+      const int kk = idx / C::BMC, ci = idx % C::BMC;
       const int row = i0 + ci, col = k0 + kk;
       if (row < n && col < n)
         ra[q] = *reinterpret_cast<const v2*>(H + 2 * (static_cast<int64_t>(row) +
@@ -97,9 +114,9 @@ __global__ __launch_bounds__(kThreads, 2) void hemm_step_kernel(
         ra[q] = v2{T(0), T(0)};
     }
 #pragma unroll
-    for (int q = 0; q < B_PER; ++q) {
+    for (int q = 0; q < C::B_PER; ++q) {
       const int idx = tid + kThreads * q;
-      const int jj = idx / KT, kk = idx % KT;
+      const int jj = idx / C::KT, kk = idx % C::KT;
       const int row = k0 + kk, col = j0 + jj;
       if (row < n && col < ncols)
         rb[q] = *reinterpret_cast<const v2*>(X + 2 * (static_cast<int64_t>(row) +
@@ -110,83 +127,236 @@ __global__ __launch_bounds__(kThreads, 2) void hemm_step_kernel(
   };
   auto store_tiles = [&](int buf) {
 #pragma unroll
-    for (int q = 0; q < A_PER; ++q) {
+    for (int q = 0; q < C::A_PER; ++q) {
       const int idx = tid + kThreads * q;
-      const int kk = idx / BMC, ci = idx % BMC;
-      *reinterpret_cast<v2*>(&As[buf][kk][2 * ci]) = ra[q];
+      const int kk = idx / C::BMC, ci = idx % C::BMC;
+      *reinterpret_cast<v2*>(&sm.As[buf][kk][2 * ci]) = ra[q];
     }
 #pragma unroll
-    for (int q = 0; q < B_PER; ++q) {
+    for (int q = 0; q < C::B_PER; ++q) {
       const int idx = tid + kThreads * q;
-      const int jj = idx / KT, kk = idx % KT;
-      Bs[buf][kk][jj] = rb[q].x;
-      Bs[buf][kk][BNC + jj] = rb[q].y;
+      const int jj = idx / C::KT, kk = idx % C::KT;
+      sm.Bs[buf][kk][jj] = rb[q].x;
+      sm.Bs[buf][kk][C::BNC + jj] = rb[q].y;
     }
   };
 
-  acc_t acc[4][2][2];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < C::RT; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+    for (int b = 0; b < C::CG; ++b)
 #pragma unroll
-      for (int c = 0; c < 2; ++c) acc[a][b][c] = acc_t{0};
+      for (int c = 0; c < 2; ++c) f.acc[a][b][c] = acc_t{0};
 
   const int arow = a_row<T>(li);
-  const int nk = (n + KT - 1) / KT;
-  load_tiles(0);
+  const int rbase = wr * (C::BMC / C::WR) * 2;  // first real row of this wave in the A stage
+  const int cbase = wc * (C::BNC / C::WC);      // first complex column of this wave
+  load_tiles(ka * C::KT);
   store_tiles(0);
   __syncthreads();
-  for (int kt = 0; kt < nk; ++kt) {
-    const int cur = kt & 1;
-    if (kt + 1 < nk) load_tiles((kt + 1) * KT);
+  for (int kt = ka; kt < kb; ++kt) {
+    const int cur = (kt - ka) & 1;
+    if (kt + 1 < kb) load_tiles((kt + 1) * C::KT);
 #pragma unroll
-    for (int s = 0; s < KT / 4; ++s) {
+    for (int s = 0; s < C::KT / 4; ++s) {
       const int k = 4 * s + g;
-      T a[4], b[2][2];
+      T a[C::RT], b[C::CG][2];
 #pragma unroll
-      for (int rt = 0; rt < 4; ++rt) a[rt] = As[cur][k][wr * 64 + rt * 16 + arow];
+      for (int rt = 0; rt < C::RT; ++rt) a[rt] = sm.As[cur][k][rbase + rt * 16 + arow];
 #pragma unroll
-      for (int cg = 0; cg < 2; ++cg) {
-        b[cg][0] = Bs[cur][k][wc * 32 + cg * 16 + li];
-        b[cg][1] = Bs[cur][k][BNC + wc * 32 + cg * 16 + li];
+      for (int cg = 0; cg < C::CG; ++cg) {
+        b[cg][0] = sm.Bs[cur][k][cbase + cg * 16 + li];
+        b[cg][1] = sm.Bs[cur][k][C::BNC + cbase + cg * 16 + li];
       }
 #pragma unroll
-      for (int rt = 0; rt < 4; ++rt)
+      for (int rt = 0; rt < C::RT; ++rt)
 #pragma unroll
-        for (int cg = 0; cg < 2; ++cg)
+        for (int cg = 0; cg < C::CG; ++cg)
 #pragma unroll
-          for (int p = 0; p < 2; ++p) acc[rt][cg][p] = mfma(a[rt], b[cg][p], acc[rt][cg][p]);
+          for (int p = 0; p < 2; ++p)
+            f.acc[rt][cg][p] = mfma(a[rt], b[cg][p], f.acc[rt][cg][p]);
     }
-    if (kt + 1 < nk) store_tiles(cur ^ 1);
+    if (kt + 1 < kb) store_tiles(cur ^ 1);
     __syncthreads();
   }
+}
 
-  // Epilogue: complex combine, then alpha*HX + gamma*X + beta*OUT.
+// Visit the complex results held by this lane: fn(row_in_tile, col_in_tile, re, im).
+template <typename T, class C, typename Fn>
+__device__ __forceinline__ void tile_foreach(const typename C::Frag& f, Fn&& fn) {
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 4, li = lane & 15;
+  const int wr = wave / C::WC, wc = wave % C::WC;
 #pragma unroll
-  for (int rt = 0; rt < 4; ++rt)
+  for (int rt = 0; rt < C::RT; ++rt)
 #pragma unroll
-    for (int cg = 0; cg < 2; ++cg)
+    for (int cg = 0; cg < C::CG; ++cg)
 #pragma unroll
       for (int p = 0; p < 2; ++p) {
-        const int row = i0 + wr * 32 + rt * 8 + c_row<T>(g, p);
-        const int col = j0 + wc * 32 + cg * 16 + li;
-        if (row < n && col < ncols) {
-          const T hre = acc[rt][cg][0][2 * p] - acc[rt][cg][1][2 * p + 1];
-          const T him = acc[rt][cg][1][2 * p] + acc[rt][cg][0][2 * p + 1];
-          const v2 x = *reinterpret_cast<const v2*>(
-              X + 2 * (static_cast<int64_t>(row) + static_cast<int64_t>(col) * ldx));
-          T* o = OUT + 2 * (static_cast<int64_t>(row) + static_cast<int64_t>(col) * ldo);
-          T ore = alpha * hre + gamma * x.x;
-          T oim = alpha * him + gamma * x.y;
-          if (beta != T(0)) {
-            const v2 y = *reinterpret_cast<const v2*>(o);
-            ore += beta * y.x;
-            oim += beta * y.y;
-          }
-          *reinterpret_cast<v2*>(o) = v2{ore, oim};
-        }
+        const int r = wr * (C::BMC / C::WR) + rt * 8 + c_row<T>(g, p);
+        const int c = wc * (C::BNC / C::WC) + cg * 16 + li;
+        const T hre = f.acc[rt][cg][0][2 * p] - f.acc[rt][cg][1][2 * p + 1];
+        const T him = f.acc[rt][cg][1][2 * p] + f.acc[rt][cg][0][2 * p + 1];
+        fn(r, c, hre, him);
       }
+}
+
+// OUT <- alpha*HX + gamma*X + beta*OUT at (row, col); OUT is not read when beta == 0.
+template <typename T>
+__device__ __forceinline__ void epilogue_store(const T* __restrict__ X, int64_t ldx,
+                                               T* __restrict__ OUT, int64_t ldo, int row, int col,
+                                               T hre, T him, T alpha, T beta, T gamma) {
+  using v2 = typename Acc<T>::v2;
+  const v2 x = *reinterpret_cast<const v2*>(
+      X + 2 * (static_cast<int64_t>(row) + static_cast<int64_t>(col) * ldx));
+  T* o = OUT + 2 * (static_cast<int64_t>(row) + static_cast<int64_t>(col) * ldo);
+  T ore = alpha * hre + gamma * x.x;
+  T oim = alpha * him + gamma * x.y;
+  if (beta != T(0)) {
+    const v2 y = *reinterpret_cast<const v2*>(o);
+    ore += beta * y.x;
+    oim += beta * y.y;
+  }
+  *reinterpret_cast<v2*>(o) = v2{ore, oim};
+}
+
+// Data-parallel schedule: one workgroup per output tile (row tiles vary fastest).
+template <typename T, class C, int OCC>
+__global__ __launch_bounds__(kThreads, OCC) void hemm_dp_kernel(
+    const T* __restrict__ H, int64_t ldh, int n, const T* __restrict__ X, int64_t ldx,
+    T* __restrict__ OUT, int64_t ldo, int ncols, T alpha, T beta, T gamma, int tiles_m) {
+  __shared__ typename C::Smem sm;
+  typename C::Frag f;
+  const int tile_m = static_cast<int>(blockIdx.x) % tiles_m;
+  const int tile_n = static_cast<int>(blockIdx.x) / tiles_m;
+  const int i0 = tile_m * C::BMC, j0 = tile_n * C::BNC;
+  const int nk = (n + C::KT - 1) / C::KT;
+  tile_mainloop<T, C>(sm, f, H, ldh, n, X, ldx, ncols, i0, j0, 0, nk);
+  tile_foreach<T, C>(f, [&](int r, int c, T hre, T him) {
+    if (i0 + r < n && j0 + c < ncols)
+      epilogue_store<T>(X, ldx, OUT, ldo, i0 + r, j0 + c, hre, him, alpha, beta, gamma);
+  });
+}
+
+// Stream-K schedule.  The work units (tile, K stage) are numbered tile-major,
+// u = t * nk + kt, and persistent workgroup p owns [u0(p), u1(p)) with u0(p) = floor(p U / P).
+// A tile whose K range is covered by one workgroup is finished in place; otherwise each
+// contributor writes its partial sum H X (before the epilogue) to its own slot -- slot 0 for
+// the segment in the tile containing u0(p), slot 1 for the segment in the tile containing
+// u1(p) - 1 -- and hemm_fixup_kernel adds the slots in increasing p, so the result does not
+// depend on timing.
+__device__ __forceinline__ int64_t sk_start(int64_t p, int64_t units, int64_t P) {
+  return p * units / P;
+}
+__device__ __forceinline__ int64_t sk_owner(int64_t u, int64_t units, int64_t P) {
+  return ((u + 1) * P - 1) / units;  // max p with sk_start(p) <= u
+}
+
+template <typename T, class C, int OCC>
+__global__ __launch_bounds__(kThreads, OCC) void hemm_sk_kernel(
+    const T* __restrict__ H, int64_t ldh, int n, const T* __restrict__ X, int64_t ldx,
+    T* __restrict__ OUT, int64_t ldo, int ncols, T alpha, T beta, T gamma, int tiles_m,
+    int nk, int64_t units, T* __restrict__ partial) {
+  __shared__ typename C::Smem sm;
+  typename C::Frag f;
+  const int64_t P = gridDim.x, p = blockIdx.x;
+  const int64_t u0 = sk_start(p, units, P), u1 = sk_start(p + 1, units, P);
+  const int64_t t_first = u0 / nk;
+  constexpr int TE = C::BMC * C::BNC;  // complex elements per tile
+  int64_t u = u0;
+  while (u < u1) {
+    const int64_t t = u / nk;
+    const int ka = static_cast<int>(u - t * nk);
+    const int kb = static_cast<int>(min(static_cast<int64_t>(nk), ka + (u1 - u)));
+    const int tile_m = static_cast<int>(t % tiles_m), tile_n = static_cast<int>(t / tiles_m);
+    const int i0 = tile_m * C::BMC, j0 = tile_n * C::BNC;
+    tile_mainloop<T, C>(sm, f, H, ldh, n, X, ldx, ncols, i0, j0, ka, kb);
+    if (ka == 0 && kb == nk) {
+      tile_foreach<T, C>(f, [&](int r, int c, T hre, T him) {
+        if (i0 + r < n && j0 + c < ncols)
+          epilogue_store<T>(X, ldx, OUT, ldo, i0 + r, j0 + c, hre, him, alpha, beta, gamma);
+      });
+    } else {
+      T* dst = partial + 2 * (p * 2 + (t == t_first ? 0 : 1)) * TE;
+      tile_foreach<T, C>(f, [&](int r, int c, T hre, T him) {
+        dst[2 * (r + c * C::BMC)] = hre;
+        dst[2 * (r + c * C::BMC) + 1] = him;
+      });
+    }
+    u = t * nk + kb;
+  }
+}
+
+// One workgroup per boundary p (grid = P); it completes the split tile that contains u0(p)
+// when p is the first workgroup whose range starts inside that tile.
+template <typename T, class C>
+__global__ __launch_bounds__(kThreads) void hemm_fixup_kernel(
+    const T* __restrict__ X, int64_t ldx, T* __restrict__ OUT, int64_t ldo, int n, int ncols,
+    T alpha, T beta, T gamma, int tiles_m, int nk, int64_t units, int64_t P,
+    const T* __restrict__ partial) {
+  const int64_t q = blockIdx.x;
+  if (q == 0) return;
+  const int64_t uq = sk_start(q, units, P);
+  if (uq >= units || uq % nk == 0) return;
+  const int64_t t = uq / nk;
+  if (sk_start(q - 1, units, P) > t * nk) return;  // an earlier boundary handles this tile
+  const int64_t pf = sk_owner(t * nk, units, P), pl = sk_owner((t + 1) * nk - 1, units, P);
+  const int tile_m = static_cast<int>(t % tiles_m), tile_n = static_cast<int>(t / tiles_m);
+  const int i0 = tile_m * C::BMC, j0 = tile_n * C::BNC;
+  constexpr int TE = C::BMC * C::BNC;
+  for (int e = threadIdx.x; e < TE; e += kThreads) {
+    const int r = e % C::BMC, c = e / C::BMC;
+    T hre = T(0), him = T(0);
+    for (int64_t p = pf; p <= pl; ++p) {
+      const int64_t a = sk_start(p, units, P), b = sk_start(p + 1, units, P);
+      if (a >= b) continue;  // empty range
+      const T* src = partial + 2 * (p * 2 + (a / nk == t ? 0 : 1)) * TE;
+      hre += src[2 * e];
+      him += src[2 * e + 1];
+    }
+    if (i0 + r < n && j0 + c < ncols)
+      epilogue_store<T>(X, ldx, OUT, ldo, i0 + r, j0 + c, hre, him, alpha, beta, gamma);
+  }
+}
+
+template <typename T, class C, int OCC>
+hipError_t launch_dp(const T* H, int64_t ldh, int64_t n, const T* X, int64_t ldx, T* OUT,
+                     int64_t ldo, int64_t ncols, T alpha, T beta, T gamma, hipStream_t stream) {
+  const int tiles_m = static_cast<int>((n + C::BMC - 1) / C::BMC);
+  const int tiles_n = static_cast<int>((ncols + C::BNC - 1) / C::BNC);
+  const int64_t blocks = static_cast<int64_t>(tiles_m) * tiles_n;
+  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((hemm_dp_kernel<T, C, OCC>), dim3(static_cast<unsigned>(blocks)),
+                     dim3(kThreads), 0, stream, H, ldh, static_cast<int>(n), X, ldx, OUT, ldo,
+                     static_cast<int>(ncols), alpha, beta, gamma, tiles_m);
+  return hipGetLastError();
+}
+
+// Bytes of partial-sum scratch the stream-K schedule needs for P persistent workgroups.
+template <typename T, class C>
+constexpr size_t sk_scratch_bytes(int64_t P) {
+  return static_cast<size_t>(P) * 2 * C::BMC * C::BNC * 2 * sizeof(T);
+}
+
+template <typename T, class C, int OCC>
+hipError_t launch_sk(const T* H, int64_t ldh, int64_t n, const T* X, int64_t ldx, T* OUT,
+                     int64_t ldo, int64_t ncols, T alpha, T beta, T gamma, int64_t P, T* partial,
+                     hipStream_t stream) {
+  const int tiles_m = static_cast<int>((n + C::BMC - 1) / C::BMC);
+  const int tiles_n = static_cast<int>((ncols + C::BNC - 1) / C::BNC);
+  const int nk = static_cast<int>((n + C::KT - 1) / C::KT);
+  const int64_t units = static_cast<int64_t>(tiles_m) * tiles_n * nk;
+  if (P > units) P = units;
+  hipLaunchKernelGGL((hemm_sk_kernel<T, C, OCC>), dim3(static_cast<unsigned>(P)), dim3(kThreads), 0,
+                     stream, H, ldh, static_cast<int>(n), X, ldx, OUT, ldo,
+                     static_cast<int>(ncols), alpha, beta, gamma, tiles_m, nk, units, partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((hemm_fixup_kernel<T, C>), dim3(static_cast<unsigned>(P)), dim3(kThreads), 0,
+                     stream, X, ldx, OUT, ldo, static_cast<int>(n), static_cast<int>(ncols), alpha,
+                     beta, gamma, tiles_m, nk, units, P, partial);
+  return hipGetLastError();
 }
 
 template <typename S, typename D>
@@ -205,27 +375,54 @@ __global__ void convert_kernel(const S* __restrict__ src, int64_t lds, D* __rest
 
 }  // namespace
 
+namespace {
+// Tile shapes (complex rows x complex columns, K stage, wave grid).  Both precisions use the
+// same wide tile; columns <= 32 use the narrow one.
+template <typename T> using WideTile = Tile<T, 64, 64, 16, 2, 2>;
+template <typename T> using NarrowTile = Tile<T, 64, 32, 16, 4, 1>;
+constexpr int kOcc = 2;  // workgroups per CU the tiles are built for
+
+template <typename T, class C>
+hipError_t launch_sched(const T* H, int64_t ldh, int64_t n, const T* X, int64_t ldx, T* OUT,
+                        int64_t ldo, int64_t ncols, T alpha, T beta, T gamma,
+                        const ProductScratch& ps, hipStream_t stream) {
+  const int64_t tiles = ((n + C::BMC - 1) / C::BMC) * ((ncols + C::BNC - 1) / C::BNC);
+  const int64_t slots = static_cast<int64_t>(ps.cus) * kOcc;
+  const int64_t rounds = (tiles + slots - 1) / slots;
+  const double eff = static_cast<double>(tiles) / static_cast<double>(rounds * slots);
+  if (eff >= 0.92 || !ps.ptr || sk_scratch_bytes<T, C>(slots) > ps.bytes)
+    return launch_dp<T, C, kOcc>(H, ldh, n, X, ldx, OUT, ldo, ncols, alpha, beta, gamma, stream);
+  return launch_sk<T, C, kOcc>(H, ldh, n, X, ldx, OUT, ldo, ncols, alpha, beta, gamma, slots,
+                               static_cast<T*>(ps.ptr), stream);
+}
+}  // namespace
+
+size_t product_scratch_bytes(int cus) {
+  const int64_t slots = static_cast<int64_t>(cus) * kOcc;
+  size_t b = sk_scratch_bytes<double, WideTile<double>>(slots);
+  b = std::max(b, sk_scratch_bytes<float, WideTile<float>>(slots));
+  b = std::max(b, sk_scratch_bytes<double, NarrowTile<double>>(slots));
+  return b;
+}
+
 template <typename T>
 hipError_t launch_hemm_step(const T* H, int64_t ldh, int64_t n, const T* X, int64_t ldx, T* OUT,
                             int64_t ldo, int64_t ncols, T alpha, T beta, T gamma,
-                            hipStream_t stream) {
+                            const ProductScratch& ps, hipStream_t stream) {
   if (n <= 0 || ncols <= 0) return hipSuccess;
-  const int tiles_m = static_cast<int>((n + BMC - 1) / BMC);
-  const int tiles_n = static_cast<int>((ncols + BNC - 1) / BNC);
-  const int64_t blocks = static_cast<int64_t>(tiles_m) * tiles_n;
-  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(hemm_step_kernel<T>, dim3(static_cast<unsigned>(blocks)), dim3(kThreads), 0,
-                     stream, H, ldh, static_cast<int>(n), X, ldx, OUT, ldo,
-                     static_cast<int>(ncols), alpha, beta, gamma, tiles_m);
-  return hipGetLastError();
+  if (ncols <= 32)
+    return launch_sched<T, NarrowTile<T>>(H, ldh, n, X, ldx, OUT, ldo, ncols, alpha, beta, gamma,
+                                          ps, stream);
+  return launch_sched<T, WideTile<T>>(H, ldh, n, X, ldx, OUT, ldo, ncols, alpha, beta, gamma, ps,
+                                      stream);
 }
 
 template hipError_t launch_hemm_step<double>(const double*, int64_t, int64_t, const double*,
                                              int64_t, double*, int64_t, int64_t, double, double,
-                                             double, hipStream_t);
+                                             double, const ProductScratch&, hipStream_t);
 template hipError_t launch_hemm_step<float>(const float*, int64_t, int64_t, const float*, int64_t,
                                             float*, int64_t, int64_t, float, float, float,
-                                            hipStream_t);
+                                            const ProductScratch&, hipStream_t);
 
 static unsigned convert_blocks(int64_t total) {
   int64_t b = (total + 255) / 256;

@@ -12,6 +12,14 @@
 
 namespace chase {
 
+// Partial-sum scratch of the stream-K product schedule (owned by the context, fixed size).
+struct ProductScratch {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+  int cus = 0;  // compute units of the device
+};
+size_t product_scratch_bytes(int cus);
+
 // ----------------------------------------------------------------------------- kernels
 // One fused complex product  OUT <- alpha*H*X + gamma*X + beta*OUT  on ncols columns.
 // T = double (complex128 data) or float (complex64 data); pointers address interleaved
@@ -19,7 +27,7 @@ namespace chase {
 template <typename T>
 hipError_t launch_hemm_step(const T* H, int64_t ldh, int64_t n, const T* X, int64_t ldx, T* OUT,
                             int64_t ldo, int64_t ncols, T alpha, T beta, T gamma,
-                            hipStream_t stream);
+                            const ProductScratch& ps, hipStream_t stream);
 
 hipError_t launch_convert_c128_to_c64(const double* src, int64_t lds, float* dst, int64_t ldd,
                                       int64_t rows, int64_t cols, hipStream_t stream);
@@ -46,7 +54,7 @@ hipError_t launch_gaussian(double* X, int64_t n, int64_t ld, int64_t cols, uint6
 template <typename T>
 hipError_t run_filter(const T* H, int64_t ldh, int64_t n, T* V, T* W, int64_t ld, int64_t ncols,
                       const int32_t* degrees, double b_sup, double mu_1, double mu_nevnex,
-                      hipStream_t stream, int64_t* matvecs_out);
+                      const ProductScratch& ps, hipStream_t stream, int64_t* matvecs_out);
 
 }  // namespace chase
 
@@ -55,6 +63,7 @@ struct chase_ctx {
   hipStream_t stream = nullptr;
   bool own_stream = false;
   rocblas_handle blas = nullptr;
+  chase::ProductScratch prod;
   std::string last_error;
   // device workspace, grown monotonically
   void* ws = nullptr;

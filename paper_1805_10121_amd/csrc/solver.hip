@@ -286,7 +286,7 @@ int Solver::lanczos(const double* H, int64_t ldh, double* V) {
     double* Uj = U + 2 * static_cast<int64_t>(j) * nv * n_;
     const double* Up = j > 0 ? U + 2 * static_cast<int64_t>(j - 1) * nv * n_ : Uj;
     const double* bp = j > 0 ? at<double>(L_.lbe) + (j - 1) * nv : at<double>(L_.zero);
-    if ((rc = hip(launch_hemm_step<double>(H, ldh, n_, Uj, n_, Wl, n_, nv, 1.0, 0.0, 0.0, s_),
+    if ((rc = hip(launch_hemm_step<double>(H, ldh, n_, Uj, n_, Wl, n_, nv, 1.0, 0.0, 0.0, ctx_->prod, s_),
                   "lanczos product")))
       return rc;
     if ((rc = hip(launch_lanczos_step(Uj, Up, Wl, Uj + 2 * nv * n_, n_, n_, nv, bp,
@@ -454,7 +454,7 @@ int Solver::filter(const double* H, int64_t ldh, int64_t nlock, int64_t nact,
     if ((rc = hip(launch_convert_c128_to_c64(col(L_.V, nlock), n_, V32, n_, n_, n32, s_), "cvt")))
       return rc;
     if ((rc = hip(run_filter<float>(at<float>(L_.H32), n_, n_, V32, at<float>(L_.W32), n_, n32,
-                                    m.data(), b_sup_, mu_1_, mu_b_, s_, &mv),
+                                    m.data(), b_sup_, mu_1_, mu_b_, ctx_->prod, s_, &mv),
                   "filter fp32")))
       return rc;
     st_.filter_matvecs += mv;
@@ -463,7 +463,7 @@ int Solver::filter(const double* H, int64_t ldh, int64_t nlock, int64_t nact,
   }
   if (nact - n32 > 0) {
     if ((rc = hip(run_filter<double>(H, ldh, n_, col(L_.V, nlock + n32), col(L_.W, nlock + n32),
-                                     n_, nact - n32, m.data() + n32, b_sup_, mu_1_, mu_b_, s_, &mv),
+                                     n_, nact - n32, m.data() + n32, b_sup_, mu_1_, mu_b_, ctx_->prod, s_, &mv),
                   "filter fp64")))
       return rc;
     st_.filter_matvecs += mv;
@@ -562,7 +562,7 @@ int Solver::run(const void* Hv, int64_t ldh, void* Vuser, int64_t ldv, double* r
     double* Q = col(L_.V, nlock);
     double* AQ = at<double>(L_.AQ);
     double* G = at<double>(L_.G);
-    if ((rc = hip(launch_hemm_step<double>(H, ldh, n_, Q, n_, AQ, n_, nact, 1.0, 0.0, 0.0, s_),
+    if ((rc = hip(launch_hemm_step<double>(H, ldh, n_, Q, n_, AQ, n_, nact, 1.0, 0.0, 0.0, ctx_->prod, s_),
                   "H Q")))
       return rc;
     st_.matvecs += nact;
