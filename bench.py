@@ -76,6 +76,95 @@ def cpu_baseline(H_host, V_host, deg, b_sup, mu_1, mu_b, budget_s=15.0):
     }
 
 
+def make_sequence_problem(n, lam, k, eps, seed, prev=None, norm=None):
+    """H_1 (k = 0) or H_{k+1} = H_k + eps ||H_k|| E_k on the device (E_k Hermitian Gaussian
+    scaled to unit spectral norm by a 40-step power iteration)."""
+    import torch
+
+    from paper_1805_10121_amd import workloads as wl
+
+    if k == 0:
+        return wl.hermitian_torch_fast(n, lam, seed)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(seed + 7919 * k)
+    E = torch.complex(torch.randn((n, n), generator=gen, device="cuda", dtype=torch.float64),
+                      torch.randn((n, n), generator=gen, device="cuda", dtype=torch.float64))
+    E.add_(E.conj().T.clone())
+    E.mul_(0.5)
+    x = torch.randn(n, generator=gen, device="cuda", dtype=torch.float64).to(torch.complex128)
+    for _ in range(40):
+        x = E @ x
+        x /= torch.linalg.vector_norm(x)
+    enorm = float(torch.linalg.vector_norm(E @ x))
+    prev.add_(E, alpha=eps * norm / enorm)
+    del E
+    return prev
+
+
+def run_sequence(args):
+    """Warm-started sequence (order 20000, nev 1000, nex 200, eps 1e-3 by default): total
+    time-to-solution with the plain FP64 filter and with the mixed FP32/FP64 filter."""
+    import numpy as np
+    import torch
+
+    from paper_1805_10121_amd import capi
+    from paper_1805_10121_amd import workloads as wl
+
+    c = wl.CONFIGS[3]
+    n = args.order
+    nev = max(1, round(c["nev"] * n / c["n"]))
+    nex = max(1, round(c["nex"] * n / c["n"]))
+    eps = c["eps"]
+    lam = wl.spectrum_for(3, n=n)
+    norm = float(np.max(np.abs(lam)))
+    ctx = capi.Context(0)
+    res = {}
+    for mode, prec in (("fp64", capi.CHASE_FP64), ("mixed", capi.CHASE_MIXED)):
+        cfg = capi.config(n, nev, nex, optim=1, precision=prec, seed=3000)
+        seq = capi.Sequence(ctx, cfg)
+        H = None
+        per = []
+        for k in range(args.problems):
+            H = make_sequence_problem(n, lam, k, eps, 3001, prev=H, norm=norm)
+            torch.cuda.synchronize()
+            ritzv, resid = np.zeros(nev + nex), np.zeros(nev + nex)
+            t0 = time.perf_counter()
+            rc, st = seq.chase_seq_solve(H, n, ritzv, resid)
+            dt = time.perf_counter() - t0
+            per.append({"k": k + 1, "status": rc, "time_s": round(dt, 4),
+                        "iterations": st.iterations, "fp32_iterations": st.fp32_iterations,
+                        "filter_ms": round(st.filter_ms, 2),
+                        "filter_tflops": round(st.filter_flops / max(st.filter_ms, 1e-9) / 1e9, 2),
+                        "max_resid_over_normH": float(np.max(resid[:nev]) / norm),
+                        "ritz_first": float(ritzv[0]), "ritz_nev": float(ritzv[nev - 1])})
+            if k == 0:
+                per[-1]["max_eig_error_over_normH"] = float(
+                    np.max(np.abs(ritzv[:nev] - lam[:nev])) / norm)
+            per[-1]["ritz"] = ritzv[:nev].copy()
+            log(f"sequence {mode} problem {k + 1}: {dt:.3f} s, {st.iterations} it "
+                f"(fp32 {st.fp32_iterations}), rc={rc}")
+        seq.close()
+        del H
+        torch.cuda.empty_cache()
+        res[mode] = per
+    diffs = [float(np.max(np.abs(a["ritz"] - b["ritz"])) / norm)
+             for a, b in zip(res["fp64"], res["mixed"])]
+    for mode in res:
+        for p in res[mode]:
+            p.pop("ritz")
+    t64 = sum(p["time_s"] for p in res["fp64"])
+    tmx = sum(p["time_s"] for p in res["mixed"])
+    ctx.close()
+    return {
+        "workload": f"sequence n={n} nev={nev} nex={nex} problems={args.problems} eps={eps}, "
+                    "clustered spectrum (600 clustered values), warm-started, tol 1e-10",
+        "fp64_total_s": round(t64, 3), "mixed_total_s": round(tmx, 3),
+        "mixed_speedup": round(t64 / tmx, 3),
+        "max_eig_diff_mixed_vs_fp64_over_normH": max(diffs),
+        "fp64": res["fp64"], "mixed": res["mixed"],
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -84,6 +173,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
+    ap.add_argument("--workload", choices=["filter", "sequence"], default="filter",
+                    help="filter: the hot-path benchmark (default); sequence: time-to-solution of "
+                         "a warm-started sequence, plain FP64 against the mixed FP32/FP64 filter")
+    ap.add_argument("--problems", type=int, default=10)
+    ap.add_argument("--order", type=int, default=20000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy three times (counter calibration)")
     args = ap.parse_args()
@@ -106,6 +200,10 @@ def main():
 
     from paper_1805_10121_amd import capi
     from paper_1805_10121_amd import workloads as wl
+
+    if args.workload == "sequence":
+        print(json.dumps(run_sequence(args)), flush=True)
+        return
 
     cfg = wl.CONFIGS[2]
     n, nb = cfg["n"], cfg["nev"] + cfg["nex"]

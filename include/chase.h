@@ -106,7 +106,9 @@ typedef struct chase_ctx chase_ctx;
 void chase_config_init(chase_config* cfg, int64_t n, int64_t nev, int64_t nex);
 
 /* Create a context on HIP device `device`.  hip_stream: a hipStream_t to order all work on, or
-   NULL for a stream owned by the context.  Allocates no large memory. */
+   NULL for a stream owned by the context.  Allocates a fixed partial-sum scratch for the
+   stream-K schedule of the product kernel (two tile-sized slots per persistent workgroup:
+   64 MiB on a 256-CU device) and a rocBLAS handle; the solver workspace comes later. */
 int chase_create(chase_ctx** out, int device, void* hip_stream);
 void chase_destroy(chase_ctx* ctx);
 
@@ -194,6 +196,47 @@ int chase_seq_solve(chase_seq* seq, const void* H, int64_t ldh, double* ritzv, d
 /* Borrowed device pointer to the current n x (nev+nex) vectors (valid until the next call). */
 int chase_seq_vectors(chase_seq* seq, void** V, int64_t* ldv);
 void chase_seq_destroy(chase_seq* seq);
+
+/*
+ * Serving: continuous batching of solves from many concurrent sequences of uneven order on one
+ * device (the sequence setting of Sec. 2 and Sec. 6.1, served as requests arrive).
+ *
+ * Each request is one problem of a sequence identified by seq_id.  Problems of one sequence run
+ * in submission order; the first is solved cold (cfg->approx as given), every later one is warm
+ * started from the previous solution, which stays in device memory (the sequence state:
+ * n x (nev+nex) complex128 vectors and the Ritz values).  A request is started when its sequence
+ * is idle and the device memory it needs -- the sequence state if new, plus the growth of a
+ * worker's workspace (chase_workspace_bytes) -- fits in mem_budget_bytes beside what is already
+ * held.  Up to `workers` requests run at once, each on its own stream; the products of all
+ * filter calls in flight are grouped into shared launches.  A request's results are bitwise the
+ * same whatever else runs beside it.
+ *
+ * H: device complex128, n x n, ldh >= n, owned by the caller and kept valid and unchanged until
+ * the request's ticket reports done.  n, nev and nex must stay the same within a sequence.
+ * Sequence states are held until chase_server_end_sequence or chase_server_destroy.
+ */
+typedef struct chase_server chase_server;
+/* workers in [1, 64]; mem_budget_bytes > 0.  Creates a batching thread and the workers. */
+int chase_server_create(chase_server** out, int device, size_t mem_budget_bytes, int workers);
+/* Queue one problem.  CHASE_EINVAL on a bad configuration or a size change inside a sequence;
+   CHASE_EBUSY if the request alone needs more than the budget.  *ticket identifies it. */
+int chase_server_submit(chase_server* s, uint64_t seq_id, const chase_config* cfg, const void* H,
+                        int64_t ldh, uint64_t* ticket);
+/* Poll (wait = 0) or wait (wait != 0) for a ticket.  When *done is set, ritzv / resid (host,
+   nev+nex doubles), stats and latency_s (seconds from submit to completion) are filled (any may
+   be NULL), the ticket is released, and the return value is the solve's chase_status. */
+int chase_server_poll(chase_server* s, uint64_t ticket, int wait, int* done, double* ritzv,
+                      double* resid, chase_stats* stats, double* latency_s);
+/* Borrowed device pointer to an idle sequence's current vectors (CHASE_EINVAL if busy/unknown). */
+int chase_server_vectors(chase_server* s, uint64_t seq_id, void** V, int64_t* ldv);
+/* Release an idle sequence's state.  CHASE_EBUSY while it runs or has queued requests. */
+int chase_server_end_sequence(chase_server* s, uint64_t seq_id);
+/* Counters: grouped launches and products issued by the batcher, bytes admitted. */
+int chase_server_info(chase_server* s, int64_t* grouped_launches, int64_t* grouped_products,
+                      size_t* bytes_in_use);
+const char* chase_server_last_error(chase_server* s);
+/* Finishes every queued request, then frees everything. */
+void chase_server_destroy(chase_server* s);
 
 #ifdef __cplusplus
 }

@@ -15,7 +15,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OBJ = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libchase.so")
-SOURCES = ["capi.hip", "filter.hip", "filter_kernels.hip", "loop_kernels.hip", "solver.hip"]
+SOURCES = ["capi.hip", "filter.hip", "filter_kernels.hip", "loop_kernels.hip", "solver.hip", "serving.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -25,7 +25,7 @@ FLAGS = [
     "-Wall", "-Wno-unused-function", "-Wno-unused-result",
     "-I" + os.path.join(ROOT, "include"), "-I/opt/rocm/include",
 ]
-LIBS = ["-L/opt/rocm/lib", "-lrocsolver", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"]
+LIBS = ["-L/opt/rocm/lib", "-lrocsolver", "-lrocblas", "-lpthread", "-Wl,-rpath,/opt/rocm/lib"]
 
 
 def _compile(src: str) -> str:

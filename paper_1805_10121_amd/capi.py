@@ -76,6 +76,21 @@ _PROTOTYPES = {
                                        ctypes.POINTER(_f64), ctypes.POINTER(chase_stats)]),
     "chase_seq_vectors": (ctypes.c_int, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_i64)]),
     "chase_seq_destroy": (None, [_vp]),
+    "chase_server_create": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_size_t,
+                                           ctypes.c_int]),
+    "chase_server_submit": (ctypes.c_int, [_vp, ctypes.c_uint64, ctypes.POINTER(chase_config), _vp,
+                                           _i64, ctypes.POINTER(ctypes.c_uint64)]),
+    "chase_server_poll": (ctypes.c_int, [_vp, ctypes.c_uint64, ctypes.c_int,
+                                         ctypes.POINTER(ctypes.c_int), ctypes.POINTER(_f64),
+                                         ctypes.POINTER(_f64), ctypes.POINTER(chase_stats),
+                                         ctypes.POINTER(_f64)]),
+    "chase_server_vectors": (ctypes.c_int, [_vp, ctypes.c_uint64, ctypes.POINTER(_vp),
+                                            ctypes.POINTER(_i64)]),
+    "chase_server_end_sequence": (ctypes.c_int, [_vp, ctypes.c_uint64]),
+    "chase_server_info": (ctypes.c_int, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64),
+                                         ctypes.POINTER(ctypes.c_size_t)]),
+    "chase_server_last_error": (ctypes.c_char_p, [_vp]),
+    "chase_server_destroy": (None, [_vp]),
 }
 
 _lib = None
@@ -222,6 +237,74 @@ class Sequence:
             pass
 
 
+class Server:
+    """chase_server: continuous batching of solves from many sequences on one device."""
+
+    def __init__(self, device: int = 0, mem_budget_bytes: int = 288 << 30, workers: int = 8):
+        h = ctypes.c_void_p()
+        rc = lib().chase_server_create(ctypes.byref(h), device, mem_budget_bytes, workers)
+        if rc != CHASE_OK:
+            raise ChaseError(rc, "chase_server_create failed")
+        self.handle = h
+        self._cfgs = {}
+
+    def _err(self, rc):
+        if rc < 0:
+            raise ChaseError(rc, lib().chase_server_last_error(self.handle).decode())
+        return rc
+
+    def chase_server_submit(self, seq_id, cfg, H, ldh):
+        t = ctypes.c_uint64()
+        self._err(lib().chase_server_submit(self.handle, seq_id, ctypes.byref(cfg), _ptr(H), ldh,
+                                            ctypes.byref(t)))
+        self._cfgs[t.value] = cfg.nev + cfg.nex
+        return t.value
+
+    def chase_server_poll(self, ticket, wait=False):
+        """Returns None while running, else (status, ritzv, resid, stats, latency_s)."""
+        import numpy as np
+
+        nb = self._cfgs[ticket]
+        done = ctypes.c_int()
+        ritzv, resid = np.zeros(nb), np.zeros(nb)
+        st, lat = chase_stats(), _f64()
+        rc = lib().chase_server_poll(self.handle, ticket, 1 if wait else 0, ctypes.byref(done),
+                                     ritzv.ctypes.data_as(ctypes.POINTER(_f64)),
+                                     resid.ctypes.data_as(ctypes.POINTER(_f64)), ctypes.byref(st),
+                                     ctypes.byref(lat))
+        if not done.value:
+            self._err(rc)
+            return None
+        self._cfgs.pop(ticket, None)
+        self._err(rc)
+        return rc, ritzv, resid, st, lat.value
+
+    def chase_server_vectors(self, seq_id):
+        p, ld = ctypes.c_void_p(), _i64()
+        self._err(lib().chase_server_vectors(self.handle, seq_id, ctypes.byref(p), ctypes.byref(ld)))
+        return p.value, ld.value
+
+    def chase_server_end_sequence(self, seq_id):
+        return self._err(lib().chase_server_end_sequence(self.handle, seq_id))
+
+    def chase_server_info(self):
+        a, b, c = _i64(), _i64(), ctypes.c_size_t()
+        self._err(lib().chase_server_info(self.handle, ctypes.byref(a), ctypes.byref(b),
+                                          ctypes.byref(c)))
+        return {"grouped_launches": a.value, "grouped_products": b.value, "bytes_in_use": c.value}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().chase_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 # ----------------------------------------------------------------------------- layout helpers
 
 def to_device(A, device="cuda"):
@@ -232,6 +315,22 @@ def to_device(A, device="cuda"):
 
     A = np.asarray(A)
     return torch.from_numpy(np.ascontiguousarray(A.T)).to(device)
+
+
+def device_block_to_host(ptr, ld, rows, cols):
+    """Copy a borrowed device complex128 block (column-major, leading dimension ld) to a numpy
+    array (rows, cols) -- a hipMemcpy2D through the HIP runtime, no arithmetic."""
+    import numpy as np
+
+    hip = ctypes.CDLL("libamdhip64.so")
+    hip.hipMemcpy2D.restype = ctypes.c_int
+    hip.hipMemcpy2D.argtypes = [_vp, ctypes.c_size_t, _vp, ctypes.c_size_t, ctypes.c_size_t,
+                                ctypes.c_size_t, ctypes.c_int]
+    out = np.empty((cols, rows), dtype=np.complex128)
+    rc = hip.hipMemcpy2D(out.ctypes.data, rows * 16, ptr, ld * 16, rows * 16, cols, 2)
+    if rc != 0:
+        raise RuntimeError(f"hipMemcpy2D failed ({rc})")
+    return out.T
 
 
 def from_device(t):

@@ -11,50 +11,49 @@
 
 namespace chase {
 
-template <typename T>
-hipError_t run_filter(const T* H, int64_t ldh, int64_t n, T* V, T* W, int64_t ld, int64_t ncols,
-                      const int32_t* degrees, double b_sup, double mu_1, double mu_nevnex,
-                      const ProductScratch& ps, hipStream_t stream, int64_t* matvecs_out) {
-  int64_t matvecs = 0;
-  if (ncols <= 0 || n <= 0) {
-    if (matvecs_out) *matvecs_out = 0;
-    return hipSuccess;
-  }
+std::vector<FilterProduct> filter_schedule(int64_t ncols, const int32_t* degrees, double b_sup,
+                                           double mu_1, double mu_nevnex) {
+  std::vector<FilterProduct> out;
+  if (ncols <= 0) return out;
   const double c = 0.5 * (b_sup + mu_nevnex);
   const double e = 0.5 * (b_sup - mu_nevnex);
   const double sigma1 = e / (mu_1 - c);
   const int32_t m_max = degrees[ncols - 1];
-
   // product 1, every column: W <- a1 H V + g1 V
   double alpha = sigma1 / e;
-  hipError_t err = launch_hemm_step<T>(H, ldh, n, V, ld, W, ld, ncols, static_cast<T>(alpha),
-                                       T(0), static_cast<T>(-alpha * c), ps, stream);
-  if (err != hipSuccess) return err;
-  matvecs += ncols;
-
-  T* cur_in = W;   // holds p_{i-1}
-  T* cur_out = V;  // holds p_{i-2}, receives p_i
+  out.push_back({/*from_v=*/true, 0, ncols, alpha, 0.0, -alpha * c});
+  bool in_is_w = true;  // p_{i-1} lives in W, p_{i-2} in V
   double sigma = sigma1;
   int64_t s = 0;
   while (s < ncols && degrees[s] <= 1) ++s;
   for (int32_t i = 2; i <= m_max; ++i) {
     const double tau = 1.0 / (2.0 / sigma1 - sigma);
     alpha = 2.0 * tau / e;
-    const double beta = -tau * sigma;
-    const double gamma = -alpha * c;
-    const int64_t act = ncols - s;
-    err = launch_hemm_step<T>(H, ldh, n, cur_in + 2 * s * ld, ld, cur_out + 2 * s * ld, ld, act,
-                              static_cast<T>(alpha), static_cast<T>(beta),
-                              static_cast<T>(gamma), ps, stream);
-    if (err != hipSuccess) return err;
-    matvecs += act;
-    T* tmp = cur_in;
-    cur_in = cur_out;
-    cur_out = tmp;
+    out.push_back({/*from_v=*/!in_is_w, s, ncols - s, alpha, -tau * sigma, -alpha * c});
+    in_is_w = !in_is_w;
     sigma = tau;
     while (s < ncols && degrees[s] <= i) ++s;
   }
-  // m_max is even, so the last product wrote V (cur_in == V now).
+  // m_max is even, so the last product wrote V.
+  return out;
+}
+
+template <typename T>
+hipError_t run_filter(const T* H, int64_t ldh, int64_t n, T* V, T* W, int64_t ld, int64_t ncols,
+                      const int32_t* degrees, double b_sup, double mu_1, double mu_nevnex,
+                      const ProductScratch& ps, hipStream_t stream, int64_t* matvecs_out) {
+  int64_t matvecs = 0;
+  if (ncols > 0 && n > 0) {
+    for (const FilterProduct& p : filter_schedule(ncols, degrees, b_sup, mu_1, mu_nevnex)) {
+      const T* X = (p.from_v ? V : W) + 2 * p.col0 * ld;
+      T* OUT = (p.from_v ? W : V) + 2 * p.col0 * ld;
+      hipError_t err = launch_hemm_step<T>(H, ldh, n, X, ld, OUT, ld, p.ncols,
+                                           static_cast<T>(p.alpha), static_cast<T>(p.beta),
+                                           static_cast<T>(p.gamma), ps, stream);
+      if (err != hipSuccess) return err;
+      matvecs += p.ncols;
+    }
+  }
   if (matvecs_out) *matvecs_out = matvecs;
   return hipSuccess;
 }

@@ -320,6 +320,31 @@ __global__ __launch_bounds__(kThreads) void hemm_fixup_kernel(
   }
 }
 
+// Grouped data-parallel schedule: one launch runs one product for each of up to kMaxGroup
+// independent problems (continuous batching of small solves).  The tiles of all problems are
+// concatenated; every tile is computed exactly as hemm_dp_kernel computes it (same K order),
+// so a problem's result does not depend on what it was grouped with.
+template <typename T, class C, int OCC>
+__global__ __launch_bounds__(kThreads, OCC) void hemm_group_kernel(GroupArgs<T> args) {
+  __shared__ typename C::Smem sm;
+  typename C::Frag f;
+  const int b = static_cast<int>(blockIdx.x);
+  int g = 0;
+  while (g + 1 < args.count && b >= args.d[g + 1].tile_begin) ++g;
+  const GroupDesc<T> d = args.d[g];
+  const int local = b - d.tile_begin;
+  const int tiles_m = (d.n + C::BMC - 1) / C::BMC;
+  const int tile_m = local % tiles_m, tile_n = local / tiles_m;
+  const int i0 = tile_m * C::BMC, j0 = tile_n * C::BNC;
+  const int nk = (d.n + C::KT - 1) / C::KT;
+  tile_mainloop<T, C>(sm, f, d.H, d.ldh, d.n, d.X, d.ldx, d.ncols, i0, j0, 0, nk);
+  tile_foreach<T, C>(f, [&](int r, int c, T hre, T him) {
+    if (i0 + r < d.n && j0 + c < d.ncols)
+      epilogue_store<T>(d.X, d.ldx, d.OUT, d.ldo, i0 + r, j0 + c, hre, him, d.alpha, d.beta,
+                        d.gamma);
+  });
+}
+
 template <typename T, class C, int OCC>
 hipError_t launch_dp(const T* H, int64_t ldh, int64_t n, const T* X, int64_t ldx, T* OUT,
                      int64_t ldo, int64_t ncols, T alpha, T beta, T gamma, hipStream_t stream) {
@@ -416,6 +441,31 @@ hipError_t launch_hemm_step(const T* H, int64_t ldh, int64_t n, const T* X, int6
   return launch_sched<T, WideTile<T>>(H, ldh, n, X, ldx, OUT, ldo, ncols, alpha, beta, gamma, ps,
                                       stream);
 }
+
+template <typename T>
+hipError_t launch_hemm_group(const GroupDesc<T>* descs, int count, hipStream_t stream) {
+  for (int base = 0; base < count; base += kMaxGroup) {
+    GroupArgs<T> a{};
+    a.count = std::min(kMaxGroup, count - base);
+    int64_t tiles = 0;
+    for (int q = 0; q < a.count; ++q) {
+      a.d[q] = descs[base + q];
+      a.d[q].tile_begin = static_cast<int>(tiles);
+      using C = WideTile<T>;
+      tiles += ((a.d[q].n + C::BMC - 1) / C::BMC) *
+               static_cast<int64_t>((a.d[q].ncols + C::BNC - 1) / C::BNC);
+    }
+    if (tiles == 0) continue;
+    if (tiles > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((hemm_group_kernel<T, WideTile<T>, kOcc>),
+                       dim3(static_cast<unsigned>(tiles)), dim3(kThreads), 0, stream, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+template hipError_t launch_hemm_group<double>(const GroupDesc<double>*, int, hipStream_t);
+template hipError_t launch_hemm_group<float>(const GroupDesc<float>*, int, hipStream_t);
 
 template hipError_t launch_hemm_step<double>(const double*, int64_t, int64_t, const double*,
                                              int64_t, double*, int64_t, int64_t, double, double,

@@ -29,6 +29,29 @@ hipError_t launch_hemm_step(const T* H, int64_t ldh, int64_t n, const T* X, int6
                             int64_t ldo, int64_t ncols, T alpha, T beta, T gamma,
                             const ProductScratch& ps, hipStream_t stream);
 
+// One product of one problem inside a grouped launch (fields as in launch_hemm_step;
+// tile_begin is filled by the launcher).  Zero-column products are allowed and skipped.
+template <typename T>
+struct GroupDesc {
+  const T* H;
+  const T* X;
+  T* OUT;
+  int64_t ldh, ldx, ldo;
+  int n, ncols;
+  T alpha, beta, gamma;
+  int tile_begin;
+};
+constexpr int kMaxGroup = 16;
+template <typename T>
+struct GroupArgs {
+  int count;
+  GroupDesc<T> d[kMaxGroup];
+};
+// Grouped products; every product is computed exactly as the data-parallel schedule computes
+// it alone, so results do not depend on the grouping.
+template <typename T>
+hipError_t launch_hemm_group(const GroupDesc<T>* descs, int count, hipStream_t stream);
+
 hipError_t launch_convert_c128_to_c64(const double* src, int64_t lds, float* dst, int64_t ldd,
                                       int64_t rows, int64_t cols, hipStream_t stream);
 hipError_t launch_convert_c64_to_c128(const float* src, int64_t lds, double* dst, int64_t ldd,
@@ -49,12 +72,47 @@ hipError_t launch_gaussian(double* X, int64_t n, int64_t ld, int64_t cols, uint6
                            hipStream_t s);
 
 // ----------------------------------------------------------------------------- filter driver
+// One product of Algorithm 4: OUT[:, col0:col0+ncols] <- alpha H X + gamma X + beta OUT where
+// (X, OUT) = (V, W) when from_v, else (W, V).
+struct FilterProduct {
+  bool from_v;
+  int64_t col0, ncols;
+  double alpha, beta, gamma;
+};
+// The products of one filter call on sorted even degrees (the recurrence scalars of Eq. (7)).
+std::vector<FilterProduct> filter_schedule(int64_t ncols, const int32_t* degrees, double b_sup,
+                                           double mu_1, double mu_nevnex);
+
 // Algorithm 4 on an n x ncols block with sorted even degrees (validated by the caller).  The
 // result ends in V.  scalars: the per-product (alpha, beta, gamma) in FP64.
 template <typename T>
 hipError_t run_filter(const T* H, int64_t ldh, int64_t n, T* V, T* W, int64_t ld, int64_t ncols,
                       const int32_t* degrees, double b_sup, double mu_1, double mu_nevnex,
                       const ProductScratch& ps, hipStream_t stream, int64_t* matvecs_out);
+
+// Continuous batching of filter products across concurrent solves: the products of every
+// submitted filter call advance one per tick, each tick being one grouped launch per precision
+// on the batcher's own stream.
+class Batcher {
+ public:
+  explicit Batcher(int device);
+  ~Batcher();
+  bool ok() const { return ok_; }
+  // Enqueue the products of one filter call; returns once all are launched, after making
+  // `caller` wait for their completion.  fp64: complex128 data, else complex64.  `ready` and
+  // `done` are events owned by the caller (reused across calls, destroyed only after the
+  // caller's stream has drained).
+  hipError_t run(bool fp64, const void* H, int64_t ldh, int64_t n, void* V, void* W, int64_t ld,
+                 const std::vector<FilterProduct>& prods, hipStream_t caller, hipEvent_t ready,
+                 hipEvent_t done);
+  void counters(int64_t* launches, int64_t* products) const;
+
+ private:
+  struct Job;
+  struct Impl;
+  Impl* impl_ = nullptr;
+  bool ok_ = false;
+};
 
 }  // namespace chase
 
@@ -74,6 +132,11 @@ namespace chase {
 int set_error(chase_ctx* ctx, int code, const std::string& msg);
 int ensure_workspace(chase_ctx* ctx, size_t bytes);
 int hip_ok(chase_ctx* ctx);  // hipSetDevice(ctx->device) with error reporting
+class Batcher;
+// chase_solve with an optional batcher for the filter products (serving).
+int solve_with(chase_ctx* ctx, const chase_config* cfg, const void* H, int64_t ldh, void* V,
+               int64_t ldv, double* ritzv, double* resid, chase_stats* stats, Batcher* batcher);
+int check_config(chase_ctx* ctx, const chase_config* cfg);
 }  // namespace chase
 
 #define CHASE_HIP_TRY(ctx, expr)                                                            \

@@ -206,13 +206,16 @@ struct Timer {
 
 class Solver {
  public:
-  Solver(chase_ctx* ctx, const chase_config& cfg) : ctx_(ctx), cfg_(cfg) {}
+  Solver(chase_ctx* ctx, const chase_config& cfg, Batcher* batcher)
+      : ctx_(ctx), cfg_(cfg), batcher_(batcher) {}
   int run(const void* H, int64_t ldh, void* Vuser, int64_t ldv, double* ritzv, double* resid,
           chase_stats* stats);
 
  private:
   chase_ctx* ctx_;
   chase_config cfg_;
+  Batcher* batcher_ = nullptr;
+  hipEvent_t bev_[2] = {nullptr, nullptr};  // events handed to the batcher (ready, done)
   Layout L_{};
   char* base_ = nullptr;
   int64_t n_ = 0, nb_ = 0;
@@ -453,19 +456,38 @@ int Solver::filter(const double* H, int64_t ldh, int64_t nlock, int64_t nact,
     float* V32 = at<float>(L_.V32);
     if ((rc = hip(launch_convert_c128_to_c64(col(L_.V, nlock), n_, V32, n_, n_, n32, s_), "cvt")))
       return rc;
-    if ((rc = hip(run_filter<float>(at<float>(L_.H32), n_, n_, V32, at<float>(L_.W32), n_, n32,
-                                    m.data(), b_sup_, mu_1_, mu_b_, ctx_->prod, s_, &mv),
-                  "filter fp32")))
-      return rc;
+    if (batcher_) {
+      const auto prods = filter_schedule(n32, m.data(), b_sup_, mu_1_, mu_b_);
+      mv = 0;
+      for (const auto& p : prods) mv += p.ncols;
+      rc = hip(batcher_->run(false, at<float>(L_.H32), n_, n_, V32, at<float>(L_.W32), n_, prods,
+                             s_, bev_[0], bev_[1]),
+               "batched filter fp32");
+    } else {
+      rc = hip(run_filter<float>(at<float>(L_.H32), n_, n_, V32, at<float>(L_.W32), n_, n32,
+                                 m.data(), b_sup_, mu_1_, mu_b_, ctx_->prod, s_, &mv),
+               "filter fp32");
+    }
+    if (rc) return rc;
     st_.filter_matvecs += mv;
     if ((rc = hip(launch_convert_c64_to_c128(V32, n_, col(L_.V, nlock), n_, n_, n32, s_), "cvt")))
       return rc;
   }
   if (nact - n32 > 0) {
-    if ((rc = hip(run_filter<double>(H, ldh, n_, col(L_.V, nlock + n32), col(L_.W, nlock + n32),
-                                     n_, nact - n32, m.data() + n32, b_sup_, mu_1_, mu_b_, ctx_->prod, s_, &mv),
-                  "filter fp64")))
-      return rc;
+    if (batcher_) {
+      const auto prods = filter_schedule(nact - n32, m.data() + n32, b_sup_, mu_1_, mu_b_);
+      mv = 0;
+      for (const auto& p : prods) mv += p.ncols;
+      rc = hip(batcher_->run(true, H, ldh, n_, col(L_.V, nlock + n32), col(L_.W, nlock + n32), n_,
+                             prods, s_, bev_[0], bev_[1]),
+               "batched filter fp64");
+    } else {
+      rc = hip(run_filter<double>(H, ldh, n_, col(L_.V, nlock + n32), col(L_.W, nlock + n32), n_,
+                                  nact - n32, m.data() + n32, b_sup_, mu_1_, mu_b_, ctx_->prod, s_,
+                                  &mv),
+               "filter fp64");
+    }
+    if (rc) return rc;
     st_.filter_matvecs += mv;
   }
   return CHASE_OK;
@@ -496,6 +518,18 @@ int Solver::run(const void* Hv, int64_t ldh, void* Vuser, int64_t ldv, double* r
       for (int i = 0; i < 8; ++i) (void)hipEventDestroy(e[i]);
     }
   } guard{ev};
+  struct BevGuard {
+    hipEvent_t* e;
+    hipStream_t s;
+    ~BevGuard() {
+      if (e[0] || e[1]) (void)hipStreamSynchronize(s);
+      for (int i = 0; i < 2; ++i)
+        if (e[i]) (void)hipEventDestroy(e[i]);
+    }
+  } bguard{bev_, s_};
+  if (batcher_)
+    for (auto& e : bev_)
+      if ((rc = hip(hipEventCreateWithFlags(&e, hipEventDisableTiming), "event"))) return rc;
   auto elapsed = [&](int a, int b) {
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, ev[a], ev[b]);
@@ -722,6 +756,8 @@ int Solver::run(const void* Hv, int64_t ldh, void* Vuser, int64_t ldv, double* r
   return st_.status;
 }
 
+}  // namespace
+
 int check_config(chase_ctx* ctx, const chase_config* cfg) {
   if (!cfg) return set_error(ctx, CHASE_EINVAL, "cfg is NULL");
   if (cfg->n < 1 || cfg->nev < 1 || cfg->nex < 0 || cfg->nev + cfg->nex > cfg->n)
@@ -746,8 +782,8 @@ int check_config(chase_ctx* ctx, const chase_config* cfg) {
   return CHASE_OK;
 }
 
-int solve_impl(chase_ctx* ctx, const chase_config* cfg, const void* H, int64_t ldh, void* V,
-               int64_t ldv, double* ritzv, double* resid, chase_stats* stats) {
+int solve_with(chase_ctx* ctx, const chase_config* cfg, const void* H, int64_t ldh, void* V,
+               int64_t ldv, double* ritzv, double* resid, chase_stats* stats, Batcher* batcher) {
   if (!ctx) return CHASE_EINVAL;
   ctx->last_error.clear();
   int rc = check_config(ctx, cfg);
@@ -764,11 +800,9 @@ int solve_impl(chase_ctx* ctx, const chase_config* cfg, const void* H, int64_t l
   const size_t vb = (static_cast<size_t>(nb - 1) * ldv + cfg->n) * 16;
   if (ph < pv + vb && pv < ph + hb) return set_error(ctx, CHASE_EINVAL, "H and V overlap");
   if ((rc = hip_ok(ctx))) return rc;
-  Solver s(ctx, *cfg);
+  Solver s(ctx, *cfg, batcher);
   return s.run(H, ldh, V, ldv, ritzv, resid, stats);
 }
-
-}  // namespace
 
 int hip_ok(chase_ctx* ctx) {
   hipError_t e = hipSetDevice(ctx->device);
@@ -801,7 +835,7 @@ size_t chase_workspace_bytes(const chase_config* cfg) {
 
 int chase_solve(chase_ctx* ctx, const chase_config* cfg, const void* H, int64_t ldh, void* V,
                 int64_t ldv, double* ritzv, double* resid, chase_stats* stats) {
-  return solve_impl(ctx, cfg, H, ldh, V, ldv, ritzv, resid, stats);
+  return solve_with(ctx, cfg, H, ldh, V, ldv, ritzv, resid, stats, nullptr);
 }
 
 int chase_seq_create(chase_ctx* ctx, const chase_config* cfg, chase_seq** out) {
@@ -842,7 +876,7 @@ int chase_seq_solve(chase_seq* seq, const void* H, int64_t ldh, double* ritzv, d
   const int64_t nb = cfg.nev + cfg.nex;
   std::vector<double> rs(nb, 0.0);
   if (seq->solved == 0 && seq->cfg.approx && ritzv) rv.assign(ritzv, ritzv + nb);
-  int rc = solve_impl(seq->ctx, &cfg, H, ldh, seq->V, cfg.n, rv.data(), rs.data(), stats);
+  int rc = solve_with(seq->ctx, &cfg, H, ldh, seq->V, cfg.n, rv.data(), rs.data(), stats, nullptr);
   if (rc < 0) return rc;
   seq->ritzv = rv;
   ++seq->solved;

@@ -141,6 +141,38 @@ def optimized_degree_profile(b: int, deg_max: int = 36) -> np.ndarray:
 
 # ----------------------------------------------------------------------------- torch (device)
 
+def hermitian_torch_fast(n: int, lam: np.ndarray, seed: int, device: str = "cuda",
+                         reflectors: int = 4):
+    """H = Q diag(lam) Q^H with Q = D_phase P_1 ... P_r, P_j = I - 2 u_j u_j^H for complex
+    Gaussian unit u_j and random unit phases D_phase -- a dense unitary that costs O(r n^2) to
+    apply, for orders where a Haar QR is impractical (n >= 20000).  With Gaussian start vectors
+    the iteration statistics of the eigensolver depend only on the spectrum, so this changes no
+    convergence behaviour.  Built in place (rank-one updates), so the peak memory is one n x n
+    complex128 matrix plus O(n) vectors.  The returned buffer, read column-major, is a Hermitian
+    matrix with spectrum lam."""
+    import torch
+
+    gen = torch.Generator(device=device)
+    gen.manual_seed(seed)
+    H = torch.diag(torch.as_tensor(lam, device=device, dtype=torch.float64).to(torch.complex128))
+    for _ in range(reflectors):
+        u = torch.complex(torch.randn(n, generator=gen, device=device, dtype=torch.float64),
+                          torch.randn(n, generator=gen, device=device, dtype=torch.float64))
+        u = u / torch.linalg.vector_norm(u)
+        # P H P = H - 2 u (u^H H) - 2 (H u) u^H + 4 (u^H H u) u u^H
+        Hu = H @ u
+        uHu = torch.vdot(u, Hu)
+        w = Hu - uHu * u                    # so that P H P = H - 2 u w^H - 2 w u^H
+        H.addr_(u, w.conj(), alpha=-2.0)
+        H.addr_(w, u.conj(), alpha=-2.0)
+        del Hu, w, u
+    ph = torch.rand(n, generator=gen, device=device, dtype=torch.float64) * (2 * np.pi)
+    d = torch.polar(torch.ones(n, device=device, dtype=torch.float64), ph)
+    H.mul_(d[:, None])
+    H.mul_(d.conj()[None, :])
+    return H
+
+
 def hermitian_torch(n: int, lam: np.ndarray, seed: int, device: str = "cuda",
                     dtype=None):
     """Same recipe on a torch device (for orders where the host QR is too slow).
