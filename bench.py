@@ -165,6 +165,173 @@ def run_sequence(args):
     }
 
 
+class _SeqSource:
+    """Problems of one serving sequence, generated on the device when they arrive."""
+
+    def __init__(self, sid, n, eps, seed):
+        from paper_1805_10121_amd import workloads as wl
+        import numpy as np
+
+        self.sid, self.n, self.eps, self.seed = sid, n, eps, seed
+        self.nev = max(1, round(0.05 * n))
+        self.nex = max(1, round(0.2 * self.nev))
+        self.lam = wl.spectrum_for(3, n=n, seed=seed)
+        self.norm = float(np.max(np.abs(self.lam)))
+        self.prev = None
+        self.k = 0
+
+    def next(self):
+        """H of the next problem (a new device tensor; the previous one stays valid)."""
+        H = make_sequence_problem(self.n, self.lam, self.k, self.eps, self.seed,
+                                  prev=None if self.prev is None else self.prev.clone(),
+                                  norm=self.norm)
+        self.prev = H
+        self.k += 1
+        return H
+
+
+def run_serving(n_seq=16, problems=8, rates=(0.5, 0.8, 1.0), sizes=(2000, 4000, 8000, 16000),
+                workers=8, precision_name="mixed", seed=4000):
+    """Continuous-batching serving of n_seq sequences: a closed-loop run (each sequence submits
+    its next problem when the previous finishes) measures the saturated throughput X; then
+    Poisson arrivals (each sequence its own process of rate r/n_seq) at r = f * X for f in
+    rates.  Latency = completion - arrival."""
+    import numpy as np
+    import torch
+
+    from paper_1805_10121_amd import capi
+    from paper_1805_10121_amd import workloads as wl
+
+    prec = capi.CHASE_MIXED if precision_name == "mixed" else capi.CHASE_FP64
+    ns = wl.serving_size(sizes, n_seq, seed)
+
+    def one_run(rate):
+        srcs = [_SeqSource(s, ns[s], 1e-3, seed + 10 * s) for s in range(n_seq)]
+        srv = capi.Server(0, mem_budget_bytes=288 << 30, workers=workers)
+        cfgs = [capi.config(src.n, src.nev, src.nex, optim=1, precision=prec, seed=seed + s)
+                for s, src in enumerate(srcs)]
+        g = wl.rng(seed + 999)
+        t0 = time.perf_counter()
+        if rate is None:
+            arrivals = [[0.0] + [None] * (problems - 1) for _ in range(n_seq)]
+        else:
+            arrivals = [list(np.cumsum(g.exponential(n_seq / rate, problems))) for _ in range(n_seq)]
+        nxt = [0] * n_seq
+        live = {}          # ticket -> (sid, k, arrival_time, H)
+        lat, errs, iters = [], [], []
+        done_count, total = 0, n_seq * problems
+        busy = [False] * n_seq
+        first_arr = None
+        while done_count < total:
+            now = time.perf_counter() - t0
+            for s in range(n_seq):
+                k = nxt[s]
+                if k >= problems:
+                    continue
+                ta = arrivals[s][k]
+                if ta is None:            # closed loop: arrive when the previous finished
+                    if busy[s]:
+                        continue
+                    ta = now
+                if ta <= now:
+                    H = srcs[s].next()
+                    torch.cuda.synchronize()
+                    t = srv.chase_server_submit(s, cfgs[s], H, srcs[s].n)
+                    live[t] = (s, k, ta, H)
+                    first_arr = ta if first_arr is None else min(first_arr, ta)
+                    nxt[s] += 1
+                    busy[s] = True
+            for t in list(live):
+                r = srv.chase_server_poll(t)
+                if r is None:
+                    continue
+                rc, ritzv, resid, st, _ = r
+                s, k, ta, H = live.pop(t)
+                t_end = time.perf_counter() - t0
+                lat.append(t_end - ta)
+                iters.append(st.iterations)
+                src = srcs[s]
+                if rc != 0:
+                    errs.append(float("inf"))
+                else:
+                    errs.append(float(np.max(resid[:src.nev]) / src.norm))
+                if k == 0:
+                    errs[-1] = max(errs[-1], float(np.max(np.abs(ritzv[:src.nev] - src.lam[:src.nev]))
+                                                   / src.norm))
+                busy[s] = any(v[0] == s for v in live.values())
+                done_count += 1
+                last_end = t_end
+            time.sleep(0.0005)
+        info = srv.chase_server_info()
+        srv.close()
+        del srcs
+        torch.cuda.empty_cache()
+        span = last_end - (first_arr or 0.0)
+        lat = np.array(lat)
+        return {"solves": total, "span_s": round(span, 3), "solves_per_s": round(total / span, 3),
+                "p50_latency_s": round(float(np.percentile(lat, 50)), 4),
+                "p99_latency_s": round(float(np.percentile(lat, 99)), 4),
+                "max_error_over_normH": max(errs), "mean_iterations": float(np.mean(iters)),
+                "grouped_products_per_launch": round(info["grouped_products"] /
+                                                     max(1, info["grouped_launches"]), 2)}
+
+    log(f"serving: sizes {ns}")
+    closed = one_run(None)
+    log(f"serving: closed loop {closed}")
+    X = closed["solves_per_s"]
+    out = {"workload": f"serving {n_seq} sequences x {problems} problems, n per sequence from "
+                       f"{list(sizes)} (drawn: {ns}), nev = 5% n, nex = 20% nev, eps 1e-3, "
+                       f"{precision_name} filter, tol 1e-10, {workers} workers",
+           "closed_loop": closed, "poisson": {}}
+    for f in rates:
+        r = one_run(f * X)
+        log(f"serving: poisson {f} x {X:.3f}/s: {r}")
+        out["poisson"][f"{f}x"] = dict(r, offered_rate=round(f * X, 3))
+    return out
+
+
+def run_ablation(cfg_id=1, degrees=(8, 12, 16, 20, 24, 28, 32, 36)):
+    """Degree-optimisation ablation (the paper's Fig. 1 experiment on a synthetic problem):
+    constant degree (optim off) against per-vector degrees (optim on, deg = initial degree),
+    reporting filter and total matvecs, iterations and time-to-solution per setting."""
+    import numpy as np
+    import torch
+
+    from paper_1805_10121_amd import capi
+    from paper_1805_10121_amd import workloads as wl
+
+    c = wl.CONFIGS[cfg_id]
+    n, nev, nex = c["n"], c["nev"], c["nex"]
+    lam = wl.spectrum_for(cfg_id)
+    if n <= 2000:
+        dH = capi.to_device(wl.hermitian(n, lam, 1000 * cfg_id + 1))
+    else:
+        dH = wl.hermitian_torch(n, lam, seed=1000 * cfg_id + 1)
+    V0 = wl.start_block(n, nev + nex, 1000 * cfg_id + 500)
+    ctx = capi.Context(0)
+    rows = []
+    for optim in (0, 1):
+        for d in degrees:
+            cfg = capi.config(n, nev, nex, optim=optim, deg=d, seed=1000 * cfg_id + 600)
+            dV = capi.to_device(V0)
+            ritzv, resid = np.zeros(nev + nex), np.zeros(nev + nex)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rc, st = ctx.chase_solve(cfg, dH, n, dV, n, ritzv, resid)
+            dt = time.perf_counter() - t0
+            other_mv = st.matvecs - st.filter_matvecs
+            rows.append({"optim": optim, "deg": d, "status": rc, "iterations": st.iterations,
+                         "filter_gflop": round(8e-9 * n * n * st.filter_matvecs, 2),
+                         "other_matvec_gflop": round(8e-9 * n * n * other_mv, 2),
+                         "time_s": round(dt, 4),
+                         "max_eig_error_over_normH": float(
+                             np.max(np.abs(ritzv[:nev] - lam[:nev])) / np.max(np.abs(lam)))})
+            log(f"ablation cfg{cfg_id} optim={optim} deg={d}: {rows[-1]}")
+    ctx.close()
+    return {"workload": f"degree ablation, problem n={n} nev={nev} nex={nex} (cold start)",
+            "rows": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -173,7 +340,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
-    ap.add_argument("--workload", choices=["filter", "sequence"], default="filter",
+    ap.add_argument("--workload", choices=["filter", "sequence", "serving", "ablation"],
+                    default="filter",
                     help="filter: the hot-path benchmark (default); sequence: time-to-solution of "
                          "a warm-started sequence, plain FP64 against the mixed FP32/FP64 filter")
     ap.add_argument("--problems", type=int, default=10)
@@ -203,6 +371,14 @@ def main():
 
     if args.workload == "sequence":
         print(json.dumps(run_sequence(args)), flush=True)
+        return
+    if args.workload == "ablation":
+        out = {"config1": run_ablation(1), "config2": run_ablation(2)}
+        print(json.dumps(out), flush=True)
+        return
+    if args.workload == "serving":
+        print(json.dumps(run_serving(problems=args.problems if args.problems != 10 else 8)),
+              flush=True)
         return
 
     cfg = wl.CONFIGS[2]

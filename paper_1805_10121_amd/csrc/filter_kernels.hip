@@ -64,13 +64,13 @@ constexpr int kThreads = 256;
 // waves form a WR x WC grid, each owning (BMC/WR) x (BNC/WC) complex outputs, i.e. RT row
 // slabs of 8 complex (16 real) rows times CG column groups of 16, each group an (Re X, Im X)
 // pair of MFMA tiles.
-template <typename T, int BMC_, int BNC_, int KT_, int WR_, int WC_>
+template <typename T, int BMC_, int BNC_, int KT_, int WR_, int WC_, int PAD_ = 2>
 struct Tile {
   static constexpr int BMC = BMC_, BNC = BNC_, KT = KT_, WR = WR_, WC = WC_;
   static constexpr int RT = BMC / WR / 8;
   static constexpr int CG = BNC / WC / 16;
-  static constexpr int AR = 2 * BMC + 2;  // padded real rows per A stage row (k fixed)
-  static constexpr int BR = 2 * BNC + 2;  // padded real columns per B stage row (k fixed)
+  static constexpr int AR = 2 * BMC + PAD_;  // padded real rows per A stage row (k fixed)
+  static constexpr int BR = 2 * BNC + PAD_;  // padded real columns per B stage row (k fixed)
   static constexpr int A_PER = BMC * KT / kThreads;
   static constexpr int B_PER = BNC * KT / kThreads;
   static_assert(WR * WC == 4, "four waves");

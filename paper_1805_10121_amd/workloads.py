@@ -141,33 +141,56 @@ def optimized_degree_profile(b: int, deg_max: int = 36) -> np.ndarray:
 
 # ----------------------------------------------------------------------------- torch (device)
 
+def structured_unitary(n: int, seed: int, reflectors: int = 4):
+    """Host-drawn factors of Q = D P_r ... P_1 (P_j = I - 2 u_j u_j^H, D = diag(d)): unit
+    complex Gaussian u_j (rows of U) and unit phases d."""
+    g = rng(seed)
+    U = complex_gaussian(g, reflectors, n)
+    U /= np.linalg.norm(U, axis=1, keepdims=True)
+    d = np.exp(2j * np.pi * g.uniform(0.0, 1.0, n))
+    return U, d
+
+
+def apply_colmajor_qh(U, d, v):
+    """Q-bar^H v for the matrix that hermitian_torch_fast's buffer holds when read column-major
+    (that matrix is Q-bar diag(lam) Q-bar^H with Q-bar = conj(Q)); v: (n,) or (n, k)."""
+    w = (d.reshape(-1, *([1] * (np.ndim(v) - 1)))) * v
+    for j in range(U.shape[0] - 1, -1, -1):
+        u = U[j].conj()
+        w = w - 2.0 * np.multiply.outer(u, u.conj() @ w) if np.ndim(v) > 1 else w - 2.0 * u * (u.conj() @ w)
+    return w
+
+
+def apply_colmajor_q(U, d, z):
+    """Q-bar z (inverse of apply_colmajor_qh)."""
+    w = np.array(z, dtype=np.complex128, copy=True)
+    for j in range(U.shape[0]):
+        u = U[j].conj()
+        w = w - 2.0 * np.multiply.outer(u, u.conj() @ w) if np.ndim(z) > 1 else w - 2.0 * u * (u.conj() @ w)
+    return np.conj(d).reshape(-1, *([1] * (np.ndim(z) - 1))) * w
+
+
 def hermitian_torch_fast(n: int, lam: np.ndarray, seed: int, device: str = "cuda",
                          reflectors: int = 4):
-    """H = Q diag(lam) Q^H with Q = D_phase P_1 ... P_r, P_j = I - 2 u_j u_j^H for complex
-    Gaussian unit u_j and random unit phases D_phase -- a dense unitary that costs O(r n^2) to
-    apply, for orders where a Haar QR is impractical (n >= 20000).  With Gaussian start vectors
-    the iteration statistics of the eigensolver depend only on the spectrum, so this changes no
-    convergence behaviour.  Built in place (rank-one updates), so the peak memory is one n x n
-    complex128 matrix plus O(n) vectors.  The returned buffer, read column-major, is a Hermitian
-    matrix with spectrum lam."""
+    """H = Q diag(lam) Q^H with Q = D P_r ... P_1 from ``structured_unitary`` -- a dense unitary
+    that costs O(r n^2) to apply, for orders where a Haar QR is impractical (n >= 20000).  With
+    Gaussian start vectors the iteration statistics of the eigensolver depend only on the
+    spectrum, so this changes no convergence behaviour.  Built in place (rank-one updates): the
+    peak memory is one n x n complex128 matrix plus O(n) vectors.  The returned buffer, read
+    column-major, is Q-bar diag(lam) Q-bar^H (see ``apply_colmajor_q``)."""
     import torch
 
-    gen = torch.Generator(device=device)
-    gen.manual_seed(seed)
+    Uh, dh = structured_unitary(n, seed, reflectors)
     H = torch.diag(torch.as_tensor(lam, device=device, dtype=torch.float64).to(torch.complex128))
-    for _ in range(reflectors):
-        u = torch.complex(torch.randn(n, generator=gen, device=device, dtype=torch.float64),
-                          torch.randn(n, generator=gen, device=device, dtype=torch.float64))
-        u = u / torch.linalg.vector_norm(u)
-        # P H P = H - 2 u (u^H H) - 2 (H u) u^H + 4 (u^H H u) u u^H
+    for j in range(reflectors):
+        u = torch.as_tensor(Uh[j], device=device)
+        # P H P = H - 2 u w^H - 2 w u^H with w = H u - (u^H H u) u
         Hu = H @ u
-        uHu = torch.vdot(u, Hu)
-        w = Hu - uHu * u                    # so that P H P = H - 2 u w^H - 2 w u^H
+        w = Hu - torch.vdot(u, Hu) * u
         H.addr_(u, w.conj(), alpha=-2.0)
         H.addr_(w, u.conj(), alpha=-2.0)
         del Hu, w, u
-    ph = torch.rand(n, generator=gen, device=device, dtype=torch.float64) * (2 * np.pi)
-    d = torch.polar(torch.ones(n, device=device, dtype=torch.float64), ph)
+    d = torch.as_tensor(dh, device=device)
     H.mul_(d[:, None])
     H.mul_(d.conj()[None, :])
     return H

@@ -227,3 +227,37 @@ def test_filter_full_size_sampled(ctx):
     ref = ch.filter_columns(H, V[:, cols], deg[cols], b_sup, mu_1, mu_b)
     for k in range(len(cols)):
         assert np.linalg.norm(sub[:, k] - ref[:, k]) <= 1e-12 * np.linalg.norm(ref[:, k]) * 10
+
+
+@pytest.mark.parametrize("n,nb,profile_max", [(20000, 1200, 36), (60000, 2400, 4)])
+def test_filter_large_orders_closed_form(ctx, n, nb, profile_max):
+    """Orders 20000 (1200 columns, degrees 2..36) and 60000 (2400 columns, degrees 2..4) on the
+    structured generator: every column against the closed form Qbar diag(p_m(lam)) Qbar^H v."""
+    import torch
+    from paper_1805_10121_amd import capi
+
+    print(f"large-order filter n={n} nb={nb}: generating", flush=True)
+    lam = wl.spectrum_for(5 if n == 60000 else 3, n=n)
+    dH = wl.hermitian_torch_fast(n, lam, seed=7000 + n)
+    U, d = wl.structured_unitary(n, 7000 + n)
+    V = wl.start_block(n, nb, 7100)
+    deg = wl.optimized_degree_profile(nb, profile_max)
+    b_sup, mu_1, mu_b = float(lam[-1]) + 0.05, float(lam[0]), float(lam[nb - 1])
+    dV = capi.to_device(V)
+    dW = torch.empty_like(dV)
+    print("large-order filter: running", flush=True)
+    ctx.chase_filter(capi.CHASE_FP64, dH, n, n, dV, dW, n, nb, deg, b_sup, mu_1, mu_b)
+    torch.cuda.synchronize()
+    del dH, dW
+    got = capi.from_device(dV)
+    del dV
+    torch.cuda.empty_cache()
+    print("large-order filter: closed form", flush=True)
+    Wq = wl.apply_colmajor_qh(U, d, V)
+    for m in np.unique(deg):
+        cols = deg == m
+        Wq[:, cols] *= ch.p_closed(lam, int(m), b_sup, mu_1, mu_b)[:, None]
+    ref = wl.apply_colmajor_q(U, d, Wq)
+    err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    print(f"large-order filter n={n}: block-relative error {err:.3e}")
+    assert err <= 1e-12

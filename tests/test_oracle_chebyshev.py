@@ -128,3 +128,20 @@ def test_alg4_rejects_odd_or_unsorted():
         ch.filter_alg4(A, V, [3, 4], 2.0, -1.0, 0.0)
     with pytest.raises(ValueError):
         ch.filter_alg4(A, V, [4, 2], 2.0, -1.0, 0.0)
+
+
+def test_structured_generator_closed_form():
+    # The fast device generator's matrix, read column-major, is Qbar diag(lam) Qbar^H with the
+    # host-reproducible reflector factors; the filter on it has the closed form of Eq. (5).
+    n, nb = 160, 5
+    lam = wl.spectrum_uniform(n, wl.rng(8))
+    A = wl.hermitian_torch_fast(n, lam, 21, device="cpu").numpy().T
+    U, d = wl.structured_unitary(n, 21)
+    V = wl.complex_gaussian(wl.rng(9), n, nb)
+    deg = np.array([2, 4, 8, 16, 36])
+    got = ch.filter_columns(A, V, deg, 1.1, lam[0], lam[15])
+    W = wl.apply_colmajor_qh(U, d, V)
+    for a in range(nb):
+        W[:, a] *= p_lib(lam, int(deg[a]), 1.1, lam[0], lam[15])
+    ref = wl.apply_colmajor_q(U, d, W)
+    assert np.linalg.norm(got - ref) <= 1e-12 * np.linalg.norm(ref)
