@@ -346,6 +346,9 @@ def main():
                          "a warm-started sequence, plain FP64 against the mixed FP32/FP64 filter")
     ap.add_argument("--problems", type=int, default=10)
     ap.add_argument("--order", type=int, default=20000)
+    ap.add_argument("--h-gen", choices=["haar", "structured"], default="haar",
+                    help="H for the filter workload: Haar Q (QR of a Gaussian) or the structured "
+                         "reflector unitary (no QR; used for counter-collection runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy three times (counter calibration)")
     args = ap.parse_args()
@@ -384,8 +387,9 @@ def main():
     cfg = wl.CONFIGS[2]
     n, nb = cfg["n"], cfg["nev"] + cfg["nex"]
     lam = wl.spectrum_for(2)
-    log(f"bench: generating H (n={n}) on the device")
-    dH = wl.hermitian_torch(n, lam, seed=2001)
+    log(f"bench: generating H (n={n}, {args.h_gen}) on the device")
+    dH = (wl.hermitian_torch(n, lam, seed=2001) if args.h_gen == "haar"
+          else wl.hermitian_torch_fast(n, lam, seed=2001))
     V = wl.start_block(n, nb, 2500)
     deg = wl.optimized_degree_profile(nb, 36)
     b_sup, mu_1, mu_b = float(lam[-1]) + 0.05, float(lam[0]), float(lam[nb - 1])

@@ -64,9 +64,13 @@ constexpr int kThreads = 256;
 // waves form a WR x WC grid, each owning (BMC/WR) x (BNC/WC) complex outputs, i.e. RT row
 // slabs of 8 complex (16 real) rows times CG column groups of 16, each group an (Re X, Im X)
 // pair of MFMA tiles.
-template <typename T, int BMC_, int BNC_, int KT_, int WR_, int WC_, int PAD_ = 2>
+// PROMOTE_ > 0 (complex64 only): every PROMOTE_ K stages the FP32 MFMA accumulators are added
+// into FP64 accumulators and cleared, so rounding error stops growing with the length of the
+// dot product (FP32 products, FP64 sums across stages).
+template <typename T, int BMC_, int BNC_, int KT_, int WR_, int WC_, int PAD_ = 2, int PROMOTE_ = 0>
 struct Tile {
   static constexpr int BMC = BMC_, BNC = BNC_, KT = KT_, WR = WR_, WC = WC_;
+  static constexpr int PROMOTE = PROMOTE_;
   static constexpr int RT = BMC / WR / 8;
   static constexpr int CG = BNC / WC / 16;
   static constexpr int AR = 2 * BMC + PAD_;  // padded real rows per A stage row (k fixed)
@@ -82,62 +86,87 @@ struct Tile {
     T As[2][KT][AR];
     T Bs[2][KT][BR];
   };
-  struct Frag {
+  struct Frag64 {
+    acc_t acc[RT][CG][2];
+    double acc64[RT][CG][2][4];
+  };
+  struct Frag32 {
     acc_t acc[RT][CG][2];
   };
+  using Frag = typename std::conditional<(PROMOTE_ > 0), Frag64, Frag32>::type;
 };
 
 // acc <- R[i0.., k] [Re X | Im X][k, j0..] summed over the K stages ka <= kt < kb.
-template <typename T, class C>
+// V16 (complex64 only): global loads of two consecutive complex elements (16 bytes); the caller
+// guarantees 16-byte aligned H and X and even leading dimensions.
+template <typename T, class C, bool V16 = false>
 __device__ __forceinline__ void tile_mainloop(typename C::Smem& sm, typename C::Frag& f,
                                               const T* __restrict__ H, int64_t ldh, int n,
                                               const T* __restrict__ X, int64_t ldx, int ncols,
                                               int i0, int j0, int ka, int kb) {
   using v2 = typename C::v2;
   using acc_t = typename C::acc_t;
+  constexpr int VEC = (V16 && sizeof(T) == 4) ? 2 : 1;  // complex elements per global load
+  struct alignas(16) VL { v2 e[VEC]; };
+  constexpr int A_LD = C::BMC * C::KT / (kThreads * VEC);
+  constexpr int B_LD = C::BNC * C::KT / (kThreads * VEC);
+  static_assert(A_LD * kThreads * VEC == C::BMC * C::KT, "A load split");
+  static_assert(B_LD * kThreads * VEC == C::BNC * C::KT, "B load split");
+  static_assert(VEC == 1 || (C::AR * sizeof(T)) % 16 == 0, "16-byte LDS rows for V16");
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, li = lane & 15;
   const int wr = wave / C::WC, wc = wave % C::WC;
-  v2 ra[C::A_PER], rb[C::B_PER];
+  VL ra[A_LD], rb[B_LD];
 
   auto load_tiles = [&](int k0) {
 #pragma unroll
-    for (int q = 0; q < C::A_PER; ++q) {
+    for (int q = 0; q < A_LD; ++q) {
       const int idx = tid + kThreads * q;
-      const int kk = idx / C::BMC, ci = idx % C::BMC;
+      const int kk = idx / (C::BMC / VEC), ci = (idx % (C::BMC / VEC)) * VEC;
       const int row = i0 + ci, col = k0 + kk;
-      if (row < n && col < n)
-        ra[q] = *reinterpret_cast<const v2*>(H + 2 * (static_cast<int64_t>(row) +
-                                                       static_cast<int64_t>(col) * ldh));
-      else
-        ra[q] = v2{T(0), T(0)};
+      const T* src = H + 2 * (static_cast<int64_t>(row) + static_cast<int64_t>(col) * ldh);
+      if (col < n && row + VEC - 1 < n) {
+        ra[q] = *reinterpret_cast<const VL*>(src);
+      } else {
+#pragma unroll
+        for (int e = 0; e < VEC; ++e)
+          ra[q].e[e] = (col < n && row + e < n) ? reinterpret_cast<const v2*>(src)[e]
+                                                  : v2{T(0), T(0)};
+      }
     }
 #pragma unroll
-    for (int q = 0; q < C::B_PER; ++q) {
+    for (int q = 0; q < B_LD; ++q) {
       const int idx = tid + kThreads * q;
-      const int jj = idx / C::KT, kk = idx % C::KT;
+      const int jj = idx / (C::KT / VEC), kk = (idx % (C::KT / VEC)) * VEC;
       const int row = k0 + kk, col = j0 + jj;
-      if (row < n && col < ncols)
-        rb[q] = *reinterpret_cast<const v2*>(X + 2 * (static_cast<int64_t>(row) +
-                                                       static_cast<int64_t>(col) * ldx));
-      else
-        rb[q] = v2{T(0), T(0)};
+      const T* src = X + 2 * (static_cast<int64_t>(row) + static_cast<int64_t>(col) * ldx);
+      if (col < ncols && row + VEC - 1 < n) {
+        rb[q] = *reinterpret_cast<const VL*>(src);
+      } else {
+#pragma unroll
+        for (int e = 0; e < VEC; ++e)
+          rb[q].e[e] = (col < ncols && row + e < n) ? reinterpret_cast<const v2*>(src)[e]
+                                                     : v2{T(0), T(0)};
+      }
     }
   };
   auto store_tiles = [&](int buf) {
 #pragma unroll
-    for (int q = 0; q < C::A_PER; ++q) {
+    for (int q = 0; q < A_LD; ++q) {
       const int idx = tid + kThreads * q;
-      const int kk = idx / C::BMC, ci = idx % C::BMC;
-      *reinterpret_cast<v2*>(&sm.As[buf][kk][2 * ci]) = ra[q];
+      const int kk = idx / (C::BMC / VEC), ci = (idx % (C::BMC / VEC)) * VEC;
+      *reinterpret_cast<VL*>(&sm.As[buf][kk][2 * ci]) = ra[q];
     }
 #pragma unroll
-    for (int q = 0; q < C::B_PER; ++q) {
+    for (int q = 0; q < B_LD; ++q) {
       const int idx = tid + kThreads * q;
-      const int jj = idx / C::KT, kk = idx % C::KT;
-      sm.Bs[buf][kk][jj] = rb[q].x;
-      sm.Bs[buf][kk][C::BNC + jj] = rb[q].y;
+      const int jj = idx / (C::KT / VEC), kk = (idx % (C::KT / VEC)) * VEC;
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) {
+        sm.Bs[buf][kk + e][jj] = rb[q].e[e].x;
+        sm.Bs[buf][kk + e][C::BNC + jj] = rb[q].e[e].y;
+      }
     }
   };
 
@@ -146,7 +175,13 @@ __device__ __forceinline__ void tile_mainloop(typename C::Smem& sm, typename C::
 #pragma unroll
     for (int b = 0; b < C::CG; ++b)
 #pragma unroll
-      for (int c = 0; c < 2; ++c) f.acc[a][b][c] = acc_t{0};
+      for (int c = 0; c < 2; ++c) {
+        f.acc[a][b][c] = acc_t{0};
+        if constexpr (C::PROMOTE > 0) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) f.acc64[a][b][c][e] = 0.0;
+        }
+      }
 
   const int arow = a_row<T>(li);
   const int rbase = wr * (C::BMC / C::WR) * 2;  // first real row of this wave in the A stage
@@ -176,6 +211,20 @@ __device__ __forceinline__ void tile_mainloop(typename C::Smem& sm, typename C::
           for (int p = 0; p < 2; ++p)
             f.acc[rt][cg][p] = mfma(a[rt], b[cg][p], f.acc[rt][cg][p]);
     }
+    if constexpr (C::PROMOTE > 0) {
+      if ((kt - ka + 1) % C::PROMOTE == 0 || kt + 1 == kb) {
+#pragma unroll
+        for (int a = 0; a < C::RT; ++a)
+#pragma unroll
+          for (int b = 0; b < C::CG; ++b)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+#pragma unroll
+              for (int e = 0; e < 4; ++e) f.acc64[a][b][c][e] += static_cast<double>(f.acc[a][b][c][e]);
+              f.acc[a][b][c] = acc_t{0};
+            }
+      }
+    }
     if (kt + 1 < kb) store_tiles(cur ^ 1);
     __syncthreads();
   }
@@ -196,9 +245,15 @@ __device__ __forceinline__ void tile_foreach(const typename C::Frag& f, Fn&& fn)
       for (int p = 0; p < 2; ++p) {
         const int r = wr * (C::BMC / C::WR) + rt * 8 + c_row<T>(g, p);
         const int c = wc * (C::BNC / C::WC) + cg * 16 + li;
-        const T hre = f.acc[rt][cg][0][2 * p] - f.acc[rt][cg][1][2 * p + 1];
-        const T him = f.acc[rt][cg][1][2 * p] + f.acc[rt][cg][0][2 * p + 1];
-        fn(r, c, hre, him);
+        if constexpr (C::PROMOTE > 0) {
+          const double hre = f.acc64[rt][cg][0][2 * p] - f.acc64[rt][cg][1][2 * p + 1];
+          const double him = f.acc64[rt][cg][1][2 * p] + f.acc64[rt][cg][0][2 * p + 1];
+          fn(r, c, static_cast<T>(hre), static_cast<T>(him));
+        } else {
+          const T hre = f.acc[rt][cg][0][2 * p] - f.acc[rt][cg][1][2 * p + 1];
+          const T him = f.acc[rt][cg][1][2 * p] + f.acc[rt][cg][0][2 * p + 1];
+          fn(r, c, hre, him);
+        }
       }
 }
 
@@ -222,7 +277,7 @@ __device__ __forceinline__ void epilogue_store(const T* __restrict__ X, int64_t 
 }
 
 // Data-parallel schedule: one workgroup per output tile (row tiles vary fastest).
-template <typename T, class C, int OCC>
+template <typename T, class C, int OCC, bool V16>
 __global__ __launch_bounds__(kThreads, OCC) void hemm_dp_kernel(
     const T* __restrict__ H, int64_t ldh, int n, const T* __restrict__ X, int64_t ldx,
     T* __restrict__ OUT, int64_t ldo, int ncols, T alpha, T beta, T gamma, int tiles_m) {
@@ -232,20 +287,30 @@ __global__ __launch_bounds__(kThreads, OCC) void hemm_dp_kernel(
   const int tile_n = static_cast<int>(blockIdx.x) / tiles_m;
   const int i0 = tile_m * C::BMC, j0 = tile_n * C::BNC;
   const int nk = (n + C::KT - 1) / C::KT;
-  tile_mainloop<T, C>(sm, f, H, ldh, n, X, ldx, ncols, i0, j0, 0, nk);
+  tile_mainloop<T, C, V16>(sm, f, H, ldh, n, X, ldx, ncols, i0, j0, 0, nk);
   tile_foreach<T, C>(f, [&](int r, int c, T hre, T him) {
     if (i0 + r < n && j0 + c < ncols)
       epilogue_store<T>(X, ldx, OUT, ldo, i0 + r, j0 + c, hre, him, alpha, beta, gamma);
   });
 }
 
-// Stream-K schedule.  The work units (tile, K stage) are numbered tile-major,
-// u = t * nk + kt, and persistent workgroup p owns [u0(p), u1(p)) with u0(p) = floor(p U / P).
-// A tile whose K range is covered by one workgroup is finished in place; otherwise each
-// contributor writes its partial sum H X (before the epilogue) to its own slot -- slot 0 for
-// the segment in the tile containing u0(p), slot 1 for the segment in the tile containing
-// u1(p) - 1 -- and hemm_fixup_kernel adds the slots in increasing p, so the result does not
-// depend on timing.
+// Hybrid data-parallel + stream-K schedule on P persistent workgroups.
+//   Phase 1: the first dp_tiles = floor(tiles / P) * P tiles, round-robin (workgroup p takes
+//            tiles p, p + P, ...), each finished in place.
+//   Phase 2: the remaining tiles' work units (tile, K stage), numbered u = (t - dp_tiles) * nk + kt,
+//            split evenly: workgroup p owns [u0(p), u1(p)) with u0(p) = floor(p U / P).  A tile
+//            covered by one workgroup is finished in place; otherwise each contributor writes its
+//            partial sum H X (before the epilogue) to its own slot -- slot 0 for the segment in
+//            the tile containing u0(p), slot 1 for the segment in the tile containing u1(p) - 1 --
+//            and hemm_fixup_kernel adds the slots in increasing p, so the result does not depend
+//            on timing.
+// Tile t -> (row tile, column tile), column tiles varying fastest: consecutive tiles share a
+// row panel of H.
+__device__ __forceinline__ void tile_coords(int64_t t, int tiles_n, int* tile_m, int* tile_n) {
+  *tile_m = static_cast<int>(t / tiles_n);
+  *tile_n = static_cast<int>(t % tiles_n);
+}
+
 __device__ __forceinline__ int64_t sk_start(int64_t p, int64_t units, int64_t P) {
   return p * units / P;
 }
@@ -253,38 +318,56 @@ __device__ __forceinline__ int64_t sk_owner(int64_t u, int64_t units, int64_t P)
   return ((u + 1) * P - 1) / units;  // max p with sk_start(p) <= u
 }
 
-template <typename T, class C, int OCC>
+template <typename T, class C, int OCC, bool V16>
 __global__ __launch_bounds__(kThreads, OCC) void hemm_sk_kernel(
     const T* __restrict__ H, int64_t ldh, int n, const T* __restrict__ X, int64_t ldx,
     T* __restrict__ OUT, int64_t ldo, int ncols, T alpha, T beta, T gamma, int tiles_m,
-    int nk, int64_t units, T* __restrict__ partial) {
+    int nk, int64_t dp_tiles, int64_t units, T* __restrict__ partial) {
   __shared__ typename C::Smem sm;
   typename C::Frag f;
   const int64_t P = gridDim.x, p = blockIdx.x;
+  const int tiles_n = (ncols + C::BNC - 1) / C::BNC;
+  // Workgroups are dealt round-robin to the 8 XCDs (each with its own L2); q renumbers them so
+  // that the workgroups of one XCD hold consecutive tiles, i.e. the column tiles of the same
+  // row panels, which then stream the same H stages through that XCD's L2 at the same time.
+  const int64_t q = (P % 8 == 0) ? (p % 8) * (P / 8) + p / 8 : p;
+  for (int64_t t = q; t < dp_tiles; t += P) {
+    int tile_m, tile_n;
+    tile_coords(t, tiles_n, &tile_m, &tile_n);
+    const int i0 = tile_m * C::BMC, j0 = tile_n * C::BNC;
+    tile_mainloop<T, C, V16>(sm, f, H, ldh, n, X, ldx, ncols, i0, j0, 0, nk);
+    tile_foreach<T, C>(f, [&](int r, int c, T hre, T him) {
+      if (i0 + r < n && j0 + c < ncols)
+        epilogue_store<T>(X, ldx, OUT, ldo, i0 + r, j0 + c, hre, him, alpha, beta, gamma);
+    });
+  }
+  if (units == 0) return;
   const int64_t u0 = sk_start(p, units, P), u1 = sk_start(p + 1, units, P);
   const int64_t t_first = u0 / nk;
   constexpr int TE = C::BMC * C::BNC;  // complex elements per tile
   int64_t u = u0;
   while (u < u1) {
-    const int64_t t = u / nk;
-    const int ka = static_cast<int>(u - t * nk);
+    const int64_t tr = u / nk;  // tile index within the stream-K part
+    const int ka = static_cast<int>(u - tr * nk);
     const int kb = static_cast<int>(min(static_cast<int64_t>(nk), ka + (u1 - u)));
-    const int tile_m = static_cast<int>(t % tiles_m), tile_n = static_cast<int>(t / tiles_m);
+    const int64_t t = dp_tiles + tr;
+    int tile_m, tile_n;
+    tile_coords(t, tiles_n, &tile_m, &tile_n);
     const int i0 = tile_m * C::BMC, j0 = tile_n * C::BNC;
-    tile_mainloop<T, C>(sm, f, H, ldh, n, X, ldx, ncols, i0, j0, ka, kb);
+    tile_mainloop<T, C, V16>(sm, f, H, ldh, n, X, ldx, ncols, i0, j0, ka, kb);
     if (ka == 0 && kb == nk) {
       tile_foreach<T, C>(f, [&](int r, int c, T hre, T him) {
         if (i0 + r < n && j0 + c < ncols)
           epilogue_store<T>(X, ldx, OUT, ldo, i0 + r, j0 + c, hre, him, alpha, beta, gamma);
       });
     } else {
-      T* dst = partial + 2 * (p * 2 + (t == t_first ? 0 : 1)) * TE;
+      T* dst = partial + 2 * (p * 2 + (tr == t_first ? 0 : 1)) * TE;
       tile_foreach<T, C>(f, [&](int r, int c, T hre, T him) {
         dst[2 * (r + c * C::BMC)] = hre;
         dst[2 * (r + c * C::BMC) + 1] = him;
       });
     }
-    u = t * nk + kb;
+    u = tr * nk + kb;
   }
 }
 
@@ -293,25 +376,27 @@ __global__ __launch_bounds__(kThreads, OCC) void hemm_sk_kernel(
 template <typename T, class C>
 __global__ __launch_bounds__(kThreads) void hemm_fixup_kernel(
     const T* __restrict__ X, int64_t ldx, T* __restrict__ OUT, int64_t ldo, int n, int ncols,
-    T alpha, T beta, T gamma, int tiles_m, int nk, int64_t units, int64_t P,
+    T alpha, T beta, T gamma, int tiles_m, int nk, int64_t dp_tiles, int64_t units, int64_t P,
     const T* __restrict__ partial) {
   const int64_t q = blockIdx.x;
-  if (q == 0) return;
+  if (q == 0 || units == 0) return;
   const int64_t uq = sk_start(q, units, P);
   if (uq >= units || uq % nk == 0) return;
-  const int64_t t = uq / nk;
-  if (sk_start(q - 1, units, P) > t * nk) return;  // an earlier boundary handles this tile
-  const int64_t pf = sk_owner(t * nk, units, P), pl = sk_owner((t + 1) * nk - 1, units, P);
-  const int tile_m = static_cast<int>(t % tiles_m), tile_n = static_cast<int>(t / tiles_m);
+  const int64_t tr = uq / nk;
+  if (sk_start(q - 1, units, P) > tr * nk) return;  // an earlier boundary handles this tile
+  const int64_t pf = sk_owner(tr * nk, units, P), pl = sk_owner((tr + 1) * nk - 1, units, P);
+  const int64_t t = dp_tiles + tr;
+  int tile_m, tile_n;
+  tile_coords(t, (ncols + C::BNC - 1) / C::BNC, &tile_m, &tile_n);
   const int i0 = tile_m * C::BMC, j0 = tile_n * C::BNC;
   constexpr int TE = C::BMC * C::BNC;
   for (int e = threadIdx.x; e < TE; e += kThreads) {
     const int r = e % C::BMC, c = e / C::BMC;
     T hre = T(0), him = T(0);
-    for (int64_t p = pf; p <= pl; ++p) {
-      const int64_t a = sk_start(p, units, P), b = sk_start(p + 1, units, P);
+    for (int64_t pp = pf; pp <= pl; ++pp) {
+      const int64_t a = sk_start(pp, units, P), b = sk_start(pp + 1, units, P);
       if (a >= b) continue;  // empty range
-      const T* src = partial + 2 * (p * 2 + (a / nk == t ? 0 : 1)) * TE;
+      const T* src = partial + 2 * (pp * 2 + (a / nk == tr ? 0 : 1)) * TE;
       hre += src[2 * e];
       him += src[2 * e + 1];
     }
@@ -324,7 +409,7 @@ __global__ __launch_bounds__(kThreads) void hemm_fixup_kernel(
 // independent problems (continuous batching of small solves).  The tiles of all problems are
 // concatenated; every tile is computed exactly as hemm_dp_kernel computes it (same K order),
 // so a problem's result does not depend on what it was grouped with.
-template <typename T, class C, int OCC>
+template <typename T, class C, int OCC, bool V16>
 __global__ __launch_bounds__(kThreads, OCC) void hemm_group_kernel(GroupArgs<T> args) {
   __shared__ typename C::Smem sm;
   typename C::Frag f;
@@ -337,7 +422,7 @@ __global__ __launch_bounds__(kThreads, OCC) void hemm_group_kernel(GroupArgs<T> 
   const int tile_m = local % tiles_m, tile_n = local / tiles_m;
   const int i0 = tile_m * C::BMC, j0 = tile_n * C::BNC;
   const int nk = (d.n + C::KT - 1) / C::KT;
-  tile_mainloop<T, C>(sm, f, d.H, d.ldh, d.n, d.X, d.ldx, d.ncols, i0, j0, 0, nk);
+  tile_mainloop<T, C, V16>(sm, f, d.H, d.ldh, d.n, d.X, d.ldx, d.ncols, i0, j0, 0, nk);
   tile_foreach<T, C>(f, [&](int r, int c, T hre, T him) {
     if (i0 + r < d.n && j0 + c < d.ncols)
       epilogue_store<T>(d.X, d.ldx, d.OUT, d.ldo, i0 + r, j0 + c, hre, him, d.alpha, d.beta,
@@ -345,14 +430,15 @@ __global__ __launch_bounds__(kThreads, OCC) void hemm_group_kernel(GroupArgs<T> 
   });
 }
 
-template <typename T, class C, int OCC>
+
+template <typename T, class C, int OCC, bool V16 = false>
 hipError_t launch_dp(const T* H, int64_t ldh, int64_t n, const T* X, int64_t ldx, T* OUT,
                      int64_t ldo, int64_t ncols, T alpha, T beta, T gamma, hipStream_t stream) {
   const int tiles_m = static_cast<int>((n + C::BMC - 1) / C::BMC);
   const int tiles_n = static_cast<int>((ncols + C::BNC - 1) / C::BNC);
   const int64_t blocks = static_cast<int64_t>(tiles_m) * tiles_n;
   if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((hemm_dp_kernel<T, C, OCC>), dim3(static_cast<unsigned>(blocks)),
+  hipLaunchKernelGGL((hemm_dp_kernel<T, C, OCC, V16>), dim3(static_cast<unsigned>(blocks)),
                      dim3(kThreads), 0, stream, H, ldh, static_cast<int>(n), X, ldx, OUT, ldo,
                      static_cast<int>(ncols), alpha, beta, gamma, tiles_m);
   return hipGetLastError();
@@ -364,23 +450,26 @@ constexpr size_t sk_scratch_bytes(int64_t P) {
   return static_cast<size_t>(P) * 2 * C::BMC * C::BNC * 2 * sizeof(T);
 }
 
-template <typename T, class C, int OCC>
+template <typename T, class C, int OCC, bool V16 = false>
 hipError_t launch_sk(const T* H, int64_t ldh, int64_t n, const T* X, int64_t ldx, T* OUT,
                      int64_t ldo, int64_t ncols, T alpha, T beta, T gamma, int64_t P, T* partial,
-                     hipStream_t stream) {
+                     hipStream_t stream, bool hybrid = true) {
   const int tiles_m = static_cast<int>((n + C::BMC - 1) / C::BMC);
   const int tiles_n = static_cast<int>((ncols + C::BNC - 1) / C::BNC);
   const int nk = static_cast<int>((n + C::KT - 1) / C::KT);
-  const int64_t units = static_cast<int64_t>(tiles_m) * tiles_n * nk;
-  if (P > units) P = units;
-  hipLaunchKernelGGL((hemm_sk_kernel<T, C, OCC>), dim3(static_cast<unsigned>(P)), dim3(kThreads), 0,
+  const int64_t tiles = static_cast<int64_t>(tiles_m) * tiles_n;
+  int64_t dp_tiles = hybrid ? (tiles / P) * P : 0;
+  int64_t units = (tiles - dp_tiles) * nk;
+  if (dp_tiles == 0 && P > units) P = units;
+  hipLaunchKernelGGL((hemm_sk_kernel<T, C, OCC, V16>), dim3(static_cast<unsigned>(P)), dim3(kThreads), 0,
                      stream, H, ldh, static_cast<int>(n), X, ldx, OUT, ldo,
-                     static_cast<int>(ncols), alpha, beta, gamma, tiles_m, nk, units, partial);
+                     static_cast<int>(ncols), alpha, beta, gamma, tiles_m, nk, dp_tiles, units,
+                     partial);
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  if (e != hipSuccess || units == 0) return e;
   hipLaunchKernelGGL((hemm_fixup_kernel<T, C>), dim3(static_cast<unsigned>(P)), dim3(kThreads), 0,
                      stream, X, ldx, OUT, ldo, static_cast<int>(n), static_cast<int>(ncols), alpha,
-                     beta, gamma, tiles_m, nk, units, P, partial);
+                     beta, gamma, tiles_m, nk, dp_tiles, units, P, partial);
   return hipGetLastError();
 }
 
@@ -400,11 +489,22 @@ __global__ void convert_kernel(const S* __restrict__ src, int64_t lds, D* __rest
 
 }  // namespace
 
+
 namespace {
 // Tile shapes (complex rows x complex columns, K stage, wave grid).  Both precisions use the
 // same wide tile; columns <= 32 use the narrow one.
-template <typename T> using WideTile = Tile<T, 64, 64, 16, 2, 2>;
-template <typename T> using NarrowTile = Tile<T, 64, 32, 16, 4, 1>;
+// LDS rows are padded by 2 doubles (FP64) or 8 floats (FP32: keeps 16-byte aligned rows for
+// the two-element vector loads).
+template <typename T> using WideTile = Tile<T, 64, 64, 16, 2, 2, sizeof(T) == 4 ? 8 : 2>;
+template <typename T> using NarrowTile = Tile<T, 64, 32, 16, 4, 1, sizeof(T) == 4 ? 8 : 2>;
+
+// Two-element (16-byte) global loads are used for complex64 data when H and X are 16-byte
+// aligned and their leading dimensions are even.
+template <typename T>
+bool use_v16(const T* H, int64_t ldh, const T* X, int64_t ldx) {
+  return sizeof(T) == 4 && (reinterpret_cast<uintptr_t>(H) % 16) == 0 &&
+         (reinterpret_cast<uintptr_t>(X) % 16) == 0 && ldh % 2 == 0 && ldx % 2 == 0;
+}
 constexpr int kOcc = 2;  // workgroups per CU the tiles are built for
 
 template <typename T, class C>
@@ -415,8 +515,16 @@ hipError_t launch_sched(const T* H, int64_t ldh, int64_t n, const T* X, int64_t 
   const int64_t slots = static_cast<int64_t>(ps.cus) * kOcc;
   const int64_t rounds = (tiles + slots - 1) / slots;
   const double eff = static_cast<double>(tiles) / static_cast<double>(rounds * slots);
-  if (eff >= 0.92 || !ps.ptr || sk_scratch_bytes<T, C>(slots) > ps.bytes)
+  const bool v16 = use_v16(H, ldh, X, ldx);
+  if (eff >= 0.92 || !ps.ptr || sk_scratch_bytes<T, C>(slots) > ps.bytes) {
+    if (v16)
+      return launch_dp<T, C, kOcc, true>(H, ldh, n, X, ldx, OUT, ldo, ncols, alpha, beta, gamma,
+                                         stream);
     return launch_dp<T, C, kOcc>(H, ldh, n, X, ldx, OUT, ldo, ncols, alpha, beta, gamma, stream);
+  }
+  if (v16)
+    return launch_sk<T, C, kOcc, true>(H, ldh, n, X, ldx, OUT, ldo, ncols, alpha, beta, gamma,
+                                       slots, static_cast<T*>(ps.ptr), stream);
   return launch_sk<T, C, kOcc>(H, ldh, n, X, ldx, OUT, ldo, ncols, alpha, beta, gamma, slots,
                                static_cast<T*>(ps.ptr), stream);
 }
@@ -457,8 +565,14 @@ hipError_t launch_hemm_group(const GroupDesc<T>* descs, int count, hipStream_t s
     }
     if (tiles == 0) continue;
     if (tiles > 0x7fffffff) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((hemm_group_kernel<T, WideTile<T>, kOcc>),
-                       dim3(static_cast<unsigned>(tiles)), dim3(kThreads), 0, stream, a);
+    bool v16 = true;
+    for (int q = 0; q < a.count; ++q) v16 = v16 && use_v16(a.d[q].H, a.d[q].ldh, a.d[q].X, a.d[q].ldx);
+    if (v16)
+      hipLaunchKernelGGL((hemm_group_kernel<T, WideTile<T>, kOcc, true>),
+                         dim3(static_cast<unsigned>(tiles)), dim3(kThreads), 0, stream, a);
+    else
+      hipLaunchKernelGGL((hemm_group_kernel<T, WideTile<T>, kOcc, false>),
+                         dim3(static_cast<unsigned>(tiles)), dim3(kThreads), 0, stream, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

@@ -578,6 +578,11 @@ int Solver::run(const void* Hv, int64_t ldh, void* Vuser, int64_t ldv, double* r
   int64_t nlock = 0;
   std::vector<int> m(nb_, mixed ? std::min(deg0, deg32max) : deg0);
   std::vector<int> prec(nb_, mixed ? 1 : 0);
+  // Mixed mode history, indexed by ascending Ritz rank among the active pairs: last residual,
+  // whether that pair was filtered in FP32, and a sticky FP64 flag set when an FP32 iteration
+  // reduced the residual by less than 10x (the FP32 filter's accuracy floor was reached).
+  std::vector<double> hist_res(nb_, INFINITY);
+  std::vector<char> hist_fp32(nb_, mixed ? 1 : 0), lock64(nb_, 0);
   std::vector<double> lam_act(nb_, 0.0), res_act(nb_, 0.0), lam_lock, res_lock;
   std::vector<int> perm(nb_);
   int it = 0;
@@ -671,10 +676,18 @@ int Solver::run(const void* Hv, int64_t ldh, void* Vuser, int64_t ldv, double* r
     // degrees (lines 12-14, Alg. 5) and precision groups
     const int64_t rem = nact - n_new;
     std::vector<int> mnew(rem), pnew(rem), idx(rem);
+    std::vector<double> nres(rem);
+    std::vector<char> nfp32(rem), nl64(rem);
     for (int64_t q = 0; q < rem; ++q) {
-      const int a = order[n_new + q];
-      const bool fp32 = mixed && res_act[a] > tol32;
+      const int64_t r = n_new + q;
+      const int a = order[r];
+      const bool stuck = mixed && hist_fp32[r] && res_act[a] > 0.1 * hist_res[r];
+      const bool l64 = lock64[r] || stuck;
+      const bool fp32 = mixed && !l64 && res_act[a] > tol32;
       pnew[q] = fp32 ? 1 : 0;
+      nres[q] = res_act[a];
+      nfp32[q] = fp32 ? 1 : 0;
+      nl64[q] = l64 ? 1 : 0;
       if (cfg_.optim)
         mnew[q] = fp32 ? degree_of(tol32, res_act[a], lam_act[a], c, e, cfg_.deg_extra, deg32max)
                        : degree_of(tol_eff, res_act[a], lam_act[a], c, e, cfg_.deg_extra,
@@ -682,6 +695,11 @@ int Solver::run(const void* Hv, int64_t ldh, void* Vuser, int64_t ldv, double* r
       else
         mnew[q] = fp32 ? std::min(deg0, deg32max) : deg0;
       idx[q] = static_cast<int>(q);
+    }
+    for (int64_t q = 0; q < rem; ++q) {
+      hist_res[q] = nres[q];
+      hist_fp32[q] = nfp32[q];
+      lock64[q] = nl64[q];
     }
     // sort (line 15): key (precision group: FP32 first, degree)
     std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) {

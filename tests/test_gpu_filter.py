@@ -261,3 +261,29 @@ def test_filter_large_orders_closed_form(ctx, n, nb, profile_max):
     err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
     print(f"large-order filter n={n}: block-relative error {err:.3e}")
     assert err <= 1e-12
+
+
+@pytest.mark.parametrize("n,ld", [(333, 334), (333, 333), (1001, 1002)])
+def test_filter_fp32_ragged_rows_and_leading_dimension(ctx, n, ld):
+    """FP32 products use 16-byte loads when pointers and leading dimensions allow it; odd n
+    with even ld exercises the per-element tail, odd ld the 8-byte path."""
+    import torch
+    from paper_1805_10121_amd import capi
+
+    nb = 37
+    deg = wl.optimized_degree_profile(nb, 12)
+    lam, H, V = _problem(n, nb, 3000 + n + ld)
+    b_sup, mu_1, mu_b = 2.02, lam[0], lam[n // 15]
+    ref = ch.filter_columns(H, V, deg, b_sup, mu_1, mu_b)
+    Hp = np.full((ld, n), np.nan, dtype=np.complex64)
+    Hp[:n] = H.astype(np.complex64)
+    Vp = np.full((ld, nb), np.nan, dtype=np.complex64)
+    Vp[:n] = V.astype(np.complex64)
+    dH, dV = capi.to_device(Hp), capi.to_device(Vp)
+    dW = torch.zeros_like(dV)
+    ctx.chase_filter(capi.CHASE_FP32, dH, ld, n, dV, dW, ld, nb, deg, b_sup, mu_1, mu_b)
+    torch.cuda.synchronize()
+    got = capi.from_device(dV)[:n].astype(np.complex128)
+    err = _relerr(got, ref)
+    print(f"fp32 n={n} ld={ld} block-relative error {err:.3e}")
+    assert err <= 2e-5
