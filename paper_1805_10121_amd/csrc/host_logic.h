@@ -1,0 +1,178 @@
+// Host-side logic of the solver that needs no device: the filter's product schedule
+// (Algorithm 4 / Eq. (7) scalars), Algorithm 5 (degrees), the small symmetric eigensolver for
+// the Lanczos tridiagonals and the DoS estimate of Sec. 4.2 (Algorithm 6).  Header-only and free
+// of HIP so that it can also be compiled and checked on a machine without a GPU.
+#pragma once
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <numeric>
+#include <vector>
+
+namespace chase {
+
+// One product of Algorithm 4: OUT[:, col0:col0+ncols] <- alpha H X + gamma X + beta OUT where
+// (X, OUT) = (V, W) when from_v, else (W, V).
+struct FilterProduct {
+  bool from_v;
+  int64_t col0, ncols;
+  double alpha, beta, gamma;
+};
+
+// The products of one filter call on sorted even degrees (the recurrence scalars of Eq. (7)).
+inline std::vector<FilterProduct> filter_schedule(int64_t ncols, const int32_t* degrees, double b_sup,
+                                           double mu_1, double mu_nevnex) {
+  std::vector<FilterProduct> out;
+  if (ncols <= 0) return out;
+  const double c = 0.5 * (b_sup + mu_nevnex);
+  const double e = 0.5 * (b_sup - mu_nevnex);
+  const double sigma1 = e / (mu_1 - c);
+  const int32_t m_max = degrees[ncols - 1];
+  // product 1, every column: W <- a1 H V + g1 V
+  double alpha = sigma1 / e;
+  out.push_back({/*from_v=*/true, 0, ncols, alpha, 0.0, -alpha * c});
+  bool in_is_w = true;  // p_{i-1} lives in W, p_{i-2} in V
+  double sigma = sigma1;
+  int64_t s = 0;
+  while (s < ncols && degrees[s] <= 1) ++s;
+  for (int32_t i = 2; i <= m_max; ++i) {
+    const double tau = 1.0 / (2.0 / sigma1 - sigma);
+    alpha = 2.0 * tau / e;
+    out.push_back({/*from_v=*/!in_is_w, s, ncols - s, alpha, -tau * sigma, -alpha * c});
+    in_is_w = !in_is_w;
+    sigma = tau;
+    while (s < ncols && degrees[s] <= i) ++s;
+  }
+  // m_max is even, so the last product wrote V.
+  return out;
+}
+
+
+// Symmetric eigen-decomposition of a small dense matrix by cyclic Jacobi rotations (used for the
+// k x k Lanczos tridiagonals; k is a few dozen).  a: row-major k x k, destroyed.  On return
+// evals ascending and evecs[:, i] (row-major, column i) the matching eigenvectors.
+inline void jacobi_eigh(int k, std::vector<double>& a, std::vector<double>& evals,
+                 std::vector<double>& evecs) {
+  std::vector<double> v(static_cast<size_t>(k) * k, 0.0);
+  for (int i = 0; i < k; ++i) v[i * k + i] = 1.0;
+  double fro = 0.0;
+  for (double x : a) fro += x * x;
+  fro = std::sqrt(fro);
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0;
+    for (int p = 0; p < k; ++p)
+      for (int q = p + 1; q < k; ++q) off += a[p * k + q] * a[p * k + q];
+    if (std::sqrt(off) <= 1e-17 * fro) break;
+    for (int p = 0; p < k; ++p)
+      for (int q = p + 1; q < k; ++q) {
+        const double apq = a[p * k + q];
+        if (apq == 0.0) continue;
+        const double theta = (a[q * k + q] - a[p * k + p]) / (2.0 * apq);
+        const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+        const double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+        for (int r = 0; r < k; ++r) {  // columns p, q
+          const double arp = a[r * k + p], arq = a[r * k + q];
+          a[r * k + p] = c * arp - s * arq;
+          a[r * k + q] = s * arp + c * arq;
+        }
+        for (int r = 0; r < k; ++r) {  // rows p, q
+          const double apr = a[p * k + r], aqr = a[q * k + r];
+          a[p * k + r] = c * apr - s * aqr;
+          a[q * k + r] = s * apr + c * aqr;
+        }
+        for (int r = 0; r < k; ++r) {
+          const double vrp = v[r * k + p], vrq = v[r * k + q];
+          v[r * k + p] = c * vrp - s * vrq;
+          v[r * k + q] = s * vrp + c * vrq;
+        }
+      }
+  }
+  std::vector<int> idx(k);
+  std::iota(idx.begin(), idx.end(), 0);
+  std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return a[x * k + x] < a[y * k + y]; });
+  evals.resize(k);
+  evecs.assign(static_cast<size_t>(k) * k, 0.0);
+  for (int i = 0; i < k; ++i) {
+    evals[i] = a[idx[i] * k + idx[i]];
+    for (int r = 0; r < k; ++r) evecs[r * k + i] = v[r * k + idx[i]];
+  }
+}
+
+struct LanczosRun {
+  std::vector<double> ritz, evecs;  // evecs row-major k x k, column i = eigenvector i
+  int k = 0;
+  double beta_last = 0.0;
+};
+
+inline LanczosRun tridiag_eig(const std::vector<double>& al, const std::vector<double>& be, int nv, int c,
+                       int k) {
+  // truncate at the first vanishing beta (invariant subspace)
+  int kk = k;
+  for (int j = 0; j < k; ++j)
+    if (!(be[j * nv + c] > 0.0)) {
+      kk = j + 1;
+      break;
+    }
+  std::vector<double> T(static_cast<size_t>(kk) * kk, 0.0);
+  for (int j = 0; j < kk; ++j) {
+    T[j * kk + j] = al[j * nv + c];
+    if (j + 1 < kk) T[j * kk + j + 1] = T[(j + 1) * kk + j] = be[j * nv + c];
+  }
+  LanczosRun r;
+  r.k = kk;
+  r.beta_last = be[(kk - 1) * nv + c];
+  jacobi_eigh(kk, T, r.ritz, r.evecs);
+  return r;
+}
+
+// mu_{nev+nex} from the Gaussian-smoothed spectral density of the DoS runs (Sec. 4.2, Eq. (10)):
+// bisection on sum_i w_i Phi((t - lambda_i)/s) = (nev+nex)/n.
+inline double dos_mu(const std::vector<LanczosRun>& runs, double lo, double b_sup, double sigma,
+              double target) {
+  const double half = b_sup > lo ? 0.5 * (b_sup - lo) : 1.0;
+  const double s = sigma * half;
+  auto cdf = [&](double t) {
+    double acc = 0.0;
+    for (const auto& r : runs)
+      for (int i = 0; i < r.k; ++i) {
+        const double w = r.evecs[0 * r.k + i] * r.evecs[0 * r.k + i];
+        acc += w * 0.5 * (1.0 + std::erf((t - r.ritz[i]) / (s * std::sqrt(2.0))));
+      }
+    return acc / static_cast<double>(runs.size());
+  };
+  double a = lo - 8.0 * s, b = b_sup + 8.0 * s;
+  for (int it = 0; it < 200; ++it) {
+    const double mid = 0.5 * (a + b);
+    if (cdf(mid) < target)
+      a = mid;
+    else
+      b = mid;
+  }
+  return 0.5 * (a + b);
+}
+
+// Algorithm 5 for one vector.
+inline int degree_of(double tol, double res, double ritz, double c, double e, int deg_extra, int deg_max) {
+  const double t = (ritz - c) / e;
+  double rho;
+  if (std::fabs(t) <= 1.0) {
+    rho = 1.0;
+  } else {
+    const double r = std::sqrt(t * t - 1.0);
+    rho = std::max(std::fabs(t - r), std::fabs(t + r));
+  }
+  const double lr = std::log(rho);
+  int d;
+  if (!(lr > 0.0) || !(res > 0.0)) {
+    d = deg_max;
+  } else {
+    const double q = std::fabs(std::log(res / tol) / lr);
+    const double dd = std::ceil(q) + deg_extra;
+    d = dd > deg_max ? deg_max : static_cast<int>(dd);
+  }
+  return d + (d & 1);
+}
+
+
+}  // namespace chase

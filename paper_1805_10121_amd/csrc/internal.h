@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "../../include/chase.h"
+#include "host_logic.h"
 
 namespace chase {
 
@@ -72,16 +73,6 @@ hipError_t launch_gaussian(double* X, int64_t n, int64_t ld, int64_t cols, uint6
                            hipStream_t s);
 
 // ----------------------------------------------------------------------------- filter driver
-// One product of Algorithm 4: OUT[:, col0:col0+ncols] <- alpha H X + gamma X + beta OUT where
-// (X, OUT) = (V, W) when from_v, else (W, V).
-struct FilterProduct {
-  bool from_v;
-  int64_t col0, ncols;
-  double alpha, beta, gamma;
-};
-// The products of one filter call on sorted even degrees (the recurrence scalars of Eq. (7)).
-std::vector<FilterProduct> filter_schedule(int64_t ncols, const int32_t* degrees, double b_sup,
-                                           double mu_1, double mu_nevnex);
 
 // Algorithm 4 on an n x ncols block with sorted even degrees (validated by the caller).  The
 // result ends in V.  scalars: the per-product (alpha, beta, gamma) in FP64.

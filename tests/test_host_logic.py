@@ -1,0 +1,133 @@
+"""The library's host-side logic, compiled with g++ on the CPU, against the oracle (no GPU).
+
+Covers the filter's product schedule (Alg. 4 / Eq. (7) scalars and active ranges), Alg. 5
+(degrees), the tridiagonal eigensolver used on the Lanczos coefficients and the DoS estimate of
+mu_{nev+nex} (Alg. 6).  The C++ and the oracle share no code; this test only compares them.
+"""
+
+import os
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+
+from oracle import chase as och
+from oracle import chebyshev as ch
+from oracle import lanczos as lz
+from paper_1805_10121_amd import workloads as wl
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_1805_10121_amd", "csrc")
+
+DRIVER = r"""
+#include <cstdio>
+#include <string>
+#include <vector>
+#include "host_logic.h"
+using namespace chase;
+int main() {
+  char mode[32];
+  if (scanf("%31s", mode) != 1) return 1;
+  std::string m(mode);
+  if (m == "schedule") {
+    long nc; double b, m1, mb; scanf("%ld %lf %lf %lf", &nc, &b, &m1, &mb);
+    std::vector<int32_t> d(nc); for (auto& x : d) scanf("%d", &x);
+    for (auto& p : filter_schedule(nc, d.data(), b, m1, mb))
+      printf("%d %ld %ld %.17g %.17g %.17g\n", p.from_v ? 1 : 0, (long)p.col0, (long)p.ncols, p.alpha, p.beta, p.gamma);
+  } else if (m == "degrees") {
+    int k, extra, dmax; double tol, c, e; scanf("%d %lf %lf %lf %d %d", &k, &tol, &c, &e, &extra, &dmax);
+    for (int i = 0; i < k; ++i) { double r, l; scanf("%lf %lf", &r, &l); printf("%d\n", degree_of(tol, r, l, c, e, extra, dmax)); }
+  } else if (m == "tridiag") {
+    int nv, k; scanf("%d %d", &nv, &k);
+    std::vector<double> al(nv * k), be(nv * k);
+    for (auto& x : al) scanf("%lf", &x);
+    for (auto& x : be) scanf("%lf", &x);
+    for (int c = 0; c < nv; ++c) {
+      LanczosRun r = tridiag_eig(al, be, nv, c, k);
+      for (int i = 0; i < r.k; ++i) printf("%.17g %.17g\n", r.ritz[i], r.evecs[0 * r.k + i] * r.evecs[0 * r.k + i]);
+    }
+  } else if (m == "dos") {
+    int nv, k; double bsup, sigma, target; scanf("%d %d %lf %lf %lf", &nv, &k, &bsup, &sigma, &target);
+    std::vector<double> al(nv * k), be(nv * k);
+    for (auto& x : al) scanf("%lf", &x);
+    for (auto& x : be) scanf("%lf", &x);
+    std::vector<LanczosRun> runs; double lo = 1e300;
+    for (int c = 0; c < nv; ++c) { runs.push_back(tridiag_eig(al, be, nv, c, k)); lo = std::min(lo, runs.back().ritz.front()); }
+    printf("%.17g %.17g\n", lo, dos_mu(runs, lo, bsup, sigma, target));
+  }
+  return 0;
+}
+"""
+
+
+@pytest.fixture(scope="module")
+def exe():
+    d = tempfile.mkdtemp()
+    src = os.path.join(d, "drv.cpp")
+    out = os.path.join(d, "drv")
+    open(src, "w").write(DRIVER)
+    subprocess.run(["g++", "-std=c++17", "-O2", "-I", CSRC, src, "-o", out], check=True)
+    return out
+
+
+def _run(exe, text):
+    return subprocess.run([exe], input=text, capture_output=True, text=True, check=True).stdout
+
+
+def test_filter_schedule_matches_oracle(exe):
+    g = wl.rng(1)
+    for _ in range(5):
+        nc = int(g.integers(1, 40))
+        deg = np.sort(2 * g.integers(1, 19, nc)).astype(int)
+        b, m1, mb = 2.1, -1.05, float(g.uniform(-0.6, 0.5))
+        out = _run(exe, f"schedule {nc} {b!r} {m1!r} {mb!r} " + " ".join(map(str, deg)))
+        rows = [ln.split() for ln in out.strip().splitlines()]
+        ref = ch.filter_scalars(int(deg.max()), b, m1, mb)
+        assert len(rows) == int(deg.max())
+        for i, r in enumerate(rows, start=1):
+            a, bb, gg = map(float, r[3:])
+            assert np.allclose([a, bb, gg], ref[i - 1], rtol=1e-14, atol=0)
+            # active columns at product i: degrees >= i; buffers alternate V->W, W->V, ...
+            assert int(r[1]) == int(np.searchsorted(deg, i, side="left")) if i > 1 else int(r[1]) == 0
+            assert int(r[2]) == nc - int(r[1])
+            assert int(r[0]) == (1 if i % 2 == 1 else 0)
+
+
+def test_degrees_match_oracle(exe):
+    g = wl.rng(2)
+    k = 300
+    res = 10.0 ** g.uniform(-13, 0, k)
+    ritz = g.uniform(-1.5, 1.2, k)
+    c, e, tol = 0.8, 1.1, 1e-10
+    text = f"degrees {k} {tol!r} {c!r} {e!r} 2 36 " + " ".join(f"{float(r)!r} {float(l)!r}" for r, l in zip(res, ritz))
+    got = np.array([int(x) for x in _run(exe, text).split()])
+    ref = och.degrees(tol, res, ritz, c, e, 2, 36)
+    assert np.array_equal(got, ref)
+
+
+def test_tridiagonal_eigensolver_and_dos_match_oracle(exe):
+    n = 500
+    g = wl.rng(3)
+    lam = wl.spectrum_uniform(n, g)
+    A = wl.hermitian_from(wl.haar_unitary(n, g), lam)
+    nv, k = 4, 25
+    al = np.zeros((k, nv))
+    be = np.zeros((k, nv))
+    runs = []
+    for c in range(nv):
+        a, b, _ = lz.lanczos_run(A, wl.complex_gaussian(g, n), k)
+        al[:, c], be[:, c] = a, b
+        runs.append((a, b))
+    flat = " ".join(f"{float(x)!r}" for x in al.ravel()) + " " + " ".join(f"{float(x)!r}" for x in be.ravel())
+    out = _run(exe, f"tridiag {nv} {k} " + flat).split()
+    vals = np.array(out, dtype=float).reshape(nv, k, 2)
+    for c in range(nv):
+        ev, S = np.linalg.eigh(lz.tridiagonal(al[:, c], be[:, c]))
+        assert np.allclose(vals[c, :, 0], ev, atol=1e-13)
+        assert np.allclose(vals[c, :, 1], np.abs(S[0, :]) ** 2, atol=1e-12)
+    b_sup = lz.upper_bound(al[:, 0], be[:, 0])
+    mu1_ref, mub_ref = lz.dos_estimates(runs, b_sup, 40, 10, n, 0.25)
+    lo, mub = map(float, _run(exe, f"dos {nv} {k} {float(b_sup)!r} 0.25 {50 / n!r} " + flat).split())
+    assert lo == pytest.approx(mu1_ref, abs=1e-13)
+    assert mub == pytest.approx(mub_ref, abs=1e-9)
