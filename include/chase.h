@@ -43,8 +43,13 @@ typedef enum {
 typedef enum {
   CHASE_FP64 = 0,   /* complex128 buffers, FP64 MFMA with FP64 accumulation                     */
   CHASE_FP32 = 1,   /* complex64 buffers, FP32 MFMA with FP32 accumulation                      */
-  CHASE_MIXED = 2   /* chase_solve only: FP32 filter while a vector's relative residual exceeds
+  CHASE_MIXED = 2,  /* chase_solve only: FP32 filter while a vector's relative residual exceeds
                        switch_resid, FP64 afterwards; everything outside the filter stays FP64 */
+  CHASE_FP32_3M = 3 /* chase_filter / chase_hemm_step: H is "planar complex64" -- two real
+                       n x n FP32 planes, Re H then Im H at an offset of ldh * n floats, each
+                       column-major with leading dimension ldh -- and the products use three
+                       real FP32 MFMA products per complex product (3M) with FP64 sums across
+                       K stages; the blocks are complex64 as for CHASE_FP32 */
 } chase_precision;
 
 /*
@@ -157,7 +162,10 @@ int chase_hemm_step(chase_ctx* ctx, int precision, const void* H, int64_t ldh, i
                     double alpha, double beta, double gamma);
 
 /* Precision staging of the mixed filter: dst = (complex64) src / (complex128) src on a
-   rows x cols column-major block.  Device pointers; enqueues only. */
+   rows x cols column-major block; planar32 writes the n x n matrix as the two FP32 planes of
+   CHASE_FP32_3M (dst: 2 * ld_dst * n floats).  Device pointers; enqueues only. */
+int chase_convert_c128_to_planar32(chase_ctx* ctx, const void* src, int64_t ld_src, void* dst,
+                                   int64_t ld_dst, int64_t n);
 int chase_convert_c128_to_c64(chase_ctx* ctx, const void* src, int64_t ld_src, void* dst,
                               int64_t ld_dst, int64_t rows, int64_t cols);
 int chase_convert_c64_to_c128(chase_ctx* ctx, const void* src, int64_t ld_src, void* dst,

@@ -14,15 +14,25 @@ namespace chase {
 template <typename T>
 hipError_t run_filter(const T* H, int64_t ldh, int64_t n, T* V, T* W, int64_t ld, int64_t ncols,
                       const int32_t* degrees, double b_sup, double mu_1, double mu_nevnex,
-                      const ProductScratch& ps, hipStream_t stream, int64_t* matvecs_out) {
+                      const ProductScratch& ps, hipStream_t stream, int64_t* matvecs_out,
+                      int kind) {
   int64_t matvecs = 0;
   if (ncols > 0 && n > 0) {
     for (const FilterProduct& p : filter_schedule(ncols, degrees, b_sup, mu_1, mu_nevnex)) {
       const T* X = (p.from_v ? V : W) + 2 * p.col0 * ld;
       T* OUT = (p.from_v ? W : V) + 2 * p.col0 * ld;
-      hipError_t err = launch_hemm_step<T>(H, ldh, n, X, ld, OUT, ld, p.ncols,
-                                           static_cast<T>(p.alpha), static_cast<T>(p.beta),
-                                           static_cast<T>(p.gamma), ps, stream);
+      hipError_t err;
+      if constexpr (sizeof(T) == 4) {
+        if (kind == 2)
+          err = launch_hemm_step_3m(H, ldh, n, X, ld, OUT, ld, p.ncols, static_cast<T>(p.alpha),
+                                    static_cast<T>(p.beta), static_cast<T>(p.gamma), ps, stream);
+        else
+          err = launch_hemm_step<T>(H, ldh, n, X, ld, OUT, ld, p.ncols, static_cast<T>(p.alpha),
+                                    static_cast<T>(p.beta), static_cast<T>(p.gamma), ps, stream);
+      } else {
+        err = launch_hemm_step<T>(H, ldh, n, X, ld, OUT, ld, p.ncols, static_cast<T>(p.alpha),
+                                  static_cast<T>(p.beta), static_cast<T>(p.gamma), ps, stream);
+      }
       if (err != hipSuccess) return err;
       matvecs += p.ncols;
     }
@@ -33,9 +43,9 @@ hipError_t run_filter(const T* H, int64_t ldh, int64_t n, T* V, T* W, int64_t ld
 
 template hipError_t run_filter<double>(const double*, int64_t, int64_t, double*, double*, int64_t,
                                        int64_t, const int32_t*, double, double, double,
-                                       const ProductScratch&, hipStream_t, int64_t*);
+                                       const ProductScratch&, hipStream_t, int64_t*, int);
 template hipError_t run_filter<float>(const float*, int64_t, int64_t, float*, float*, int64_t,
                                       int64_t, const int32_t*, double, double, double,
-                                      const ProductScratch&, hipStream_t, int64_t*);
+                                      const ProductScratch&, hipStream_t, int64_t*, int);
 
 }  // namespace chase

@@ -69,6 +69,7 @@ constexpr int kThreads = 256;
 // dot product (FP32 products, FP64 sums across stages).
 template <typename T, int BMC_, int BNC_, int KT_, int WR_, int WC_, int PAD_ = 2, int PROMOTE_ = 0>
 struct Tile {
+  static constexpr int KIND = 0;  // 4M real embedding of interleaved complex H
   static constexpr int BMC = BMC_, BNC = BNC_, KT = KT_, WR = WR_, WC = WC_;
   static constexpr int PROMOTE = PROMOTE_;
   static constexpr int RT = BMC / WR / 8;
@@ -100,7 +101,7 @@ struct Tile {
 // V16 (complex64 only): global loads of two consecutive complex elements (16 bytes); the caller
 // guarantees 16-byte aligned H and X and even leading dimensions.
 template <typename T, class C, bool V16 = false>
-__device__ __forceinline__ void tile_mainloop(typename C::Smem& sm, typename C::Frag& f,
+__device__ __forceinline__ void tile_mainloop_4m(typename C::Smem& sm, typename C::Frag& f,
                                               const T* __restrict__ H, int64_t ldh, int n,
                                               const T* __restrict__ X, int64_t ldx, int ncols,
                                               int i0, int j0, int ka, int kb) {
@@ -232,7 +233,7 @@ __device__ __forceinline__ void tile_mainloop(typename C::Smem& sm, typename C::
 
 // Visit the complex results held by this lane: fn(row_in_tile, col_in_tile, re, im).
 template <typename T, class C, typename Fn>
-__device__ __forceinline__ void tile_foreach(const typename C::Frag& f, Fn&& fn) {
+__device__ __forceinline__ void tile_foreach_4m(const typename C::Frag& f, Fn&& fn) {
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, li = lane & 15;
@@ -255,6 +256,228 @@ __device__ __forceinline__ void tile_foreach(const typename C::Frag& f, Fn&& fn)
           fn(r, c, hre, him);
         }
       }
+}
+
+// 3M complex product on FP32 MFMA (complex64 data, H stored as two real planes: Re H, then
+// Im H at an offset of ldh * n floats).  With T1 = ReH ReX, T2 = ImH ImX and
+// T3 = (ReH + ImH)(ReX + ImX):  Re(HX) = T1 - T2, Im(HX) = T3 - T1 - T2 -- three real products
+// (6 real flops per complex multiply-add) instead of four.  The sums ReH + ImH and ReX + ImX
+// are formed in registers from the LDS planes.  Accumulators are promoted to FP64 every
+// PROMOTE stages (see Tile).  Each wave owns RT x CG MFMA tiles of 16 x 16 complex outputs.
+template <int BMC_, int BNC_, int KT_, int WR_, int WC_, int PAD_ = 4, int PROMOTE_ = 1>
+struct Tile3M {
+  static constexpr int KIND = 1;
+  static constexpr int BMC = BMC_, BNC = BNC_, KT = KT_, WR = WR_, WC = WC_;
+  static constexpr int PROMOTE = PROMOTE_;
+  static constexpr int RT = BMC / WR / 16;
+  static constexpr int CG = BNC / WC / 16;
+  static constexpr int AR = BMC + PAD_;
+  static constexpr int BR = BNC + PAD_;
+  static_assert(WR * WC == 4 && RT >= 1 && CG >= 1, "wave grid");
+  static_assert((AR * 4) % 16 == 0, "16-byte LDS rows");
+  using acc_t = f4_t;
+  using v2 = float2;
+  struct Smem {
+    float Are[2][KT][AR];
+    float Aim[2][KT][AR];
+    float Bre[2][KT][BR];
+    float Bim[2][KT][BR];
+  };
+  struct Frag64 {
+    acc_t acc[RT][CG][3];
+    double acc64[RT][CG][3][4];
+  };
+  struct Frag32 {
+    acc_t acc[RT][CG][3];
+  };
+  using Frag = typename std::conditional<(PROMOTE_ > 0), Frag64, Frag32>::type;
+};
+
+template <class C, bool V16>
+__device__ __forceinline__ void tile_mainloop_3m(typename C::Smem& sm, typename C::Frag& f,
+                                                 const float* __restrict__ H, int64_t ldh, int n,
+                                                 const float* __restrict__ X, int64_t ldx,
+                                                 int ncols, int i0, int j0, int ka, int kb) {
+  using acc_t = f4_t;
+  constexpr int AV = V16 ? 4 : 1;  // floats per A load (4 consecutive rows of one plane)
+  constexpr int BV = V16 ? 2 : 1;  // complex elements per X load
+  constexpr int A_LD = C::BMC * C::KT / (kThreads * AV);
+  constexpr int B_LD = C::BNC * C::KT / (kThreads * BV);
+  static_assert(A_LD * kThreads * AV == C::BMC * C::KT, "A split");
+  static_assert(B_LD * kThreads * BV == C::BNC * C::KT, "B split");
+  struct alignas(16) AL { float e[AV]; };
+  struct alignas(16) BL { float2 e[BV]; };
+  const float* __restrict__ Hi = H + ldh * static_cast<int64_t>(n);
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 4, li = lane & 15;
+  const int wr = wave / C::WC, wc = wave % C::WC;
+  AL rar[A_LD], rai[A_LD];
+  BL rb[B_LD];
+
+  auto load_tiles = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < A_LD; ++q) {
+      const int idx = tid + kThreads * q;
+      const int kk = idx / (C::BMC / AV), ri = (idx % (C::BMC / AV)) * AV;
+      const int row = i0 + ri, col = k0 + kk;
+      const int64_t off = static_cast<int64_t>(row) + static_cast<int64_t>(col) * ldh;
+      if (col < n && row + AV - 1 < n) {
+        rar[q] = *reinterpret_cast<const AL*>(H + off);
+        rai[q] = *reinterpret_cast<const AL*>(Hi + off);
+      } else {
+#pragma unroll
+        for (int e = 0; e < AV; ++e) {
+          const bool ok = col < n && row + e < n;
+          rar[q].e[e] = ok ? H[off + e] : 0.f;
+          rai[q].e[e] = ok ? Hi[off + e] : 0.f;
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < B_LD; ++q) {
+      const int idx = tid + kThreads * q;
+      const int jj = idx / (C::KT / BV), kk = (idx % (C::KT / BV)) * BV;
+      const int row = k0 + kk, col = j0 + jj;
+      const float* src = X + 2 * (static_cast<int64_t>(row) + static_cast<int64_t>(col) * ldx);
+      if (col < ncols && row + BV - 1 < n) {
+        rb[q] = *reinterpret_cast<const BL*>(src);
+      } else {
+#pragma unroll
+        for (int e = 0; e < BV; ++e)
+          rb[q].e[e] = (col < ncols && row + e < n) ? reinterpret_cast<const float2*>(src)[e]
+                                                     : float2{0.f, 0.f};
+      }
+    }
+  };
+  auto store_tiles = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < A_LD; ++q) {
+      const int idx = tid + kThreads * q;
+      const int kk = idx / (C::BMC / AV), ri = (idx % (C::BMC / AV)) * AV;
+      *reinterpret_cast<AL*>(&sm.Are[buf][kk][ri]) = rar[q];
+      *reinterpret_cast<AL*>(&sm.Aim[buf][kk][ri]) = rai[q];
+    }
+#pragma unroll
+    for (int q = 0; q < B_LD; ++q) {
+      const int idx = tid + kThreads * q;
+      const int jj = idx / (C::KT / BV), kk = (idx % (C::KT / BV)) * BV;
+#pragma unroll
+      for (int e = 0; e < BV; ++e) {
+        sm.Bre[buf][kk + e][jj] = rb[q].e[e].x;
+        sm.Bim[buf][kk + e][jj] = rb[q].e[e].y;
+      }
+    }
+  };
+
+#pragma unroll
+  for (int a = 0; a < C::RT; ++a)
+#pragma unroll
+    for (int b = 0; b < C::CG; ++b)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        f.acc[a][b][c] = acc_t{0};
+        if constexpr (C::PROMOTE > 0) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) f.acc64[a][b][c][e] = 0.0;
+        }
+      }
+
+  const int rbase = wr * (C::BMC / C::WR);
+  const int cbase = wc * (C::BNC / C::WC);
+  load_tiles(ka * C::KT);
+  store_tiles(0);
+  __syncthreads();
+  for (int kt = ka; kt < kb; ++kt) {
+    const int cur = (kt - ka) & 1;
+    if (kt + 1 < kb) load_tiles((kt + 1) * C::KT);
+#pragma unroll
+    for (int s = 0; s < C::KT / 4; ++s) {
+      const int k = 4 * s + g;
+      float ar[C::RT], ai[C::RT], as[C::RT], br[C::CG], bi[C::CG], bs[C::CG];
+#pragma unroll
+      for (int rt = 0; rt < C::RT; ++rt) {
+        ar[rt] = sm.Are[cur][k][rbase + rt * 16 + li];
+        ai[rt] = sm.Aim[cur][k][rbase + rt * 16 + li];
+        as[rt] = ar[rt] + ai[rt];
+      }
+#pragma unroll
+      for (int cg = 0; cg < C::CG; ++cg) {
+        br[cg] = sm.Bre[cur][k][cbase + cg * 16 + li];
+        bi[cg] = sm.Bim[cur][k][cbase + cg * 16 + li];
+        bs[cg] = br[cg] + bi[cg];
+      }
+#pragma unroll
+      for (int rt = 0; rt < C::RT; ++rt)
+#pragma unroll
+        for (int cg = 0; cg < C::CG; ++cg) {
+          f.acc[rt][cg][0] = mfma(ar[rt], br[cg], f.acc[rt][cg][0]);
+          f.acc[rt][cg][1] = mfma(ai[rt], bi[cg], f.acc[rt][cg][1]);
+          f.acc[rt][cg][2] = mfma(as[rt], bs[cg], f.acc[rt][cg][2]);
+        }
+    }
+    if constexpr (C::PROMOTE > 0) {
+      if ((kt - ka + 1) % C::PROMOTE == 0 || kt + 1 == kb) {
+#pragma unroll
+        for (int a = 0; a < C::RT; ++a)
+#pragma unroll
+          for (int b = 0; b < C::CG; ++b)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+#pragma unroll
+              for (int e = 0; e < 4; ++e) f.acc64[a][b][c][e] += static_cast<double>(f.acc[a][b][c][e]);
+              f.acc[a][b][c] = acc_t{0};
+            }
+      }
+    }
+    if (kt + 1 < kb) store_tiles(cur ^ 1);
+    __syncthreads();
+  }
+}
+
+template <class C, typename Fn>
+__device__ __forceinline__ void tile_foreach_3m(const typename C::Frag& f, Fn&& fn) {
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 4, li = lane & 15;
+  const int wr = wave / C::WC, wc = wave % C::WC;
+#pragma unroll
+  for (int rt = 0; rt < C::RT; ++rt)
+#pragma unroll
+    for (int cg = 0; cg < C::CG; ++cg)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = wr * (C::BMC / C::WR) + rt * 16 + 4 * g + r;
+        const int col = wc * (C::BNC / C::WC) + cg * 16 + li;
+        if constexpr (C::PROMOTE > 0) {
+          const double t1 = f.acc64[rt][cg][0][r], t2 = f.acc64[rt][cg][1][r];
+          const double t3 = f.acc64[rt][cg][2][r];
+          fn(row, col, static_cast<float>(t1 - t2), static_cast<float>(t3 - t1 - t2));
+        } else {
+          const float t1 = f.acc[rt][cg][0][r], t2 = f.acc[rt][cg][1][r], t3 = f.acc[rt][cg][2][r];
+          fn(row, col, t1 - t2, t3 - t1 - t2);
+        }
+      }
+}
+
+// Dispatch on the tile kind (4M interleaved or 3M planar).
+template <typename T, class C, bool V16 = false>
+__device__ __forceinline__ void tile_mainloop(typename C::Smem& sm, typename C::Frag& f,
+                                              const T* __restrict__ H, int64_t ldh, int n,
+                                              const T* __restrict__ X, int64_t ldx, int ncols,
+                                              int i0, int j0, int ka, int kb) {
+  if constexpr (C::KIND == 1)
+    tile_mainloop_3m<C, V16>(sm, f, H, ldh, n, X, ldx, ncols, i0, j0, ka, kb);
+  else
+    tile_mainloop_4m<T, C, V16>(sm, f, H, ldh, n, X, ldx, ncols, i0, j0, ka, kb);
+}
+
+template <typename T, class C, typename Fn>
+__device__ __forceinline__ void tile_foreach(const typename C::Frag& f, Fn&& fn) {
+  if constexpr (C::KIND == 1)
+    tile_foreach_3m<C>(f, fn);
+  else
+    tile_foreach_4m<T, C>(f, fn);
 }
 
 // OUT <- alpha*HX + gamma*X + beta*OUT at (row, col); OUT is not read when beta == 0.
@@ -498,6 +721,9 @@ namespace {
 template <typename T> using WideTile = Tile<T, 64, 64, 16, 2, 2, sizeof(T) == 4 ? 8 : 2>;
 template <typename T> using NarrowTile = Tile<T, 64, 32, 16, 4, 1, sizeof(T) == 4 ? 8 : 2>;
 
+// 3M tile for the planar FP32 products (FP64 promotion every stage).
+using Wide3M = Tile3M<64, 64, 16, 2, 2, 4, 1>;
+
 // Two-element (16-byte) global loads are used for complex64 data when H and X are 16-byte
 // aligned and their leading dimensions are even.
 template <typename T>
@@ -510,12 +736,12 @@ constexpr int kOcc = 2;  // workgroups per CU the tiles are built for
 template <typename T, class C>
 hipError_t launch_sched(const T* H, int64_t ldh, int64_t n, const T* X, int64_t ldx, T* OUT,
                         int64_t ldo, int64_t ncols, T alpha, T beta, T gamma,
-                        const ProductScratch& ps, hipStream_t stream) {
+                        const ProductScratch& ps, hipStream_t stream, bool v16_ok = true) {
   const int64_t tiles = ((n + C::BMC - 1) / C::BMC) * ((ncols + C::BNC - 1) / C::BNC);
   const int64_t slots = static_cast<int64_t>(ps.cus) * kOcc;
   const int64_t rounds = (tiles + slots - 1) / slots;
   const double eff = static_cast<double>(tiles) / static_cast<double>(rounds * slots);
-  const bool v16 = use_v16(H, ldh, X, ldx);
+  const bool v16 = v16_ok && use_v16(H, ldh, X, ldx);
   if (eff >= 0.92 || !ps.ptr || sk_scratch_bytes<T, C>(slots) > ps.bytes) {
     if (v16)
       return launch_dp<T, C, kOcc, true>(H, ldh, n, X, ldx, OUT, ldo, ncols, alpha, beta, gamma,
@@ -581,6 +807,43 @@ hipError_t launch_hemm_group(const GroupDesc<T>* descs, int count, hipStream_t s
 template hipError_t launch_hemm_group<double>(const GroupDesc<double>*, int, hipStream_t);
 template hipError_t launch_hemm_group<float>(const GroupDesc<float>*, int, hipStream_t);
 
+hipError_t launch_hemm_step_3m(const float* H, int64_t ldh, int64_t n, const float* X,
+                               int64_t ldx, float* OUT, int64_t ldo, int64_t ncols, float alpha,
+                               float beta, float gamma, const ProductScratch& ps,
+                               hipStream_t stream) {
+  if (n <= 0 || ncols <= 0) return hipSuccess;
+  // vector loads of four rows per plane need ldh % 4 == 0 on top of the usual conditions
+  return launch_sched<float, Wide3M>(H, ldh, n, X, ldx, OUT, ldo, ncols, alpha, beta, gamma, ps,
+                                     stream, ldh % 4 == 0);
+}
+
+hipError_t launch_hemm_group_3m(const GroupDesc<float>* descs, int count, hipStream_t stream) {
+  for (int base = 0; base < count; base += kMaxGroup) {
+    GroupArgs<float> a{};
+    a.count = std::min(kMaxGroup, count - base);
+    int64_t tiles = 0;
+    bool v16 = true;
+    for (int q = 0; q < a.count; ++q) {
+      a.d[q] = descs[base + q];
+      a.d[q].tile_begin = static_cast<int>(tiles);
+      tiles += ((a.d[q].n + Wide3M::BMC - 1) / Wide3M::BMC) *
+               static_cast<int64_t>((a.d[q].ncols + Wide3M::BNC - 1) / Wide3M::BNC);
+      v16 = v16 && a.d[q].ldh % 4 == 0 && use_v16(a.d[q].H, a.d[q].ldh, a.d[q].X, a.d[q].ldx);
+    }
+    if (tiles == 0) continue;
+    if (tiles > 0x7fffffff) return hipErrorInvalidValue;
+    if (v16)
+      hipLaunchKernelGGL((hemm_group_kernel<float, Wide3M, kOcc, true>),
+                         dim3(static_cast<unsigned>(tiles)), dim3(kThreads), 0, stream, a);
+    else
+      hipLaunchKernelGGL((hemm_group_kernel<float, Wide3M, kOcc, false>),
+                         dim3(static_cast<unsigned>(tiles)), dim3(kThreads), 0, stream, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 template hipError_t launch_hemm_step<double>(const double*, int64_t, int64_t, const double*,
                                              int64_t, double*, int64_t, int64_t, double, double,
                                              double, const ProductScratch&, hipStream_t);
@@ -600,6 +863,29 @@ hipError_t launch_convert_c128_to_c64(const double* src, int64_t lds, float* dst
   if (rows <= 0 || cols <= 0) return hipSuccess;
   hipLaunchKernelGGL((convert_kernel<double, float>), dim3(convert_blocks(rows * cols)), dim3(256),
                      0, stream, src, lds, dst, ldd, rows, cols);
+  return hipGetLastError();
+}
+
+namespace {
+__global__ void planar_kernel(const double* __restrict__ src, int64_t lds, float* __restrict__ dst,
+                              int64_t ldd, int64_t n) {
+  const int64_t total = n * n;
+  float* im = dst + ldd * n;
+  for (int64_t t = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; t < total;
+       t += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int64_t r = t % n, c = t / n;
+    const double* s = src + 2 * (r + c * lds);
+    dst[r + c * ldd] = static_cast<float>(s[0]);
+    im[r + c * ldd] = static_cast<float>(s[1]);
+  }
+}
+}  // namespace
+
+hipError_t launch_convert_c128_to_planar32(const double* src, int64_t lds, float* dst, int64_t ldd,
+                                           int64_t n, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(planar_kernel, dim3(convert_blocks(n * n)), dim3(256), 0, stream, src, lds,
+                     dst, ldd, n);
   return hipGetLastError();
 }
 

@@ -53,6 +53,15 @@ struct GroupArgs {
 template <typename T>
 hipError_t launch_hemm_group(const GroupDesc<T>* descs, int count, hipStream_t stream);
 
+// 3M products on planar complex64 H (Re plane, then Im plane at H + ldh * n).
+hipError_t launch_hemm_step_3m(const float* H, int64_t ldh, int64_t n, const float* X,
+                               int64_t ldx, float* OUT, int64_t ldo, int64_t ncols, float alpha,
+                               float beta, float gamma, const ProductScratch& ps,
+                               hipStream_t stream);
+hipError_t launch_hemm_group_3m(const GroupDesc<float>* descs, int count, hipStream_t stream);
+hipError_t launch_convert_c128_to_planar32(const double* src, int64_t lds, float* dst, int64_t ldd,
+                                           int64_t n, hipStream_t stream);
+
 hipError_t launch_convert_c128_to_c64(const double* src, int64_t lds, float* dst, int64_t ldd,
                                       int64_t rows, int64_t cols, hipStream_t stream);
 hipError_t launch_convert_c64_to_c128(const float* src, int64_t lds, double* dst, int64_t ldd,
@@ -76,10 +85,12 @@ hipError_t launch_gaussian(double* X, int64_t n, int64_t ld, int64_t cols, uint6
 
 // Algorithm 4 on an n x ncols block with sorted even degrees (validated by the caller).  The
 // result ends in V.  scalars: the per-product (alpha, beta, gamma) in FP64.
+// kind: 0 complex128 (4M), 1 complex64 interleaved (4M), 2 complex64 planar H (3M).
 template <typename T>
 hipError_t run_filter(const T* H, int64_t ldh, int64_t n, T* V, T* W, int64_t ld, int64_t ncols,
                       const int32_t* degrees, double b_sup, double mu_1, double mu_nevnex,
-                      const ProductScratch& ps, hipStream_t stream, int64_t* matvecs_out);
+                      const ProductScratch& ps, hipStream_t stream, int64_t* matvecs_out,
+                      int kind = 0);
 
 // Continuous batching of filter products across concurrent solves: the products of every
 // submitted filter call advance one per tick, each tick being one grouped launch per precision
@@ -93,7 +104,8 @@ class Batcher {
   // `caller` wait for their completion.  fp64: complex128 data, else complex64.  `ready` and
   // `done` are events owned by the caller (reused across calls, destroyed only after the
   // caller's stream has drained).
-  hipError_t run(bool fp64, const void* H, int64_t ldh, int64_t n, void* V, void* W, int64_t ld,
+  // kind: 0 complex128, 1 complex64 interleaved H, 2 complex64 planar H (3M).
+  hipError_t run(int kind, const void* H, int64_t ldh, int64_t n, void* V, void* W, int64_t ld,
                  const std::vector<FilterProduct>& prods, hipStream_t caller, hipEvent_t ready,
                  hipEvent_t done);
   void counters(int64_t* launches, int64_t* products) const;

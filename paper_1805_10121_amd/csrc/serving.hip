@@ -30,7 +30,7 @@
 namespace chase {
 
 struct Batcher::Job {
-  bool fp64;
+  int kind;  // 0 complex128, 1 complex64 interleaved H, 2 complex64 planar H (3M)
   const void* H;
   int64_t ldh, n, ld;
   void* V;
@@ -96,12 +96,12 @@ void Batcher::counters(int64_t* launches, int64_t* products) const {
   if (products) *products = impl_->products;
 }
 
-hipError_t Batcher::run(bool fp64, const void* H, int64_t ldh, int64_t n, void* V, void* W,
+hipError_t Batcher::run(int kind, const void* H, int64_t ldh, int64_t n, void* V, void* W,
                         int64_t ld, const std::vector<FilterProduct>& prods, hipStream_t caller,
                         hipEvent_t ready, hipEvent_t done) {
   if (prods.empty()) return hipSuccess;
   Job job;
-  job.fp64 = fp64;
+  job.kind = kind;
   job.H = H;
   job.ldh = ldh;
   job.n = n;
@@ -133,10 +133,10 @@ hipError_t Batcher::Impl::tick_once() {
     if (e != hipSuccess) return e;
   }
   std::vector<GroupDesc<double>> d64;
-  std::vector<GroupDesc<float>> d32;
+  std::vector<GroupDesc<float>> d32, d3m;
   for (Job* j : active) {
     const FilterProduct& p = (*j->prods)[j->next];
-    if (j->fp64) {
+    if (j->kind == 0) {
       const double* V = static_cast<const double*>(j->V);
       const double* W = static_cast<const double*>(j->W);
       GroupDesc<double> d{};
@@ -165,7 +165,7 @@ hipError_t Batcher::Impl::tick_once() {
       d.alpha = static_cast<float>(p.alpha);
       d.beta = static_cast<float>(p.beta);
       d.gamma = static_cast<float>(p.gamma);
-      d32.push_back(d);
+      (j->kind == 2 ? d3m : d32).push_back(d);
     }
     ++j->next;
   }
@@ -173,14 +173,16 @@ hipError_t Batcher::Impl::tick_once() {
   if (!d64.empty()) e = launch_hemm_group<double>(d64.data(), static_cast<int>(d64.size()), stream);
   if (e == hipSuccess && !d32.empty())
     e = launch_hemm_group<float>(d32.data(), static_cast<int>(d32.size()), stream);
+  if (e == hipSuccess && !d3m.empty())
+    e = launch_hemm_group_3m(d3m.data(), static_cast<int>(d3m.size()), stream);
   if (e == hipSuccess) e = hipEventRecord(tick_ev[slot], stream);
   tick_recorded[slot] = true;
   ++tick;
   {
     std::lock_guard<std::mutex> lk(mu);
-    launches += (d64.empty() ? 0 : (static_cast<int64_t>(d64.size()) + kMaxGroup - 1) / kMaxGroup) +
-                (d32.empty() ? 0 : (static_cast<int64_t>(d32.size()) + kMaxGroup - 1) / kMaxGroup);
-    products += static_cast<int64_t>(d64.size() + d32.size());
+    auto nl = [](size_t c) { return static_cast<int64_t>((c + kMaxGroup - 1) / kMaxGroup); };
+    launches += nl(d64.size()) + nl(d32.size()) + nl(d3m.size());
+    products += static_cast<int64_t>(d64.size() + d32.size() + d3m.size());
   }
   return e;
 }

@@ -336,12 +336,12 @@ int Solver::filter(const double* H, int64_t ldh, int64_t nlock, int64_t nact,
       const auto prods = filter_schedule(n32, m.data(), b_sup_, mu_1_, mu_b_);
       mv = 0;
       for (const auto& p : prods) mv += p.ncols;
-      rc = hip(batcher_->run(false, at<float>(L_.H32), n_, n_, V32, at<float>(L_.W32), n_, prods,
+      rc = hip(batcher_->run(2, at<float>(L_.H32), n_, n_, V32, at<float>(L_.W32), n_, prods,
                              s_, bev_[0], bev_[1]),
                "batched filter fp32");
     } else {
       rc = hip(run_filter<float>(at<float>(L_.H32), n_, n_, V32, at<float>(L_.W32), n_, n32,
-                                 m.data(), b_sup_, mu_1_, mu_b_, ctx_->prod, s_, &mv),
+                                 m.data(), b_sup_, mu_1_, mu_b_, ctx_->prod, s_, &mv, 2),
                "filter fp32");
     }
     if (rc) return rc;
@@ -354,7 +354,7 @@ int Solver::filter(const double* H, int64_t ldh, int64_t nlock, int64_t nact,
       const auto prods = filter_schedule(nact - n32, m.data() + n32, b_sup_, mu_1_, mu_b_);
       mv = 0;
       for (const auto& p : prods) mv += p.ncols;
-      rc = hip(batcher_->run(true, H, ldh, n_, col(L_.V, nlock + n32), col(L_.W, nlock + n32), n_,
+      rc = hip(batcher_->run(0, H, ldh, n_, col(L_.V, nlock + n32), col(L_.W, nlock + n32), n_,
                              prods, s_, bev_[0], bev_[1]),
                "batched filter fp64");
     } else {
@@ -418,7 +418,7 @@ int Solver::run(const void* Hv, int64_t ldh, void* Vuser, int64_t ldv, double* r
                                  hipMemcpyDeviceToDevice, s_),
                 "copy V")))
     return rc;
-  if (mixed && (rc = hip(launch_convert_c128_to_c64(H, ldh, at<float>(L_.H32), n_, n_, n_, s_),
+  if (mixed && (rc = hip(launch_convert_c128_to_planar32(H, ldh, at<float>(L_.H32), n_, n_, s_),
                          "convert H")))
     return rc;
 

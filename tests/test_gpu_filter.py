@@ -287,3 +287,51 @@ def test_filter_fp32_ragged_rows_and_leading_dimension(ctx, n, ld):
     err = _relerr(got, ref)
     print(f"fp32 n={n} ld={ld} block-relative error {err:.3e}")
     assert err <= 2e-5
+
+
+@pytest.mark.parametrize("n,ld", [(1000, 1000), (333, 333), (1024, 1024), (515, 516)])
+def test_filter_fp32_3m_parity(ctx, n, ld):
+    """3M products on planar complex64 H (three FP32 MFMA products per complex product, FP64
+    sums across K stages) against the FP64 oracle."""
+    import torch
+    from paper_1805_10121_amd import capi
+
+    nb = 70
+    deg = wl.optimized_degree_profile(nb, 18)
+    lam, H, V = _problem(n, nb, 5000 + n)
+    b_sup, mu_1, mu_b = 2.02, lam[0], lam[n // 15]
+    ref = ch.filter_columns(H, V, deg, b_sup, mu_1, mu_b)
+    Hp = np.zeros((ld, n), dtype=np.complex128)
+    Hp[:n] = H
+    dH = capi.to_device(Hp)
+    planes = torch.empty(2 * ld * n, dtype=torch.float32, device="cuda")
+    ctx.chase_convert_c128_to_planar32(dH, ld, planes, ld, n)
+    v32 = torch.empty((nb, n), dtype=torch.complex64, device="cuda")
+    dV = capi.to_device(V)
+    ctx.chase_convert_c128_to_c64(dV, n, v32, n, n, nb)
+    w32 = torch.empty_like(v32)
+    ctx.chase_filter(capi.CHASE_FP32_3M, planes, ld, n, v32, w32, n, nb, deg, b_sup, mu_1, mu_b)
+    ctx.chase_convert_c64_to_c128(v32, n, dV, n, n, nb)
+    torch.cuda.synchronize()
+    err = _relerr(capi.from_device(dV), ref)
+    print(f"fp32 3M n={n} ld={ld} block-relative error {err:.3e}")
+    assert err <= 2e-5
+
+
+def test_hemm_step_3m_single_product(ctx):
+    import torch
+    from paper_1805_10121_amd import capi
+
+    n, nb = 777, 45
+    _, H, X = _problem(n, nb, 99)
+    Y = wl.complex_gaussian(wl.rng(7), n, nb)
+    ref = ch.product(H, X, Y, 0.9, -0.4, 0.3)
+    dH = capi.to_device(H)
+    planes = torch.empty(2 * n * n, dtype=torch.float32, device="cuda")
+    ctx.chase_convert_c128_to_planar32(dH, n, planes, n, n)
+    x32 = capi.to_device(X.astype(np.complex64))
+    o32 = capi.to_device(Y.astype(np.complex64))
+    ctx.chase_hemm_step(capi.CHASE_FP32_3M, planes, n, n, x32, n, o32, n, nb, 0.9, -0.4, 0.3)
+    torch.cuda.synchronize()
+    got = capi.from_device(o32).astype(np.complex128)
+    assert np.max(np.abs(got - ref)) <= 1e-5 * np.max(np.abs(ref))
