@@ -108,7 +108,9 @@ __device__ __forceinline__ void tile_mainloop_4m(typename C::Smem& sm, typename 
   using v2 = typename C::v2;
   using acc_t = typename C::acc_t;
   constexpr int VEC = (V16 && sizeof(T) == 4) ? 2 : 1;  // complex elements per global load
-  struct alignas(16) VL { v2 e[VEC]; };
+  // exactly VEC elements: alignment = size, so a copy never touches a neighbour
+  struct alignas(sizeof(v2) * VEC) VL { v2 e[VEC]; };
+  static_assert(sizeof(VL) == sizeof(v2) * VEC, "load unit size");
   constexpr int A_LD = C::BMC * C::KT / (kThreads * VEC);
   constexpr int B_LD = C::BNC * C::KT / (kThreads * VEC);
   static_assert(A_LD * kThreads * VEC == C::BMC * C::KT, "A load split");
@@ -305,8 +307,11 @@ __device__ __forceinline__ void tile_mainloop_3m(typename C::Smem& sm, typename 
   constexpr int B_LD = C::BNC * C::KT / (kThreads * BV);
   static_assert(A_LD * kThreads * AV == C::BMC * C::KT, "A split");
   static_assert(B_LD * kThreads * BV == C::BNC * C::KT, "B split");
-  struct alignas(16) AL { float e[AV]; };
-  struct alignas(16) BL { float2 e[BV]; };
+  // exactly AV floats / BV complex elements: alignment = size, so a copy never touches a
+  // neighbour
+  struct alignas(4 * AV) AL { float e[AV]; };
+  struct alignas(8 * BV) BL { float2 e[BV]; };
+  static_assert(sizeof(AL) == 4 * AV && sizeof(BL) == 8 * BV, "load unit size");
   const float* __restrict__ Hi = H + ldh * static_cast<int64_t>(n);
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;

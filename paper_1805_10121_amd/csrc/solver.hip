@@ -456,7 +456,7 @@ int Solver::run(const void* Hv, int64_t ldh, void* Vuser, int64_t ldv, double* r
   std::vector<int> prec(nb_, mixed ? 1 : 0);
   // Mixed mode history, indexed by ascending Ritz rank among the active pairs: last residual,
   // whether that pair was filtered in FP32, and a sticky FP64 flag set when an FP32 iteration
-  // reduced the residual by less than 10x (the FP32 filter's accuracy floor was reached).
+  // failed to halve the residual (the FP32 filter's accuracy floor was reached).
   std::vector<double> hist_res(nb_, INFINITY);
   std::vector<char> hist_fp32(nb_, mixed ? 1 : 0), lock64(nb_, 0);
   std::vector<double> lam_act(nb_, 0.0), res_act(nb_, 0.0), lam_lock, res_lock;
@@ -557,7 +557,7 @@ int Solver::run(const void* Hv, int64_t ldh, void* Vuser, int64_t ldv, double* r
     for (int64_t q = 0; q < rem; ++q) {
       const int64_t r = n_new + q;
       const int a = order[r];
-      const bool stuck = mixed && hist_fp32[r] && res_act[a] > 0.1 * hist_res[r];
+      const bool stuck = mixed && hist_fp32[r] && res_act[a] > 0.5 * hist_res[r];
       const bool l64 = lock64[r] || stuck;
       const bool fp32 = mixed && !l64 && res_act[a] > tol32;
       pnew[q] = fp32 ? 1 : 0;
