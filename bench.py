@@ -119,8 +119,17 @@ def run_sequence(args):
     norm = float(np.max(np.abs(lam)))
     ctx = capi.Context(0)
     res = {}
-    for mode, prec in (("fp64", capi.CHASE_FP64), ("mixed", capi.CHASE_MIXED)):
+    modes = [] if args.no_fp64_reference else [("fp64", capi.CHASE_FP64, None, None)]
+    for sw in args.switch_resid:
+        for dm in args.deg_max_fp32:
+            name = "mixed" if (len(args.switch_resid) == 1 and len(args.deg_max_fp32) == 1) \
+                else f"mixed sw={sw:g} dm={dm}"
+            modes.append((name, capi.CHASE_MIXED, sw, dm))
+    for mode, prec, sw, dm in modes:
         cfg = capi.config(n, nev, nex, optim=1, precision=prec, seed=3000)
+        if sw is not None:
+            cfg.switch_resid = sw
+            cfg.deg_max_fp32 = dm
         seq = capi.Sequence(ctx, cfg)
         H = None
         per = []
@@ -147,22 +156,24 @@ def run_sequence(args):
         del H
         torch.cuda.empty_cache()
         res[mode] = per
-    diffs = [float(np.max(np.abs(a["ritz"] - b["ritz"])) / norm)
-             for a, b in zip(res["fp64"], res["mixed"])]
-    for mode in res:
-        for p in res[mode]:
+    ref = res.get("fp64")
+    out = {"workload": f"sequence n={n} nev={nev} nex={nex} problems={args.problems} eps={eps}, "
+                       "clustered spectrum (600 clustered values), warm-started, tol 1e-10"}
+    totals = {m: round(sum(p["time_s"] for p in res[m]), 3) for m in res}
+    out["total_s"] = totals
+    if ref is not None:
+        for m in res:
+            if m == "fp64":
+                continue
+            out.setdefault("speedup_vs_fp64", {})[m] = round(totals["fp64"] / totals[m], 3)
+            out.setdefault("max_eig_diff_vs_fp64_over_normH", {})[m] = max(
+                float(np.max(np.abs(a["ritz"] - b["ritz"])) / norm) for a, b in zip(ref, res[m]))
+    for m in res:
+        for p in res[m]:
             p.pop("ritz")
-    t64 = sum(p["time_s"] for p in res["fp64"])
-    tmx = sum(p["time_s"] for p in res["mixed"])
+    out.update(res)
     ctx.close()
-    return {
-        "workload": f"sequence n={n} nev={nev} nex={nex} problems={args.problems} eps={eps}, "
-                    "clustered spectrum (600 clustered values), warm-started, tol 1e-10",
-        "fp64_total_s": round(t64, 3), "mixed_total_s": round(tmx, 3),
-        "mixed_speedup": round(t64 / tmx, 3),
-        "max_eig_diff_mixed_vs_fp64_over_normH": max(diffs),
-        "fp64": res["fp64"], "mixed": res["mixed"],
-    }
+    return out
 
 
 class _SeqSource:
@@ -345,6 +356,11 @@ def main():
                     help="filter: the hot-path benchmark (default); sequence: time-to-solution of "
                          "a warm-started sequence, plain FP64 against the mixed FP32/FP64 filter")
     ap.add_argument("--problems", type=int, default=10)
+    ap.add_argument("--switch-resid", type=float, nargs="*", default=[1e-6],
+                    help="sequence workload: mixed-mode switch thresholds to run")
+    ap.add_argument("--deg-max-fp32", type=int, nargs="*", default=[18],
+                    help="sequence workload: mixed-mode FP32 degree caps to run")
+    ap.add_argument("--no-fp64-reference", action="store_true")
     ap.add_argument("--order", type=int, default=20000)
     ap.add_argument("--h-gen", choices=["haar", "structured"], default="haar",
                     help="H for the filter workload: Haar Q (QR of a Gaussian) or the structured "

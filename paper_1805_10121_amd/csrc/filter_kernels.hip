@@ -726,8 +726,8 @@ namespace {
 template <typename T> using WideTile = Tile<T, 64, 64, 16, 2, 2, sizeof(T) == 4 ? 8 : 2>;
 template <typename T> using NarrowTile = Tile<T, 64, 32, 16, 4, 1, sizeof(T) == 4 ? 8 : 2>;
 
-// 3M tile for the planar FP32 products (FP64 promotion every stage).
-using Wide3M = Tile3M<64, 64, 16, 2, 2, 4, 1>;
+// 3M tile for the planar FP32 products (FP64 promotion every two stages, i.e. every 32 K terms).
+using Wide3M = Tile3M<64, 64, 16, 2, 2, 4, 2>;
 
 // Two-element (16-byte) global loads are used for complex64 data when H and X are 16-byte
 // aligned and their leading dimensions are even.
