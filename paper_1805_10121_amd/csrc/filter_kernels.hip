@@ -67,15 +67,21 @@ constexpr int kThreads = 256;
 // PROMOTE_ > 0 (complex64 only): every PROMOTE_ K stages the FP32 MFMA accumulators are added
 // into FP64 accumulators and cleared, so rounding error stops growing with the length of the
 // dot product (FP32 products, FP64 sums across stages).
-template <typename T, int BMC_, int BNC_, int KT_, int WR_, int WC_, int PAD_ = 2, int PROMOTE_ = 0>
+// BKT_ (B k-major): the B stage is stored one real column per LDS row, KT + 1 values apart, so
+// both the staging stores (consecutive k) and the MFMA operand reads (16 columns at one k) fall
+// in distinct banks; otherwise it is stored one k per row, 2 BNC + PAD_ values apart.
+template <typename T, int BMC_, int BNC_, int KT_, int WR_, int WC_, int PAD_ = 2, int PROMOTE_ = 0,
+          bool BKT_ = false>
 struct Tile {
   static constexpr int KIND = 0;  // 4M real embedding of interleaved complex H
   static constexpr int BMC = BMC_, BNC = BNC_, KT = KT_, WR = WR_, WC = WC_;
   static constexpr int PROMOTE = PROMOTE_;
+  static constexpr bool BKT = BKT_;
   static constexpr int RT = BMC / WR / 8;
   static constexpr int CG = BNC / WC / 16;
   static constexpr int AR = 2 * BMC + PAD_;  // padded real rows per A stage row (k fixed)
   static constexpr int BR = 2 * BNC + PAD_;  // padded real columns per B stage row (k fixed)
+  static constexpr int BK = KT + 1;          // padded k per B stage column (BKT_ layout)
   static constexpr int A_PER = BMC * KT / kThreads;
   static constexpr int B_PER = BNC * KT / kThreads;
   static_assert(WR * WC == 4, "four waves");
@@ -83,10 +89,15 @@ struct Tile {
   static_assert(A_PER * kThreads == BMC * KT && B_PER * kThreads == BNC * KT, "load split");
   using acc_t = typename Acc<T>::type;
   using v2 = typename Acc<T>::v2;
-  struct Smem {
+  struct SmemK {
     T As[2][KT][AR];
     T Bs[2][KT][BR];
   };
+  struct SmemT {
+    T As[2][KT][AR];
+    T Bs[2][2 * BNC][BK];
+  };
+  using Smem = typename std::conditional<BKT_, SmemT, SmemK>::type;
   struct Frag64 {
     acc_t acc[RT][CG][2];
     double acc64[RT][CG][2][4];
@@ -167,8 +178,13 @@ __device__ __forceinline__ void tile_mainloop_4m(typename C::Smem& sm, typename 
       const int jj = idx / (C::KT / VEC), kk = (idx % (C::KT / VEC)) * VEC;
 #pragma unroll
       for (int e = 0; e < VEC; ++e) {
-        sm.Bs[buf][kk + e][jj] = rb[q].e[e].x;
-        sm.Bs[buf][kk + e][C::BNC + jj] = rb[q].e[e].y;
+        if constexpr (C::BKT) {
+          sm.Bs[buf][jj][kk + e] = rb[q].e[e].x;
+          sm.Bs[buf][C::BNC + jj][kk + e] = rb[q].e[e].y;
+        } else {
+          sm.Bs[buf][kk + e][jj] = rb[q].e[e].x;
+          sm.Bs[buf][kk + e][C::BNC + jj] = rb[q].e[e].y;
+        }
       }
     }
   };
@@ -203,8 +219,13 @@ __device__ __forceinline__ void tile_mainloop_4m(typename C::Smem& sm, typename 
       for (int rt = 0; rt < C::RT; ++rt) a[rt] = sm.As[cur][k][rbase + rt * 16 + arow];
 #pragma unroll
       for (int cg = 0; cg < C::CG; ++cg) {
-        b[cg][0] = sm.Bs[cur][k][cbase + cg * 16 + li];
-        b[cg][1] = sm.Bs[cur][k][C::BNC + cbase + cg * 16 + li];
+        if constexpr (C::BKT) {
+          b[cg][0] = sm.Bs[cur][cbase + cg * 16 + li][k];
+          b[cg][1] = sm.Bs[cur][C::BNC + cbase + cg * 16 + li][k];
+        } else {
+          b[cg][0] = sm.Bs[cur][k][cbase + cg * 16 + li];
+          b[cg][1] = sm.Bs[cur][k][C::BNC + cbase + cg * 16 + li];
+        }
       }
 #pragma unroll
       for (int rt = 0; rt < C::RT; ++rt)
