@@ -70,17 +70,22 @@ constexpr int kThreads = 256;
 // BKT_ (B k-major): the B stage is stored one real column per LDS row, KT + 1 values apart, so
 // both the staging stores (consecutive k) and the MFMA operand reads (16 columns at one k) fall
 // in distinct banks; otherwise it is stored one k per row, 2 BNC + PAD_ values apart.
+// PADB_ < 0: the B stage rows use the A padding PAD_.
+// SCHED_ > 0: the LDS stores of the next stage are interleaved with the MFMAs of the last K step
+// of the current one (instead of following them); SCHED_ > 1 also interleaves the next stage's
+// global loads with the MFMAs of the first K step.
 template <typename T, int BMC_, int BNC_, int KT_, int WR_, int WC_, int PAD_ = 2, int PROMOTE_ = 0,
-          bool BKT_ = false>
+          bool BKT_ = false, int PADB_ = -1, int SCHED_ = 0>
 struct Tile {
   static constexpr int KIND = 0;  // 4M real embedding of interleaved complex H
   static constexpr int BMC = BMC_, BNC = BNC_, KT = KT_, WR = WR_, WC = WC_;
   static constexpr int PROMOTE = PROMOTE_;
+  static constexpr int SCHED = SCHED_;
   static constexpr bool BKT = BKT_;
   static constexpr int RT = BMC / WR / 8;
   static constexpr int CG = BNC / WC / 16;
   static constexpr int AR = 2 * BMC + PAD_;  // padded real rows per A stage row (k fixed)
-  static constexpr int BR = 2 * BNC + PAD_;  // padded real columns per B stage row (k fixed)
+  static constexpr int BR = 2 * BNC + (PADB_ < 0 ? PAD_ : PADB_);  // padded real columns per B stage row
   static constexpr int BK = KT + 1;          // padded k per B stage column (BKT_ layout)
   static constexpr int A_PER = BMC * KT / kThreads;
   static constexpr int B_PER = BNC * KT / kThreads;
@@ -133,57 +138,74 @@ __device__ __forceinline__ void tile_mainloop_4m(typename C::Smem& sm, typename 
   const int wr = wave / C::WC, wc = wave % C::WC;
   VL ra[A_LD], rb[B_LD];
 
+  // Load q of a thread is load 0 moved by a whole number of H columns (A) or X columns (B): one
+  // base pointer per operand plus uniform offsets.  Every load is issued unconditionally (a unit
+  // that is not wholly inside the operand reads from the operand's first element instead) and is
+  // zeroed when the stage is written to LDS, after the wait that the LDS store needs anyway, so
+  // no load is followed by an early wait.  Two-element units need n even (the launcher's rule),
+  // so a unit is either wholly inside the operand or wholly outside.
+  static_assert(kThreads % (C::BMC / VEC) == 0 && kThreads % (C::KT / VEC) == 0, "load strides");
+  static_assert(A_LD + B_LD <= 32, "validity bits");
+  const bool tile_full = i0 + C::BMC <= n && j0 + C::BNC <= ncols;
+  const T* const pa0 = H + 2 * (static_cast<int64_t>(i0 + (tid % (C::BMC / VEC)) * VEC) +
+                                static_cast<int64_t>(tid / (C::BMC / VEC)) * ldh);
+  const T* const pb0 = X + 2 * (static_cast<int64_t>((tid % (C::KT / VEC)) * VEC) +
+                                static_cast<int64_t>(j0 + tid / (C::KT / VEC)) * ldx);
+  const int64_t sa = 2 * static_cast<int64_t>(kThreads / (C::BMC / VEC)) * ldh;
+  const int64_t sb = 2 * static_cast<int64_t>(kThreads / (C::KT / VEC)) * ldx;
+  uint32_t valid = 0;  // bit u: load u (A loads, then B loads) is inside its operand
+
   auto load_tiles = [&](int k0) {
+    const bool fast = tile_full && k0 + C::KT <= n;
+    const T* a = pa0 + 2 * static_cast<int64_t>(k0) * ldh;
+    const T* b = pb0 + 2 * static_cast<int64_t>(k0);
+    uint32_t bits = 0;
 #pragma unroll
     for (int q = 0; q < A_LD; ++q) {
       const int idx = tid + kThreads * q;
       const int kk = idx / (C::BMC / VEC), ci = (idx % (C::BMC / VEC)) * VEC;
-      const int row = i0 + ci, col = k0 + kk;
-      const T* src = H + 2 * (static_cast<int64_t>(row) + static_cast<int64_t>(col) * ldh);
-      if (col < n && row + VEC - 1 < n) {
-        ra[q] = *reinterpret_cast<const VL*>(src);
-      } else {
-#pragma unroll
-        for (int e = 0; e < VEC; ++e)
-          ra[q].e[e] = (col < n && row + e < n) ? reinterpret_cast<const v2*>(src)[e]
-                                                  : v2{T(0), T(0)};
-      }
+      const bool ok = fast || (k0 + kk < n && i0 + ci + VEC - 1 < n);
+      ra[q] = *reinterpret_cast<const VL*>(ok ? a + q * sa : H);
+      bits |= (ok ? 1u : 0u) << q;
     }
 #pragma unroll
     for (int q = 0; q < B_LD; ++q) {
       const int idx = tid + kThreads * q;
       const int jj = idx / (C::KT / VEC), kk = (idx % (C::KT / VEC)) * VEC;
-      const int row = k0 + kk, col = j0 + jj;
-      const T* src = X + 2 * (static_cast<int64_t>(row) + static_cast<int64_t>(col) * ldx);
-      if (col < ncols && row + VEC - 1 < n) {
-        rb[q] = *reinterpret_cast<const VL*>(src);
-      } else {
-#pragma unroll
-        for (int e = 0; e < VEC; ++e)
-          rb[q].e[e] = (col < ncols && row + e < n) ? reinterpret_cast<const v2*>(src)[e]
-                                                     : v2{T(0), T(0)};
-      }
+      const bool ok = fast || (j0 + jj < ncols && k0 + kk + VEC - 1 < n);
+      rb[q] = *reinterpret_cast<const VL*>(ok ? b + q * sb : X);
+      bits |= (ok ? 1u : 0u) << (A_LD + q);
     }
+    valid = bits;
+  };
+  // The unit as it goes to LDS: zero when it lies outside the operand.
+  auto fix_unit = [&](VL v, int u) {
+    if (!((valid >> u) & 1u)) {
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) v.e[e] = v2{T(0), T(0)};
+    }
+    return v;
   };
   auto store_tiles = [&](int buf) {
 #pragma unroll
     for (int q = 0; q < A_LD; ++q) {
       const int idx = tid + kThreads * q;
       const int kk = idx / (C::BMC / VEC), ci = (idx % (C::BMC / VEC)) * VEC;
-      *reinterpret_cast<VL*>(&sm.As[buf][kk][2 * ci]) = ra[q];
+      *reinterpret_cast<VL*>(&sm.As[buf][kk][2 * ci]) = fix_unit(ra[q], q);
     }
 #pragma unroll
     for (int q = 0; q < B_LD; ++q) {
       const int idx = tid + kThreads * q;
       const int jj = idx / (C::KT / VEC), kk = (idx % (C::KT / VEC)) * VEC;
+      const VL v = fix_unit(rb[q], A_LD + q);
 #pragma unroll
       for (int e = 0; e < VEC; ++e) {
         if constexpr (C::BKT) {
-          sm.Bs[buf][jj][kk + e] = rb[q].e[e].x;
-          sm.Bs[buf][C::BNC + jj][kk + e] = rb[q].e[e].y;
+          sm.Bs[buf][jj][kk + e] = v.e[e].x;
+          sm.Bs[buf][C::BNC + jj][kk + e] = v.e[e].y;
         } else {
-          sm.Bs[buf][kk + e][jj] = rb[q].e[e].x;
-          sm.Bs[buf][kk + e][C::BNC + jj] = rb[q].e[e].y;
+          sm.Bs[buf][kk + e][jj] = v.e[e].x;
+          sm.Bs[buf][kk + e][C::BNC + jj] = v.e[e].y;
         }
       }
     }
@@ -208,33 +230,31 @@ __device__ __forceinline__ void tile_mainloop_4m(typename C::Smem& sm, typename 
   load_tiles(ka * C::KT);
   store_tiles(0);
   __syncthreads();
-  for (int kt = ka; kt < kb; ++kt) {
-    const int cur = (kt - ka) & 1;
-    if (kt + 1 < kb) load_tiles((kt + 1) * C::KT);
+  // Operand fragments of K step s (4 values of k) from LDS buffer cur.
+  auto fragments = [&](int cur, int s, T (&a)[C::RT], T (&b)[C::CG][2]) {
+    const int k = 4 * s + g;
 #pragma unroll
-    for (int s = 0; s < C::KT / 4; ++s) {
-      const int k = 4 * s + g;
-      T a[C::RT], b[C::CG][2];
+    for (int rt = 0; rt < C::RT; ++rt) a[rt] = sm.As[cur][k][rbase + rt * 16 + arow];
 #pragma unroll
-      for (int rt = 0; rt < C::RT; ++rt) a[rt] = sm.As[cur][k][rbase + rt * 16 + arow];
-#pragma unroll
-      for (int cg = 0; cg < C::CG; ++cg) {
-        if constexpr (C::BKT) {
-          b[cg][0] = sm.Bs[cur][cbase + cg * 16 + li][k];
-          b[cg][1] = sm.Bs[cur][C::BNC + cbase + cg * 16 + li][k];
-        } else {
-          b[cg][0] = sm.Bs[cur][k][cbase + cg * 16 + li];
-          b[cg][1] = sm.Bs[cur][k][C::BNC + cbase + cg * 16 + li];
-        }
+    for (int cg = 0; cg < C::CG; ++cg) {
+      if constexpr (C::BKT) {
+        b[cg][0] = sm.Bs[cur][cbase + cg * 16 + li][k];
+        b[cg][1] = sm.Bs[cur][C::BNC + cbase + cg * 16 + li][k];
+      } else {
+        b[cg][0] = sm.Bs[cur][k][cbase + cg * 16 + li];
+        b[cg][1] = sm.Bs[cur][k][C::BNC + cbase + cg * 16 + li];
       }
-#pragma unroll
-      for (int rt = 0; rt < C::RT; ++rt)
-#pragma unroll
-        for (int cg = 0; cg < C::CG; ++cg)
-#pragma unroll
-          for (int p = 0; p < 2; ++p)
-            f.acc[rt][cg][p] = mfma(a[rt], b[cg][p], f.acc[rt][cg][p]);
     }
+  };
+  auto products = [&](const T (&a)[C::RT], const T (&b)[C::CG][2]) {
+#pragma unroll
+    for (int rt = 0; rt < C::RT; ++rt)
+#pragma unroll
+      for (int cg = 0; cg < C::CG; ++cg)
+#pragma unroll
+        for (int p = 0; p < 2; ++p) f.acc[rt][cg][p] = mfma(a[rt], b[cg][p], f.acc[rt][cg][p]);
+  };
+  auto promote = [&](int kt) {
     if constexpr (C::PROMOTE > 0) {
       if ((kt - ka + 1) % C::PROMOTE == 0 || kt + 1 == kb) {
 #pragma unroll
@@ -249,8 +269,66 @@ __device__ __forceinline__ void tile_mainloop_4m(typename C::Smem& sm, typename 
             }
       }
     }
-    if (kt + 1 < kb) store_tiles(cur ^ 1);
-    __syncthreads();
+  };
+  constexpr int STEPS = C::KT / 4;
+  constexpr int NMFMA = C::RT * C::CG * 2;
+
+  if constexpr (C::SCHED == 0) {
+    for (int kt = ka; kt < kb; ++kt) {
+      const int cur = (kt - ka) & 1;
+      if (kt + 1 < kb) load_tiles((kt + 1) * C::KT);
+#pragma unroll
+      for (int s = 0; s < STEPS; ++s) {
+        T a[C::RT], b[C::CG][2];
+        fragments(cur, s, a, b);
+        products(a, b);
+      }
+      promote(kt);
+      if (kt + 1 < kb) store_tiles(cur ^ 1);
+      __syncthreads();
+    }
+  } else {
+    int kt = ka;
+    for (; kt + 1 < kb; ++kt) {  // stages followed by another: prefetch and stage the next one
+      const int cur = (kt - ka) & 1;
+#pragma unroll
+      for (int s = 0; s < STEPS; ++s) {
+        T a[C::RT], b[C::CG][2];
+        fragments(cur, s, a, b);
+        if (s == 0) load_tiles((kt + 1) * C::KT);
+        if (s == STEPS - 1) store_tiles(cur ^ 1);
+        products(a, b);
+        if (s == 0 && C::SCHED > 1) {
+          constexpr int NL = A_LD + B_LD;
+#pragma unroll
+          for (int i = 0; i < NL; ++i) {
+            __builtin_amdgcn_sched_group_barrier(0x008, NMFMA / NL > 0 ? NMFMA / NL : 1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
+          }
+        }
+        if (s == STEPS - 1) {
+          constexpr int NW = A_LD + B_LD;
+#pragma unroll
+          for (int i = 0; i < NW; ++i) {
+            __builtin_amdgcn_sched_group_barrier(0x008, NMFMA / NW > 0 ? NMFMA / NW : 1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);
+          }
+        }
+      }
+      promote(kt);
+      __syncthreads();
+    }
+    if (kt < kb) {  // last stage
+      const int cur = (kt - ka) & 1;
+#pragma unroll
+      for (int s = 0; s < STEPS; ++s) {
+        T a[C::RT], b[C::CG][2];
+        fragments(cur, s, a, b);
+        products(a, b);
+      }
+      promote(kt);
+      __syncthreads();
+    }
   }
 }
 
@@ -744,41 +822,52 @@ namespace {
 // same wide tile; columns <= 32 use the narrow one.
 // LDS rows are padded by 2 doubles (FP64) or 8 floats (FP32: keeps 16-byte aligned rows for
 // the two-element vector loads).
-template <typename T> using WideTile = Tile<T, 64, 64, 16, 2, 2, sizeof(T) == 4 ? 8 : 2>;
+// The FP64 wide tile interleaves the next stage's LDS stores with its last K step's MFMAs.
+template <typename T>
+using WideTile = Tile<T, 64, 64, 16, 2, 2, sizeof(T) == 4 ? 8 : 2, 0, false, -1, sizeof(T) == 4 ? 0 : 1>;
 template <typename T> using NarrowTile = Tile<T, 64, 32, 16, 4, 1, sizeof(T) == 4 ? 8 : 2>;
+// FP64 slim tile: 32 columns, K stages of 8, four workgroups per CU (125 VGPRs, 25 KB LDS); the
+// next stage's global loads and LDS stores are both interleaved with MFMAs.  Padding the
+// columns to 32 instead of 64 wastes less work on ragged widths, but it moves more operand data
+// per flop: with full-precision operands (where the chip runs at its power limit) it is about
+// 7 % slower per executed flop than the wide tile.  It is chosen only when padding to 64 would
+// waste over 10 % more work than padding to 32.
+using SlimTile64 = Tile<double, 64, 32, 8, 2, 2, 2, 0, false, 1, 2>;
+constexpr int kOccSlim = 4;
+constexpr double kSlimCost = 1.10;
 
 // 3M tile for the planar FP32 products (FP64 promotion every two stages, i.e. every 32 K terms).
 using Wide3M = Tile3M<64, 64, 16, 2, 2, 4, 2>;
 
 // Two-element (16-byte) global loads are used for complex64 data when H and X are 16-byte
-// aligned and their leading dimensions are even.
+// aligned and n and their leading dimensions are even.
 template <typename T>
-bool use_v16(const T* H, int64_t ldh, const T* X, int64_t ldx) {
+bool use_v16(const T* H, int64_t ldh, const T* X, int64_t ldx, int64_t n) {
   return sizeof(T) == 4 && (reinterpret_cast<uintptr_t>(H) % 16) == 0 &&
-         (reinterpret_cast<uintptr_t>(X) % 16) == 0 && ldh % 2 == 0 && ldx % 2 == 0;
+         (reinterpret_cast<uintptr_t>(X) % 16) == 0 && ldh % 2 == 0 && ldx % 2 == 0 && n % 2 == 0;
 }
 constexpr int kOcc = 2;  // workgroups per CU the tiles are built for
 
-template <typename T, class C>
+template <typename T, class C, int OCC = kOcc>
 hipError_t launch_sched(const T* H, int64_t ldh, int64_t n, const T* X, int64_t ldx, T* OUT,
                         int64_t ldo, int64_t ncols, T alpha, T beta, T gamma,
                         const ProductScratch& ps, hipStream_t stream, bool v16_ok = true) {
   const int64_t tiles = ((n + C::BMC - 1) / C::BMC) * ((ncols + C::BNC - 1) / C::BNC);
-  const int64_t slots = static_cast<int64_t>(ps.cus) * kOcc;
+  const int64_t slots = static_cast<int64_t>(ps.cus) * OCC;
   const int64_t rounds = (tiles + slots - 1) / slots;
   const double eff = static_cast<double>(tiles) / static_cast<double>(rounds * slots);
-  const bool v16 = v16_ok && use_v16(H, ldh, X, ldx);
+  const bool v16 = v16_ok && use_v16(H, ldh, X, ldx, n);
   if (eff >= 0.92 || !ps.ptr || sk_scratch_bytes<T, C>(slots) > ps.bytes) {
     if (v16)
-      return launch_dp<T, C, kOcc, true>(H, ldh, n, X, ldx, OUT, ldo, ncols, alpha, beta, gamma,
-                                         stream);
-    return launch_dp<T, C, kOcc>(H, ldh, n, X, ldx, OUT, ldo, ncols, alpha, beta, gamma, stream);
+      return launch_dp<T, C, OCC, true>(H, ldh, n, X, ldx, OUT, ldo, ncols, alpha, beta, gamma,
+                                        stream);
+    return launch_dp<T, C, OCC>(H, ldh, n, X, ldx, OUT, ldo, ncols, alpha, beta, gamma, stream);
   }
   if (v16)
-    return launch_sk<T, C, kOcc, true>(H, ldh, n, X, ldx, OUT, ldo, ncols, alpha, beta, gamma,
-                                       slots, static_cast<T*>(ps.ptr), stream);
-  return launch_sk<T, C, kOcc>(H, ldh, n, X, ldx, OUT, ldo, ncols, alpha, beta, gamma, slots,
-                               static_cast<T*>(ps.ptr), stream);
+    return launch_sk<T, C, OCC, true>(H, ldh, n, X, ldx, OUT, ldo, ncols, alpha, beta, gamma,
+                                      slots, static_cast<T*>(ps.ptr), stream);
+  return launch_sk<T, C, OCC>(H, ldh, n, X, ldx, OUT, ldo, ncols, alpha, beta, gamma, slots,
+                              static_cast<T*>(ps.ptr), stream);
 }
 }  // namespace
 
@@ -787,6 +876,7 @@ size_t product_scratch_bytes(int cus) {
   size_t b = sk_scratch_bytes<double, WideTile<double>>(slots);
   b = std::max(b, sk_scratch_bytes<float, WideTile<float>>(slots));
   b = std::max(b, sk_scratch_bytes<double, NarrowTile<double>>(slots));
+  b = std::max(b, sk_scratch_bytes<double, SlimTile64>(static_cast<int64_t>(cus) * kOccSlim));
   return b;
 }
 
@@ -795,6 +885,20 @@ hipError_t launch_hemm_step(const T* H, int64_t ldh, int64_t n, const T* X, int6
                             int64_t ldo, int64_t ncols, T alpha, T beta, T gamma,
                             const ProductScratch& ps, hipStream_t stream) {
   if (n <= 0 || ncols <= 0) return hipSuccess;
+  if constexpr (sizeof(T) == 8) {
+    // Columns padded to whole tiles: 32-wide slim tiles when that saves more than their lower
+    // per-flop rate costs.
+    if (ncols <= 32)
+      return launch_sched<T, NarrowTile<T>>(H, ldh, n, X, ldx, OUT, ldo, ncols, alpha, beta,
+                                            gamma, ps, stream);
+    const double w64 = static_cast<double>((ncols + 63) / 64 * 64);
+    const double w32 = static_cast<double>((ncols + 31) / 32 * 32);
+    if (w32 * kSlimCost < w64)
+      return launch_sched<T, SlimTile64, kOccSlim>(H, ldh, n, X, ldx, OUT, ldo, ncols, alpha,
+                                                   beta, gamma, ps, stream);
+    return launch_sched<T, WideTile<T>>(H, ldh, n, X, ldx, OUT, ldo, ncols, alpha, beta, gamma,
+                                        ps, stream);
+  }
   if (ncols <= 32)
     return launch_sched<T, NarrowTile<T>>(H, ldh, n, X, ldx, OUT, ldo, ncols, alpha, beta, gamma,
                                           ps, stream);
@@ -818,7 +922,7 @@ hipError_t launch_hemm_group(const GroupDesc<T>* descs, int count, hipStream_t s
     if (tiles == 0) continue;
     if (tiles > 0x7fffffff) return hipErrorInvalidValue;
     bool v16 = true;
-    for (int q = 0; q < a.count; ++q) v16 = v16 && use_v16(a.d[q].H, a.d[q].ldh, a.d[q].X, a.d[q].ldx);
+    for (int q = 0; q < a.count; ++q) v16 = v16 && use_v16(a.d[q].H, a.d[q].ldh, a.d[q].X, a.d[q].ldx, a.d[q].n);
     if (v16)
       hipLaunchKernelGGL((hemm_group_kernel<T, WideTile<T>, kOcc, true>),
                          dim3(static_cast<unsigned>(tiles)), dim3(kThreads), 0, stream, a);
@@ -854,7 +958,7 @@ hipError_t launch_hemm_group_3m(const GroupDesc<float>* descs, int count, hipStr
       a.d[q].tile_begin = static_cast<int>(tiles);
       tiles += ((a.d[q].n + Wide3M::BMC - 1) / Wide3M::BMC) *
                static_cast<int64_t>((a.d[q].ncols + Wide3M::BNC - 1) / Wide3M::BNC);
-      v16 = v16 && a.d[q].ldh % 4 == 0 && use_v16(a.d[q].H, a.d[q].ldh, a.d[q].X, a.d[q].ldx);
+      v16 = v16 && a.d[q].ldh % 4 == 0 && use_v16(a.d[q].H, a.d[q].ldh, a.d[q].X, a.d[q].ldx, a.d[q].n);
     }
     if (tiles == 0) continue;
     if (tiles > 0x7fffffff) return hipErrorInvalidValue;
