@@ -87,10 +87,26 @@ def make_sequence_problem(n, lam, k, eps, seed, prev=None, norm=None):
         return wl.hermitian_torch_fast(n, lam, seed)
     gen = torch.Generator(device="cuda")
     gen.manual_seed(seed + 7919 * k)
-    E = torch.complex(torch.randn((n, n), generator=gen, device="cuda", dtype=torch.float64),
-                      torch.randn((n, n), generator=gen, device="cuda", dtype=torch.float64))
-    E.add_(E.conj().T.clone())
-    E.mul_(0.5)
+    if n <= 30000:
+        E = torch.complex(torch.randn((n, n), generator=gen, device="cuda", dtype=torch.float64),
+                          torch.randn((n, n), generator=gen, device="cuda", dtype=torch.float64))
+        E.add_(E.conj().T.clone())
+        E.mul_(0.5)
+    else:
+        # one n x n buffer: complex Gaussian, then (G + G^H)/2 block pair by block pair
+        E = torch.randn((n, n), generator=gen, device="cuda", dtype=torch.complex128)
+        bs = 4096
+        for i in range(0, n, bs):
+            for j in range(i, n, bs):
+                a = E[i:i + bs, j:j + bs]
+                if i == j:
+                    a.copy_(0.5 * (a + a.conj().T))
+                else:
+                    b = E[j:j + bs, i:i + bs]
+                    sym = 0.5 * (a + b.conj().T)
+                    a.copy_(sym)
+                    b.copy_(sym.conj().T)
+                    del sym
     x = torch.randn(n, generator=gen, device="cuda", dtype=torch.float64).to(torch.complex128)
     for _ in range(40):
         x = E @ x
@@ -110,31 +126,33 @@ def run_sequence(args):
     from paper_1805_10121_amd import capi
     from paper_1805_10121_amd import workloads as wl
 
-    c = wl.CONFIGS[3]
-    n = args.order
+    c = wl.CONFIGS[args.config]
+    n = args.order or c["n"]
     nev = max(1, round(c["nev"] * n / c["n"]))
     nex = max(1, round(c["nex"] * n / c["n"]))
     eps = c["eps"]
-    lam = wl.spectrum_for(3, n=n)
+    problems = args.problems or c["problems"]
+    lam = wl.spectrum_for(args.config, n=n)
     norm = float(np.max(np.abs(lam)))
     ctx = capi.Context(0)
     res = {}
-    modes = [] if args.no_fp64_reference else [("fp64", capi.CHASE_FP64, None, None)]
-    for sw in args.switch_resid:
+    modes = [("fp64", capi.CHASE_FP64, None, None)] if "fp64" in args.modes else []
+    for sw in (args.switch_resid if "mixed" in args.modes else []):
         for dm in args.deg_max_fp32:
             name = "mixed" if (len(args.switch_resid) == 1 and len(args.deg_max_fp32) == 1) \
                 else f"mixed sw={sw:g} dm={dm}"
             modes.append((name, capi.CHASE_MIXED, sw, dm))
     for mode, prec, sw, dm in modes:
         cfg = capi.config(n, nev, nex, optim=1, precision=prec, seed=3000)
+        cfg.verbose = 1
         if sw is not None:
             cfg.switch_resid = sw
             cfg.deg_max_fp32 = dm
         seq = capi.Sequence(ctx, cfg)
         H = None
         per = []
-        for k in range(args.problems):
-            H = make_sequence_problem(n, lam, k, eps, 3001, prev=H, norm=norm)
+        for k in range(problems):
+            H = make_sequence_problem(n, lam, k, eps, 1000 * args.config + 1, prev=H, norm=norm)
             torch.cuda.synchronize()
             ritzv, resid = np.zeros(nev + nex), np.zeros(nev + nex)
             t0 = time.perf_counter()
@@ -157,8 +175,9 @@ def run_sequence(args):
         torch.cuda.empty_cache()
         res[mode] = per
     ref = res.get("fp64")
-    out = {"workload": f"sequence n={n} nev={nev} nex={nex} problems={args.problems} eps={eps}, "
-                       "clustered spectrum (600 clustered values), warm-started, tol 1e-10"}
+    out = {"workload": f"sequence n={n} nev={nev} nex={nex} problems={problems} eps={eps}, "
+                       f"clustered spectrum ({c['n_clustered']} clustered values), warm-started, "
+                       "tol 1e-10"}
     totals = {m: round(sum(p["time_s"] for p in res[m]), 3) for m in res}
     out["total_s"] = totals
     if ref is not None:
@@ -272,6 +291,9 @@ def run_serving(n_seq=16, problems=8, rates=(0.5, 0.8, 1.0), sizes=(2000, 4000, 
                 busy[s] = any(v[0] == s for v in live.values())
                 done_count += 1
                 last_end = t_end
+                if done_count % 8 == 0 or done_count == total:
+                    log(f"serving ({'closed loop' if rate is None else f'rate {rate:.3f}/s'}): "
+                        f"{done_count}/{total} solves done at {t_end:.1f} s")
             time.sleep(0.0005)
         info = srv.chase_server_info()
         srv.close()
@@ -351,17 +373,24 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
+    ap.add_argument("--no-n20000", action="store_true",
+                    help="skip the filter measurement at the order-20000 shape")
     ap.add_argument("--workload", choices=["filter", "sequence", "serving", "ablation"],
                     default="filter",
                     help="filter: the hot-path benchmark (default); sequence: time-to-solution of "
                          "a warm-started sequence, plain FP64 against the mixed FP32/FP64 filter")
-    ap.add_argument("--problems", type=int, default=10)
+    ap.add_argument("--problems", type=int, default=None,
+                    help="sequence: problems (default: the config's); serving: per sequence (8)")
+    ap.add_argument("--config", type=int, choices=[3, 5], default=3,
+                    help="sequence workload: order-20000 (3) or order-60000 (5) sequence")
+    ap.add_argument("--modes", nargs="*", default=["fp64", "mixed"], choices=["fp64", "mixed"],
+                    help="sequence workload: which filters to run")
     ap.add_argument("--switch-resid", type=float, nargs="*", default=[1e-6],
                     help="sequence workload: mixed-mode switch thresholds to run")
     ap.add_argument("--deg-max-fp32", type=int, nargs="*", default=[18],
                     help="sequence workload: mixed-mode FP32 degree caps to run")
-    ap.add_argument("--no-fp64-reference", action="store_true")
-    ap.add_argument("--order", type=int, default=20000)
+    ap.add_argument("--order", type=int, default=None,
+                    help="sequence workload: order (default: the config's)")
     ap.add_argument("--h-gen", choices=["haar", "structured"], default="haar",
                     help="H for the filter workload: Haar Q (QR of a Gaussian) or the structured "
                          "reflector unitary (no QR; used for counter-collection runs)")
@@ -396,7 +425,7 @@ def main():
         print(json.dumps(out), flush=True)
         return
     if args.workload == "serving":
-        print(json.dumps(run_serving(problems=args.problems if args.problems != 10 else 8)),
+        print(json.dumps(run_serving(problems=args.problems or 8)),
               flush=True)
         return
 
@@ -516,6 +545,36 @@ def main():
         }
         log(f"bench: solve {t_solve:.3f} s, {st.iterations} iterations")
         del dV0
+
+    if not args.no_n20000:
+        # the same filter at the order-20000 shape (1200 columns, degrees 2..36)
+        n2, nb2 = 20000, 1200
+        lam2 = wl.spectrum_for(3)
+        dH2 = wl.hermitian_torch_fast(n2, lam2, seed=3001)
+        dV2 = capi.to_device(wl.start_block(n2, nb2, 3500))
+        dW2 = torch.empty_like(dV2)
+        deg2 = wl.optimized_degree_profile(nb2, 36)
+        b2, m12, mb2 = float(lam2[-1]) + 0.05, float(lam2[0]), float(lam2[nb2 - 1])
+        fl2 = 8.0 * n2 * n2 * float(deg2.sum())
+        ctx.chase_filter(capi.CHASE_FP64, dH2, n2, n2, dV2, dW2, n2, nb2, deg2, b2, m12, mb2)
+        torch.cuda.synchronize()
+        reps = 3
+        ev0.record(stream)
+        for _ in range(reps):
+            ctx.chase_filter(capi.CHASE_FP64, dH2, n2, n2, dV2, dW2, n2, nb2, deg2, b2, m12, mb2)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms2 = ev0.elapsed_time(ev1) / reps
+        tf2 = fl2 / (ms2 * 1e-3) / 1e12
+        out["filter_n20000"] = {
+            "value": round(tf2, 3), "unit": "TFLOP/s", "peak": FP64_PEAK_TF,
+            "frac": round(tf2 / FP64_PEAK_TF, 4), "ms_per_step": round(ms2, 3), "steps": reps,
+            "workload": "chebyshev filter, n=20000, 1200 columns, sorted even degrees uniform over "
+                        "2..36, complex128 H = Q diag(lam) Q^H (structured reflector Q, order-20000 "
+                        "spectrum)"}
+        log(f"bench: fp64 filter at n=20000: {tf2:.2f} TFLOP/s")
+        del dH2, dV2, dW2
+        torch.cuda.empty_cache()
 
     if not args.no_cpu_baseline:
         log("bench: cpu baseline (oracle on a column sample)")

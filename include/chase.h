@@ -88,6 +88,8 @@ typedef struct chase_config {
   int32_t have_mu;       /* cold start only: 1 = use mu_1 / mu_nevnex below instead of the DoS
                             estimates (Alg. 1 input "estimates mu_1 and mu_{nev+nex}")    0     */
   double mu_1, mu_nevnex;
+  int32_t verbose;       /* 1: one line per outer iteration on stderr (locked pairs, largest
+                            active residual, FP32 columns, elapsed time)                  0     */
 } chase_config;
 
 /* Counters and timings of one solve (Sec. 6 reports iterations, matvecs and filter time). */

@@ -39,7 +39,7 @@ class chase_config(ctypes.Structure):
         ("precision", _i32), ("switch_resid", _f64), ("deg_max_fp32", _i32),
         ("resid_relative", _i32), ("intersperse", _i32), ("dos_sigma", _f64),
         ("seed", _u64), ("lanczos_start", _vp), ("have_mu", _i32),
-        ("mu_1", _f64), ("mu_nevnex", _f64),
+        ("mu_1", _f64), ("mu_nevnex", _f64), ("verbose", _i32),
     ]
 
 

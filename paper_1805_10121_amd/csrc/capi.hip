@@ -121,6 +121,7 @@ void chase_config_init(chase_config* cfg, int64_t n, int64_t nev, int64_t nex) {
   cfg->have_mu = 0;
   cfg->mu_1 = 0.0;
   cfg->mu_nevnex = 0.0;
+  cfg->verbose = 0;
 }
 
 int chase_create(chase_ctx** out, int device, void* hip_stream) {

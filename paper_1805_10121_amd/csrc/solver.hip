@@ -24,6 +24,9 @@
 #include "host_logic.h"
 #include "internal.h"
 
+#include <chrono>
+#include <cstdio>
+
 namespace chase {
 namespace {
 
@@ -451,6 +454,7 @@ int Solver::run(const void* Hv, int64_t ldh, void* Vuser, int64_t ldv, double* r
   const int deg32max = cfg_.deg_max_fp32 + (cfg_.deg_max_fp32 & 1);
 
   // ---------------------------------------------------------------- main loop (Alg. 1 line 3)
+  const auto t_start = std::chrono::steady_clock::now();
   int64_t nlock = 0;
   std::vector<int> m(nb_, mixed ? std::min(deg0, deg32max) : deg0);
   std::vector<int> prec(nb_, mixed ? 1 : 0);
@@ -602,6 +606,20 @@ int Solver::run(const void* Hv, int64_t ldh, void* Vuser, int64_t ldv, double* r
                   "copy")))
       return rc;
     nlock += n_new;
+    if (cfg_.verbose) {
+      int64_t n32 = 0;
+      double rmax = 0.0;
+      for (int64_t q = 0; q < rem; ++q) n32 += prec[q], rmax = std::max(rmax, res_act[q]);
+      const double secs =
+          std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+      std::fprintf(stderr,
+                   "chase: iteration %d: locked %lld of %lld, largest active residual %.3e "
+                   "(tol %.3e), next filter: %lld FP32 columns, degrees %d..%d, %.2f s\n",
+                   it, static_cast<long long>(nlock), static_cast<long long>(cfg_.nev), rmax,
+                   tol_eff, static_cast<long long>(n32), rem > 0 ? m[0] : 0,
+                   rem > 0 ? *std::max_element(m.begin(), m.begin() + rem) : 0, secs);
+      std::fflush(stderr);
+    }
   }
 
   // ---------------------------------------------------------------- output

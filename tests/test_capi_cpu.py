@@ -45,6 +45,7 @@ int main(void) {
   F(chase_config, approx) F(chase_config, tol) F(chase_config, precision)
   F(chase_config, switch_resid) F(chase_config, dos_sigma) F(chase_config, seed)
   F(chase_config, lanczos_start) F(chase_config, have_mu) F(chase_config, mu_nevnex)
+  F(chase_config, verbose)
   F(chase_stats, matvecs) F(chase_stats, filter_flops) F(chase_stats, norm_est)
   return 0;
 }
@@ -59,7 +60,7 @@ int main(void) {
     assert int(vals["sizeof_config"]) == ctypes.sizeof(capi.chase_config)
     assert int(vals["sizeof_stats"]) == ctypes.sizeof(capi.chase_stats)
     for f in ["approx", "tol", "precision", "switch_resid", "dos_sigma", "seed", "lanczos_start",
-              "have_mu", "mu_nevnex"]:
+              "have_mu", "mu_nevnex", "verbose"]:
         assert int(vals[f]) == getattr(capi.chase_config, f).offset, f
     for f in ["matvecs", "filter_flops", "norm_est"]:
         assert int(vals[f]) == getattr(capi.chase_stats, f).offset, f

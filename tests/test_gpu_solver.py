@@ -134,6 +134,23 @@ def test_warm_start_exact_vectors_one_iteration(ctx):
     _check(H, lam, ritzv, Y, nev)
 
 
+def test_verbose_iteration_lines(ctx, capfd):
+    # verbose = 1 prints one line per outer iteration on stderr; the result is unchanged
+    n, nev, nex = 200, 10, 4
+    g = wl.rng(61)
+    lam = wl.spectrum_uniform(n, g)
+    H = wl.hermitian_from(wl.haar_unitary(n, g), lam)
+    V0, S = wl.complex_gaussian(g, n, nev + nex), wl.complex_gaussian(g, n, 5)
+    rc0, st0, r0, _, _ = _gpu_solve(ctx, H, V0, S, nev=nev, optim=1)
+    capfd.readouterr()
+    rc1, st1, r1, _, _ = _gpu_solve(ctx, H, V0, S, nev=nev, optim=1, verbose=1)
+    err = capfd.readouterr().err
+    lines = [ln for ln in err.splitlines() if ln.startswith("chase: iteration ")]
+    assert rc0 == rc1 == 0 and len(lines) == st1.iterations == st0.iterations
+    assert lines[-1].startswith(f"chase: iteration {st1.iterations}: locked ")
+    assert np.array_equal(r0, r1)
+
+
 def test_max_iter_partial(ctx):
     from paper_1805_10121_amd import capi
 
