@@ -575,6 +575,29 @@ def main():
         log(f"bench: fp64 filter at n=20000: {tf2:.2f} TFLOP/s")
         del dH2, dV2, dW2
         torch.cuda.empty_cache()
+        # the real symmetric instance at the same shape: 2 n^2 flops per column and product
+        dH2 = wl.symmetric_torch_fast(n2, lam2, seed=3002)
+        dV2 = capi.to_device(wl.rng(3501).standard_normal((n2, nb2)))
+        dW2 = torch.empty_like(dV2)
+        flr = 2.0 * n2 * n2 * float(deg2.sum())
+        ctx.chase_filter(capi.CHASE_REAL_FP64, dH2, n2, n2, dV2, dW2, n2, nb2, deg2, b2, m12, mb2)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        for _ in range(reps):
+            ctx.chase_filter(capi.CHASE_REAL_FP64, dH2, n2, n2, dV2, dW2, n2, nb2, deg2, b2, m12,
+                             mb2)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        msr = ev0.elapsed_time(ev1) / reps
+        tfr = flr / (msr * 1e-3) / 1e12
+        out["filter_real_n20000"] = {
+            "value": round(tfr, 3), "unit": "TFLOP/s", "peak": FP64_PEAK_TF,
+            "frac": round(tfr / FP64_PEAK_TF, 4), "ms_per_step": round(msr, 3), "steps": reps,
+            "workload": "chebyshev filter, real symmetric float64 H (structured reflector Q), "
+                        "n=20000, 1200 columns, degrees 2..36; 2 n^2 flops per column product"}
+        log(f"bench: real fp64 filter at n=20000: {tfr:.2f} TFLOP/s")
+        del dH2, dV2, dW2
+        torch.cuda.empty_cache()
 
     if not args.no_cpu_baseline:
         log("bench: cpu baseline (oracle on a column sample)")

@@ -45,11 +45,14 @@ typedef enum {
   CHASE_FP32 = 1,   /* complex64 buffers, FP32 MFMA with FP32 accumulation                      */
   CHASE_MIXED = 2,  /* chase_solve only: FP32 filter while a vector's relative residual exceeds
                        switch_resid, FP64 afterwards; everything outside the filter stays FP64 */
-  CHASE_FP32_3M = 3 /* chase_filter / chase_hemm_step: H is "planar complex64" -- two real
+  CHASE_FP32_3M = 3, /* chase_filter / chase_hemm_step: H is "planar complex64" -- two real
                        n x n FP32 planes, Re H then Im H at an offset of ldh * n floats, each
                        column-major with leading dimension ldh -- and the products use three
                        real FP32 MFMA products per complex product (3M) with FP64 sums across
                        K stages; the blocks are complex64 as for CHASE_FP32 */
+  CHASE_REAL_FP64 = 4, /* chase_filter / chase_hemm_step: real symmetric H and real blocks, all
+                       float64 (the paper's real "D" instance, Sec. 5.1), FP64 MFMA            */
+  CHASE_REAL_FP32 = 5  /* the same with float32 H and blocks, FP32 MFMA with FP32 accumulation */
 } chase_precision;
 
 /*
@@ -90,6 +93,9 @@ typedef struct chase_config {
   double mu_1, mu_nevnex;
   int32_t verbose;       /* 1: one line per outer iteration on stderr (locked pairs, largest
                             active residual, FP32 columns, elapsed time)                  0     */
+  int32_t real_symmetric;/* 1: H is real symmetric float64 and V is real float64 (the paper's
+                            real instance); leading dimensions count real elements.  0: complex
+                            Hermitian complex128                                          0     */
 } chase_config;
 
 /* Counters and timings of one solve (Sec. 6 reports iterations, matvecs and filter time). */
@@ -137,9 +143,11 @@ size_t chase_workspace_bytes(const chase_config* cfg);
  *
  *   precision  CHASE_FP64: H, V, W are complex128.  CHASE_FP32: H, V, W are complex64 (use the
  *              conversion calls below to stage them); the recurrence coefficients are computed
- *              in FP64 and rounded to FP32 per launch.
- *   H          device, n x n, column-major, leading dimension ldh >= n, full Hermitian storage
- *              (both triangles are read).  Read only.
+ *              in FP64 and rounded to FP32 per launch.  CHASE_FP32_3M: planar complex64 H.
+ *              CHASE_REAL_FP64 / CHASE_REAL_FP32: real symmetric H and real V, W (float64 /
+ *              float32); leading dimensions count real elements.
+ *   H          device, n x n, column-major, leading dimension ldh >= n, full Hermitian (or
+ *              symmetric) storage (both triangles are read).  Read only.
  *   V          device, n x ncols, leading dimension ld >= n.  In: the block.  Out: the result.
  *   W          device, n x ncols, leading dimension ld, must not overlap V or H.  Scratch.
  *   degrees    host, ncols int32, sorted ascending, even, 2 <= m_a <= 64 (Alg. 1 line 15 and

@@ -26,6 +26,8 @@ CHASE_FP64 = 0
 CHASE_FP32 = 1
 CHASE_MIXED = 2
 CHASE_FP32_3M = 3
+CHASE_REAL_FP64 = 4
+CHASE_REAL_FP32 = 5
 
 _i64, _i32, _f64, _u64, _vp = ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_uint64, ctypes.c_void_p
 
@@ -39,7 +41,7 @@ class chase_config(ctypes.Structure):
         ("precision", _i32), ("switch_resid", _f64), ("deg_max_fp32", _i32),
         ("resid_relative", _i32), ("intersperse", _i32), ("dos_sigma", _f64),
         ("seed", _u64), ("lanczos_start", _vp), ("have_mu", _i32),
-        ("mu_1", _f64), ("mu_nevnex", _f64), ("verbose", _i32),
+        ("mu_1", _f64), ("mu_nevnex", _f64), ("verbose", _i32), ("real_symmetric", _i32),
     ]
 
 
@@ -323,17 +325,20 @@ def to_device(A, device="cuda"):
     return torch.from_numpy(np.ascontiguousarray(A.T)).to(device)
 
 
-def device_block_to_host(ptr, ld, rows, cols):
-    """Copy a borrowed device complex128 block (column-major, leading dimension ld) to a numpy
-    array (rows, cols) -- a hipMemcpy2D through the HIP runtime, no arithmetic."""
+def device_block_to_host(ptr, ld, rows, cols, dtype=None):
+    """Copy a borrowed device block (column-major, leading dimension ld; complex128 unless
+    dtype says otherwise) to a numpy array (rows, cols) -- a hipMemcpy2D through the HIP
+    runtime, no arithmetic."""
     import numpy as np
 
+    dtype = np.dtype(dtype or np.complex128)
+    es = dtype.itemsize
     hip = ctypes.CDLL("libamdhip64.so")
     hip.hipMemcpy2D.restype = ctypes.c_int
     hip.hipMemcpy2D.argtypes = [_vp, ctypes.c_size_t, _vp, ctypes.c_size_t, ctypes.c_size_t,
                                 ctypes.c_size_t, ctypes.c_int]
-    out = np.empty((cols, rows), dtype=np.complex128)
-    rc = hip.hipMemcpy2D(out.ctypes.data, rows * 16, ptr, ld * 16, rows * 16, cols, 2)
+    out = np.empty((cols, rows), dtype=dtype)
+    rc = hip.hipMemcpy2D(out.ctypes.data, rows * es, ptr, ld * es, rows * es, cols, 2)
     if rc != 0:
         raise RuntimeError(f"hipMemcpy2D failed ({rc})")
     return out.T

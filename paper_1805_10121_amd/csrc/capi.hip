@@ -66,9 +66,10 @@ int check_bounds(chase_ctx* ctx, double b_sup, double mu_1, double mu_nevnex) {
 
 int check_product_args(chase_ctx* ctx, int precision, const void* H, int64_t ldh, int64_t n,
                        const void* X, int64_t ldx, const void* OUT, int64_t ldo, int64_t ncols) {
-  if (precision != CHASE_FP64 && precision != CHASE_FP32 && precision != CHASE_FP32_3M)
+  if (precision < CHASE_FP64 || precision > CHASE_REAL_FP32 || precision == CHASE_MIXED)
     return set_error(ctx, CHASE_EINVAL,
-                     "precision must be CHASE_FP64, CHASE_FP32 or CHASE_FP32_3M");
+                     "precision must be CHASE_FP64, CHASE_FP32, CHASE_FP32_3M, CHASE_REAL_FP64 or "
+                     "CHASE_REAL_FP32");
   if (n < 0 || ncols < 0) return set_error(ctx, CHASE_EINVAL, "negative size");
   if (n > 0x7fffffffLL || ncols > 0x7fffffffLL)
     return set_error(ctx, CHASE_EINVAL, "n and ncols must fit in int32");
@@ -76,7 +77,7 @@ int check_product_args(chase_ctx* ctx, int precision, const void* H, int64_t ldh
   if (!H || !X || !OUT) return set_error(ctx, CHASE_EINVAL, "NULL buffer");
   if (ldh < n || ldx < n || ldo < n)
     return set_error(ctx, CHASE_EINVAL, "leading dimension smaller than n");
-  const size_t elem = precision == CHASE_FP64 ? 16 : 8;
+  const size_t elem = precision == CHASE_FP64 ? 16 : precision == CHASE_REAL_FP32 ? 4 : 8;
   const size_t hb = precision == CHASE_FP32_3M ? static_cast<size_t>(ldh) * n * 8
                                                : block_bytes(ldh, n, n, elem);
   const size_t xb = block_bytes(ldx, n, ncols, elem);
@@ -122,6 +123,7 @@ void chase_config_init(chase_config* cfg, int64_t n, int64_t nev, int64_t nex) {
   cfg->mu_1 = 0.0;
   cfg->mu_nevnex = 0.0;
   cfg->verbose = 0;
+  cfg->real_symmetric = 0;
 }
 
 int chase_create(chase_ctx** out, int device, void* hip_stream) {
@@ -200,10 +202,14 @@ int chase_filter(chase_ctx* ctx, int precision, const void* H, int64_t ldh, int6
   if ((rc = check_bounds(ctx, b_sup, mu_1, mu_nevnex))) return rc;
   CHASE_HIP_TRY(ctx, hipSetDevice(ctx->device));
   hipError_t e;
-  if (precision == CHASE_FP64)
+  if (precision == CHASE_FP64 || precision == CHASE_REAL_FP64)
     e = run_filter<double>(static_cast<const double*>(H), ldh, n, static_cast<double*>(V),
                            static_cast<double*>(W), ld, ncols, degrees, b_sup, mu_1, mu_nevnex,
-                           ctx->prod, ctx->stream, nullptr);
+                           ctx->prod, ctx->stream, nullptr, precision == CHASE_REAL_FP64 ? 3 : 0);
+  else if (precision == CHASE_REAL_FP32)
+    e = run_filter<float>(static_cast<const float*>(H), ldh, n, static_cast<float*>(V),
+                          static_cast<float*>(W), ld, ncols, degrees, b_sup, mu_1, mu_nevnex,
+                          ctx->prod, ctx->stream, nullptr, 3);
   else
     e = run_filter<float>(static_cast<const float*>(H), ldh, n, static_cast<float*>(V),
                           static_cast<float*>(W), ld, ncols, degrees, b_sup, mu_1, mu_nevnex,
@@ -229,6 +235,17 @@ int chase_hemm_step(chase_ctx* ctx, int precision, const void* H, int64_t ldh, i
     e = launch_hemm_step<double>(static_cast<const double*>(H), ldh, n,
                                  static_cast<const double*>(X), ldx, static_cast<double*>(OUT),
                                  ldo, ncols, alpha, beta, gamma, ctx->prod, ctx->stream);
+  else if (precision == CHASE_REAL_FP64)
+    e = launch_hemm_step_real<double>(static_cast<const double*>(H), ldh, n,
+                                      static_cast<const double*>(X), ldx,
+                                      static_cast<double*>(OUT), ldo, ncols, alpha, beta, gamma,
+                                      ctx->prod, ctx->stream);
+  else if (precision == CHASE_REAL_FP32)
+    e = launch_hemm_step_real<float>(static_cast<const float*>(H), ldh, n,
+                                     static_cast<const float*>(X), ldx, static_cast<float*>(OUT),
+                                     ldo, ncols, static_cast<float>(alpha),
+                                     static_cast<float>(beta), static_cast<float>(gamma),
+                                     ctx->prod, ctx->stream);
   else if (precision == CHASE_FP32_3M)
     e = launch_hemm_step_3m(static_cast<const float*>(H), ldh, n, static_cast<const float*>(X), ldx,
                             static_cast<float*>(OUT), ldo, ncols, static_cast<float>(alpha),

@@ -1,4 +1,5 @@
-// Host side of the Chebyshev filter (Algorithm 4 with the scaled recurrence of Eq. (7)).
+// Host side of the Chebyshev filter (Algorithm 4 with the scaled recurrence of Eq. (7)), for
+// complex Hermitian H (4M or 3M products) and real symmetric H (kind 3, real products).
 //
 // The coefficients are scalars computed here in FP64 and passed to each launch:
 //   product 1:   W <- (sigma_1/e) (H - cI) V                      (Alg. 4 line 4)
@@ -17,12 +18,16 @@ hipError_t run_filter(const T* H, int64_t ldh, int64_t n, T* V, T* W, int64_t ld
                       const ProductScratch& ps, hipStream_t stream, int64_t* matvecs_out,
                       int kind) {
   int64_t matvecs = 0;
+  const int ew = kind == 3 ? 1 : 2;  // values per element
   if (ncols > 0 && n > 0) {
     for (const FilterProduct& p : filter_schedule(ncols, degrees, b_sup, mu_1, mu_nevnex)) {
-      const T* X = (p.from_v ? V : W) + 2 * p.col0 * ld;
-      T* OUT = (p.from_v ? W : V) + 2 * p.col0 * ld;
+      const T* X = (p.from_v ? V : W) + ew * p.col0 * ld;
+      T* OUT = (p.from_v ? W : V) + ew * p.col0 * ld;
       hipError_t err;
-      if constexpr (sizeof(T) == 4) {
+      if (kind == 3) {
+        err = launch_hemm_step_real<T>(H, ldh, n, X, ld, OUT, ld, p.ncols, static_cast<T>(p.alpha),
+                                       static_cast<T>(p.beta), static_cast<T>(p.gamma), ps, stream);
+      } else if constexpr (sizeof(T) == 4) {
         if (kind == 2)
           err = launch_hemm_step_3m(H, ldh, n, X, ld, OUT, ld, p.ncols, static_cast<T>(p.alpha),
                                     static_cast<T>(p.beta), static_cast<T>(p.gamma), ps, stream);

@@ -564,6 +564,165 @@ __device__ __forceinline__ void tile_foreach_3m(const typename C::Frag& f, Fn&& 
       }
 }
 
+// ---------------------------------------------------------------------------------------------
+// Real symmetric H (the real variants of the solver): the product is a plain real GEMM, so the
+// MFMA operands are H and X themselves.  BM x BN real outputs per workgroup, K staged KT at a
+// time as in the complex tiles; each wave owns RT x CT MFMA tiles of 16 x 16.
+template <typename T, int BM_, int BN_, int KT_, int WR_, int WC_, int PAD_ = 2>
+struct TileR {
+  static constexpr int KIND = 2;
+  static constexpr int BMC = BM_, BNC = BN_, KT = KT_, WR = WR_, WC = WC_;  // real rows / columns
+  static constexpr int PROMOTE = 0;
+  static constexpr int RT = BM_ / WR_ / 16;
+  static constexpr int CT = BN_ / WC_ / 16;
+  static constexpr int AR = BM_ + PAD_;
+  static constexpr int BR = BN_ + PAD_;
+  static_assert(WR * WC == 4, "four waves");
+  static_assert(RT >= 1 && CT >= 1, "wave tile too small");
+  using acc_t = typename Acc<T>::type;
+  struct Smem {
+    T As[2][KT][AR];
+    T Bs[2][KT][BR];
+  };
+  struct Frag {
+    acc_t acc[RT][CT];
+  };
+};
+
+// acc <- H[i0.., k] X[k, j0..] over the K stages ka <= kt < kb (real H and X, column-major).
+// V2: loads of two consecutive elements (16 bytes for double); the caller guarantees aligned H
+// and X and even n, ldh and ldx, so a two-element unit is wholly inside or wholly outside.
+template <typename T, class C, bool V2 = false>
+__device__ __forceinline__ void tile_mainloop_real(typename C::Smem& sm, typename C::Frag& f,
+                                                const T* __restrict__ H, int64_t ldh, int n,
+                                                const T* __restrict__ X, int64_t ldx, int ncols,
+                                                int i0, int j0, int ka, int kb) {
+  using acc_t = typename C::acc_t;
+  // elements per global load of A and of B (B stays at one element when a stage of B has
+  // fewer than two elements per thread)
+  constexpr int VEA = V2 ? 2 : 1;
+  constexpr int VEB = (V2 && C::BNC * C::KT >= 2 * kThreads) ? 2 : 1;
+  struct alignas(sizeof(T) * VEA) VLA { T e[VEA]; };
+  struct alignas(sizeof(T) * VEB) VLB { T e[VEB]; };
+  static_assert(sizeof(VLA) == sizeof(T) * VEA && sizeof(VLB) == sizeof(T) * VEB, "unit size");
+  constexpr int A_LD = C::BMC * C::KT / (kThreads * VEA);
+  constexpr int B_LD = C::BNC * C::KT / (kThreads * VEB);
+  static_assert(A_LD >= 1 && A_LD * kThreads * VEA == C::BMC * C::KT, "A load split");
+  static_assert(B_LD >= 1 && B_LD * kThreads * VEB == C::BNC * C::KT, "B load split");
+  static_assert(kThreads % (C::BMC / VEA) == 0 && kThreads % (C::KT / VEB) == 0, "load strides");
+  static_assert(VEA == 1 || (C::AR * sizeof(T)) % (sizeof(T) * VEA) == 0, "aligned LDS rows");
+  static_assert(A_LD + B_LD <= 32, "validity bits");
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 4, li = lane & 15;
+  const int wr = wave / C::WC, wc = wave % C::WC;
+  VLA ra[A_LD];
+  VLB rb[B_LD];
+  // Same load scheme as the complex tiles: one base pointer per operand, unconditional loads,
+  // out-of-range units zeroed when written to LDS.
+  const bool tile_full = i0 + C::BMC <= n && j0 + C::BNC <= ncols;
+  const T* const pa0 = H + static_cast<int64_t>(i0 + (tid % (C::BMC / VEA)) * VEA) +
+                       static_cast<int64_t>(tid / (C::BMC / VEA)) * ldh;
+  const T* const pb0 = X + static_cast<int64_t>((tid % (C::KT / VEB)) * VEB) +
+                       static_cast<int64_t>(j0 + tid / (C::KT / VEB)) * ldx;
+  const int64_t sa = static_cast<int64_t>(kThreads / (C::BMC / VEA)) * ldh;
+  const int64_t sb = static_cast<int64_t>(kThreads / (C::KT / VEB)) * ldx;
+  uint32_t valid = 0;
+  auto load_tiles = [&](int k0) {
+    const bool fast = tile_full && k0 + C::KT <= n;
+    const T* a = pa0 + static_cast<int64_t>(k0) * ldh;
+    const T* b = pb0 + static_cast<int64_t>(k0);
+    uint32_t bits = 0;
+#pragma unroll
+    for (int q = 0; q < A_LD; ++q) {
+      const int idx = tid + kThreads * q;
+      const int kk = idx / (C::BMC / VEA), ci = (idx % (C::BMC / VEA)) * VEA;
+      const bool ok = fast || (k0 + kk < n && i0 + ci + VEA - 1 < n);
+      ra[q] = *reinterpret_cast<const VLA*>(ok ? a + q * sa : H);
+      bits |= (ok ? 1u : 0u) << q;
+    }
+#pragma unroll
+    for (int q = 0; q < B_LD; ++q) {
+      const int idx = tid + kThreads * q;
+      const int jj = idx / (C::KT / VEB), kk = (idx % (C::KT / VEB)) * VEB;
+      const bool ok = fast || (j0 + jj < ncols && k0 + kk + VEB - 1 < n);
+      rb[q] = *reinterpret_cast<const VLB*>(ok ? b + q * sb : X);
+      bits |= (ok ? 1u : 0u) << (A_LD + q);
+    }
+    valid = bits;
+  };
+  auto store_tiles = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < A_LD; ++q) {
+      const int idx = tid + kThreads * q;
+      const int kk = idx / (C::BMC / VEA), ci = (idx % (C::BMC / VEA)) * VEA;
+      VLA v = ra[q];
+      if (!((valid >> q) & 1u)) {
+#pragma unroll
+        for (int e = 0; e < VEA; ++e) v.e[e] = T(0);
+      }
+      *reinterpret_cast<VLA*>(&sm.As[buf][kk][ci]) = v;
+    }
+#pragma unroll
+    for (int q = 0; q < B_LD; ++q) {
+      const int idx = tid + kThreads * q;
+      const int jj = idx / (C::KT / VEB), kk = (idx % (C::KT / VEB)) * VEB;
+      const bool ok = (valid >> (A_LD + q)) & 1u;
+#pragma unroll
+      for (int e = 0; e < VEB; ++e) sm.Bs[buf][kk + e][jj] = ok ? rb[q].e[e] : T(0);
+    }
+  };
+
+#pragma unroll
+  for (int a = 0; a < C::RT; ++a)
+#pragma unroll
+    for (int b = 0; b < C::CT; ++b) f.acc[a][b] = acc_t{0};
+
+  const int rbase = wr * (C::BMC / C::WR);
+  const int cbase = wc * (C::BNC / C::WC);
+  load_tiles(ka * C::KT);
+  store_tiles(0);
+  __syncthreads();
+  for (int kt = ka; kt < kb; ++kt) {
+    const int cur = (kt - ka) & 1;
+    if (kt + 1 < kb) load_tiles((kt + 1) * C::KT);
+#pragma unroll
+    for (int s = 0; s < C::KT / 4; ++s) {
+      const int k = 4 * s + g;
+      T a[C::RT], b[C::CT];
+#pragma unroll
+      for (int rt = 0; rt < C::RT; ++rt) a[rt] = sm.As[cur][k][rbase + rt * 16 + li];
+#pragma unroll
+      for (int ct = 0; ct < C::CT; ++ct) b[ct] = sm.Bs[cur][k][cbase + ct * 16 + li];
+#pragma unroll
+      for (int rt = 0; rt < C::RT; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < C::CT; ++ct) f.acc[rt][ct] = mfma(a[rt], b[ct], f.acc[rt][ct]);
+    }
+    if (kt + 1 < kb) store_tiles(cur ^ 1);
+    __syncthreads();
+  }
+}
+
+// Visit the real results held by this lane: fn(row_in_tile, col_in_tile, value, 0).
+template <typename T, class C, typename Fn>
+__device__ __forceinline__ void tile_foreach_real(const typename C::Frag& f, Fn&& fn) {
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 4, li = lane & 15;
+  const int wr = wave / C::WC, wc = wave % C::WC;
+#pragma unroll
+  for (int rt = 0; rt < C::RT; ++rt)
+#pragma unroll
+    for (int ct = 0; ct < C::CT; ++ct)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int rr = sizeof(T) == 8 ? g + 4 * e : 4 * g + e;  // accumulator row layout
+        fn(wr * (C::BMC / C::WR) + rt * 16 + rr, wc * (C::BNC / C::WC) + ct * 16 + li,
+           static_cast<T>(f.acc[rt][ct][e]), T(0));
+      }
+}
+
 // Dispatch on the tile kind (4M interleaved or 3M planar).
 template <typename T, class C, bool V16 = false>
 __device__ __forceinline__ void tile_mainloop(typename C::Smem& sm, typename C::Frag& f,
@@ -572,6 +731,8 @@ __device__ __forceinline__ void tile_mainloop(typename C::Smem& sm, typename C::
                                               int i0, int j0, int ka, int kb) {
   if constexpr (C::KIND == 1)
     tile_mainloop_3m<C, V16>(sm, f, H, ldh, n, X, ldx, ncols, i0, j0, ka, kb);
+  else if constexpr (C::KIND == 2)
+    tile_mainloop_real<T, C, V16>(sm, f, H, ldh, n, X, ldx, ncols, i0, j0, ka, kb);
   else
     tile_mainloop_4m<T, C, V16>(sm, f, H, ldh, n, X, ldx, ncols, i0, j0, ka, kb);
 }
@@ -580,6 +741,8 @@ template <typename T, class C, typename Fn>
 __device__ __forceinline__ void tile_foreach(const typename C::Frag& f, Fn&& fn) {
   if constexpr (C::KIND == 1)
     tile_foreach_3m<C>(f, fn);
+  else if constexpr (C::KIND == 2)
+    tile_foreach_real<T, C>(f, fn);
   else
     tile_foreach_4m<T, C>(f, fn);
 }
@@ -603,6 +766,32 @@ __device__ __forceinline__ void epilogue_store(const T* __restrict__ X, int64_t 
   *reinterpret_cast<v2*>(o) = v2{ore, oim};
 }
 
+// Real data: OUT <- alpha*HX + gamma*X + beta*OUT at (row, col).
+template <typename T>
+__device__ __forceinline__ void epilogue_store_real(const T* __restrict__ X, int64_t ldx,
+                                                    T* __restrict__ OUT, int64_t ldo, int row,
+                                                    int col, T v, T alpha, T beta, T gamma) {
+  const T x = X[static_cast<int64_t>(row) + static_cast<int64_t>(col) * ldx];
+  T* o = OUT + static_cast<int64_t>(row) + static_cast<int64_t>(col) * ldo;
+  T r = alpha * v + gamma * x;
+  if (beta != T(0)) r += beta * *o;
+  *o = r;
+}
+
+// The epilogue of the tile's element type (complex interleaved or real).
+template <typename T, class C>
+__device__ __forceinline__ void store_result(const T* __restrict__ X, int64_t ldx,
+                                             T* __restrict__ OUT, int64_t ldo, int row, int col,
+                                             T hre, T him, T alpha, T beta, T gamma) {
+  if constexpr (C::KIND == 2)
+    epilogue_store_real<T>(X, ldx, OUT, ldo, row, col, hre, alpha, beta, gamma);
+  else
+    epilogue_store<T>(X, ldx, OUT, ldo, row, col, hre, him, alpha, beta, gamma);
+}
+
+// Values per output element: 2 for complex tiles, 1 for real ones.
+template <class C> constexpr int elem_width() { return C::KIND == 2 ? 1 : 2; }
+
 // Data-parallel schedule: one workgroup per output tile (row tiles vary fastest).
 template <typename T, class C, int OCC, bool V16>
 __global__ __launch_bounds__(kThreads, OCC) void hemm_dp_kernel(
@@ -617,7 +806,7 @@ __global__ __launch_bounds__(kThreads, OCC) void hemm_dp_kernel(
   tile_mainloop<T, C, V16>(sm, f, H, ldh, n, X, ldx, ncols, i0, j0, 0, nk);
   tile_foreach<T, C>(f, [&](int r, int c, T hre, T him) {
     if (i0 + r < n && j0 + c < ncols)
-      epilogue_store<T>(X, ldx, OUT, ldo, i0 + r, j0 + c, hre, him, alpha, beta, gamma);
+      store_result<T, C>(X, ldx, OUT, ldo, i0 + r, j0 + c, hre, him, alpha, beta, gamma);
   });
 }
 
@@ -665,13 +854,13 @@ __global__ __launch_bounds__(kThreads, OCC) void hemm_sk_kernel(
     tile_mainloop<T, C, V16>(sm, f, H, ldh, n, X, ldx, ncols, i0, j0, 0, nk);
     tile_foreach<T, C>(f, [&](int r, int c, T hre, T him) {
       if (i0 + r < n && j0 + c < ncols)
-        epilogue_store<T>(X, ldx, OUT, ldo, i0 + r, j0 + c, hre, him, alpha, beta, gamma);
+        store_result<T, C>(X, ldx, OUT, ldo, i0 + r, j0 + c, hre, him, alpha, beta, gamma);
     });
   }
   if (units == 0) return;
   const int64_t u0 = sk_start(p, units, P), u1 = sk_start(p + 1, units, P);
   const int64_t t_first = u0 / nk;
-  constexpr int TE = C::BMC * C::BNC;  // complex elements per tile
+  constexpr int TE = C::BMC * C::BNC;  // output elements per tile
   int64_t u = u0;
   while (u < u1) {
     const int64_t tr = u / nk;  // tile index within the stream-K part
@@ -685,13 +874,14 @@ __global__ __launch_bounds__(kThreads, OCC) void hemm_sk_kernel(
     if (ka == 0 && kb == nk) {
       tile_foreach<T, C>(f, [&](int r, int c, T hre, T him) {
         if (i0 + r < n && j0 + c < ncols)
-          epilogue_store<T>(X, ldx, OUT, ldo, i0 + r, j0 + c, hre, him, alpha, beta, gamma);
+          store_result<T, C>(X, ldx, OUT, ldo, i0 + r, j0 + c, hre, him, alpha, beta, gamma);
       });
     } else {
-      T* dst = partial + 2 * (p * 2 + (tr == t_first ? 0 : 1)) * TE;
+      constexpr int EW = elem_width<C>();
+      T* dst = partial + EW * (p * 2 + (tr == t_first ? 0 : 1)) * TE;
       tile_foreach<T, C>(f, [&](int r, int c, T hre, T him) {
-        dst[2 * (r + c * C::BMC)] = hre;
-        dst[2 * (r + c * C::BMC) + 1] = him;
+        dst[EW * (r + c * C::BMC)] = hre;
+        if constexpr (EW == 2) dst[EW * (r + c * C::BMC) + 1] = him;
       });
     }
     u = tr * nk + kb;
@@ -723,12 +913,13 @@ __global__ __launch_bounds__(kThreads) void hemm_fixup_kernel(
     for (int64_t pp = pf; pp <= pl; ++pp) {
       const int64_t a = sk_start(pp, units, P), b = sk_start(pp + 1, units, P);
       if (a >= b) continue;  // empty range
-      const T* src = partial + 2 * (pp * 2 + (a / nk == tr ? 0 : 1)) * TE;
-      hre += src[2 * e];
-      him += src[2 * e + 1];
+      constexpr int EW = elem_width<C>();
+      const T* src = partial + EW * (pp * 2 + (a / nk == tr ? 0 : 1)) * TE;
+      hre += src[EW * e];
+      if constexpr (EW == 2) him += src[EW * e + 1];
     }
     if (i0 + r < n && j0 + c < ncols)
-      epilogue_store<T>(X, ldx, OUT, ldo, i0 + r, j0 + c, hre, him, alpha, beta, gamma);
+      store_result<T, C>(X, ldx, OUT, ldo, i0 + r, j0 + c, hre, him, alpha, beta, gamma);
   }
 }
 
@@ -752,7 +943,7 @@ __global__ __launch_bounds__(kThreads, OCC) void hemm_group_kernel(GroupArgs<T> 
   tile_mainloop<T, C, V16>(sm, f, d.H, d.ldh, d.n, d.X, d.ldx, d.ncols, i0, j0, 0, nk);
   tile_foreach<T, C>(f, [&](int r, int c, T hre, T him) {
     if (i0 + r < d.n && j0 + c < d.ncols)
-      epilogue_store<T>(d.X, d.ldx, d.OUT, d.ldo, i0 + r, j0 + c, hre, him, d.alpha, d.beta,
+      store_result<T, C>(d.X, d.ldx, d.OUT, d.ldo, i0 + r, j0 + c, hre, him, d.alpha, d.beta,
                         d.gamma);
   });
 }
@@ -774,7 +965,7 @@ hipError_t launch_dp(const T* H, int64_t ldh, int64_t n, const T* X, int64_t ldx
 // Bytes of partial-sum scratch the stream-K schedule needs for P persistent workgroups.
 template <typename T, class C>
 constexpr size_t sk_scratch_bytes(int64_t P) {
-  return static_cast<size_t>(P) * 2 * C::BMC * C::BNC * 2 * sizeof(T);
+  return static_cast<size_t>(P) * 2 * C::BMC * C::BNC * elem_width<C>() * sizeof(T);
 }
 
 template <typename T, class C, int OCC, bool V16 = false>
@@ -834,6 +1025,10 @@ template <typename T> using NarrowTile = Tile<T, 64, 32, 16, 4, 1, sizeof(T) == 
 // waste over 10 % more work than padding to 32.
 using SlimTile64 = Tile<double, 64, 32, 8, 2, 2, 2, 0, false, 1, 2>;
 constexpr int kOccSlim = 4;
+// Real tiles: 128 x 128 real outputs (the complex wide tile's register and LDS footprint); a
+// 256 x 16 tile for the thin blocks of the Lanczos runs.
+template <typename T> using RealTile = TileR<T, 128, 128, 16, 2, 2, sizeof(T) == 4 ? 4 : 2>;
+template <typename T> using RealThinTile = TileR<T, 256, 16, 16, 4, 1, sizeof(T) == 4 ? 4 : 2>;
 constexpr double kSlimCost = 1.10;
 
 // 3M tile for the planar FP32 products (FP64 promotion every two stages, i.e. every 32 K terms).
@@ -848,6 +1043,17 @@ bool use_v16(const T* H, int64_t ldh, const T* X, int64_t ldx, int64_t n) {
 }
 constexpr int kOcc = 2;  // workgroups per CU the tiles are built for
 
+// Wide global loads: two-element units for complex64 (16 bytes) or for real data.
+template <typename T, class C>
+bool wide_loads(const T* H, int64_t ldh, const T* X, int64_t ldx, int64_t n) {
+  if constexpr (C::KIND == 2)
+    return (reinterpret_cast<uintptr_t>(H) % (2 * sizeof(T))) == 0 &&
+           (reinterpret_cast<uintptr_t>(X) % (2 * sizeof(T))) == 0 && ldh % 2 == 0 &&
+           ldx % 2 == 0 && n % 2 == 0;
+  else
+    return use_v16(H, ldh, X, ldx, n);
+}
+
 template <typename T, class C, int OCC = kOcc>
 hipError_t launch_sched(const T* H, int64_t ldh, int64_t n, const T* X, int64_t ldx, T* OUT,
                         int64_t ldo, int64_t ncols, T alpha, T beta, T gamma,
@@ -856,7 +1062,7 @@ hipError_t launch_sched(const T* H, int64_t ldh, int64_t n, const T* X, int64_t 
   const int64_t slots = static_cast<int64_t>(ps.cus) * OCC;
   const int64_t rounds = (tiles + slots - 1) / slots;
   const double eff = static_cast<double>(tiles) / static_cast<double>(rounds * slots);
-  const bool v16 = v16_ok && use_v16(H, ldh, X, ldx, n);
+  const bool v16 = v16_ok && wide_loads<T, C>(H, ldh, X, ldx, n);
   if (eff >= 0.92 || !ps.ptr || sk_scratch_bytes<T, C>(slots) > ps.bytes) {
     if (v16)
       return launch_dp<T, C, OCC, true>(H, ldh, n, X, ldx, OUT, ldo, ncols, alpha, beta, gamma,
@@ -877,8 +1083,29 @@ size_t product_scratch_bytes(int cus) {
   b = std::max(b, sk_scratch_bytes<float, WideTile<float>>(slots));
   b = std::max(b, sk_scratch_bytes<double, NarrowTile<double>>(slots));
   b = std::max(b, sk_scratch_bytes<double, SlimTile64>(static_cast<int64_t>(cus) * kOccSlim));
+  b = std::max(b, sk_scratch_bytes<double, RealTile<double>>(slots));
+  b = std::max(b, sk_scratch_bytes<double, RealThinTile<double>>(slots));
   return b;
 }
+
+template <typename T>
+hipError_t launch_hemm_step_real(const T* H, int64_t ldh, int64_t n, const T* X, int64_t ldx,
+                                 T* OUT, int64_t ldo, int64_t ncols, T alpha, T beta, T gamma,
+                                 const ProductScratch& ps, hipStream_t stream) {
+  if (n <= 0 || ncols <= 0) return hipSuccess;
+  if (ncols <= 16)
+    return launch_sched<T, RealThinTile<T>>(H, ldh, n, X, ldx, OUT, ldo, ncols, alpha, beta,
+                                            gamma, ps, stream);
+  return launch_sched<T, RealTile<T>>(H, ldh, n, X, ldx, OUT, ldo, ncols, alpha, beta, gamma, ps,
+                                      stream);
+}
+template hipError_t launch_hemm_step_real<double>(const double*, int64_t, int64_t, const double*,
+                                                  int64_t, double*, int64_t, int64_t, double,
+                                                  double, double, const ProductScratch&,
+                                                  hipStream_t);
+template hipError_t launch_hemm_step_real<float>(const float*, int64_t, int64_t, const float*,
+                                                 int64_t, float*, int64_t, int64_t, float, float,
+                                                 float, const ProductScratch&, hipStream_t);
 
 template <typename T>
 hipError_t launch_hemm_step(const T* H, int64_t ldh, int64_t n, const T* X, int64_t ldx, T* OUT,
@@ -993,6 +1220,35 @@ hipError_t launch_convert_c128_to_c64(const double* src, int64_t lds, float* dst
   if (rows <= 0 || cols <= 0) return hipSuccess;
   hipLaunchKernelGGL((convert_kernel<double, float>), dim3(convert_blocks(rows * cols)), dim3(256),
                      0, stream, src, lds, dst, ldd, rows, cols);
+  return hipGetLastError();
+}
+
+namespace {
+template <typename S, typename D>
+__global__ void convert_real_kernel(const S* __restrict__ src, int64_t lds, D* __restrict__ dst,
+                                    int64_t ldd, int64_t rows, int64_t cols) {
+  const int64_t total = rows * cols;
+  for (int64_t t = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; t < total;
+       t += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int64_t r = t % rows, c = t / rows;
+    dst[r + c * ldd] = static_cast<D>(src[r + c * lds]);
+  }
+}
+}  // namespace
+
+hipError_t launch_convert_f64_to_f32(const double* src, int64_t lds, float* dst, int64_t ldd,
+                                     int64_t rows, int64_t cols, hipStream_t stream) {
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  hipLaunchKernelGGL((convert_real_kernel<double, float>), dim3(convert_blocks(rows * cols)),
+                     dim3(256), 0, stream, src, lds, dst, ldd, rows, cols);
+  return hipGetLastError();
+}
+
+hipError_t launch_convert_f32_to_f64(const float* src, int64_t lds, double* dst, int64_t ldd,
+                                     int64_t rows, int64_t cols, hipStream_t stream) {
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  hipLaunchKernelGGL((convert_real_kernel<float, double>), dim3(convert_blocks(rows * cols)),
+                     dim3(256), 0, stream, src, lds, dst, ldd, rows, cols);
   return hipGetLastError();
 }
 

@@ -30,6 +30,13 @@ hipError_t launch_hemm_step(const T* H, int64_t ldh, int64_t n, const T* X, int6
                             int64_t ldo, int64_t ncols, T alpha, T beta, T gamma,
                             const ProductScratch& ps, hipStream_t stream);
 
+// The same product for real symmetric H and real X, OUT (T = double or float); leading
+// dimensions count real elements.
+template <typename T>
+hipError_t launch_hemm_step_real(const T* H, int64_t ldh, int64_t n, const T* X, int64_t ldx,
+                                 T* OUT, int64_t ldo, int64_t ncols, T alpha, T beta, T gamma,
+                                 const ProductScratch& ps, hipStream_t stream);
+
 // One product of one problem inside a grouped launch (fields as in launch_hemm_step;
 // tile_begin is filled by the launcher).  Zero-column products are allowed and skipped.
 template <typename T>
@@ -67,25 +74,34 @@ hipError_t launch_convert_c128_to_c64(const double* src, int64_t lds, float* dst
 hipError_t launch_convert_c64_to_c128(const float* src, int64_t lds, double* dst, int64_t ldd,
                                       int64_t rows, int64_t cols, hipStream_t stream);
 
-// Outer-loop helpers (loop_kernels.hip); complex128 data as interleaved doubles.
+// Real float64 <-> float32 copies of an m x cols column-major block.
+hipError_t launch_convert_f64_to_f32(const double* src, int64_t lds, float* dst, int64_t ldd,
+                                     int64_t rows, int64_t cols, hipStream_t stream);
+hipError_t launch_convert_f32_to_f64(const float* src, int64_t lds, double* dst, int64_t ldd,
+                                     int64_t rows, int64_t cols, hipStream_t stream);
+
+// Outer-loop helpers (loop_kernels.hip).  w = values per element: 2 for complex128 data
+// (interleaved doubles), 1 for real float64 data; leading dimensions count elements.
 hipError_t launch_lanczos_step(const double* U, const double* Up, double* W, double* Un, int64_t n,
                                int64_t ld, int64_t nv, const double* beta_prev, double* alpha_out,
-                               double* beta_out, hipStream_t s);
-hipError_t launch_normalize(double* X, int64_t n, int64_t ld, int64_t cols, hipStream_t s);
+                               double* beta_out, hipStream_t s, int w = 2);
+hipError_t launch_normalize(double* X, int64_t n, int64_t ld, int64_t cols, hipStream_t s,
+                            int w = 2);
 hipError_t launch_resid(const double* AV, const double* V, const double* lam, int64_t n, int64_t ld,
-                        int64_t cols, double* out, hipStream_t s);
+                        int64_t cols, double* out, hipStream_t s, int w = 2);
 hipError_t launch_gather(const double* src, int64_t lds, double* dst, int64_t ldd, int64_t n,
-                         const int* perm, int64_t cols, hipStream_t s);
-hipError_t launch_herm_sym(double* G, int64_t ld, int64_t m, hipStream_t s);
-hipError_t launch_add_diag(double* G, int64_t ld, int64_t m, double v, hipStream_t s);
+                         const int* perm, int64_t cols, hipStream_t s, int w = 2);
+hipError_t launch_herm_sym(double* G, int64_t ld, int64_t m, hipStream_t s, int w = 2);
+hipError_t launch_add_diag(double* G, int64_t ld, int64_t m, double v, hipStream_t s, int w = 2);
 hipError_t launch_gaussian(double* X, int64_t n, int64_t ld, int64_t cols, uint64_t seed,
-                           hipStream_t s);
+                           hipStream_t s, int w = 2);
 
 // ----------------------------------------------------------------------------- filter driver
 
 // Algorithm 4 on an n x ncols block with sorted even degrees (validated by the caller).  The
 // result ends in V.  scalars: the per-product (alpha, beta, gamma) in FP64.
-// kind: 0 complex128 (4M), 1 complex64 interleaved (4M), 2 complex64 planar H (3M).
+// kind: 0 complex128 (4M), 1 complex64 interleaved (4M), 2 complex64 planar H (3M),
+// 3 real data (T = double or float).
 template <typename T>
 hipError_t run_filter(const T* H, int64_t ldh, int64_t n, T* V, T* W, int64_t ld, int64_t ncols,
                       const int32_t* degrees, double b_sup, double mu_1, double mu_nevnex,

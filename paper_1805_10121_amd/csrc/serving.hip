@@ -269,7 +269,8 @@ struct chase_server {
 namespace {
 
 size_t state_bytes_of(const chase_config& c) {
-  return static_cast<size_t>(c.n) * static_cast<size_t>(c.nev + c.nex) * 16;
+  return static_cast<size_t>(c.n) * static_cast<size_t>(c.nev + c.nex) *
+         (c.real_symmetric ? 8 : 16);
 }
 
 size_t ws_bytes_of(const chase_config& c, bool warm) {
@@ -340,7 +341,7 @@ void chase_server::worker(int w) {
       if (e == hipSuccess) e = hipMalloc(&seq->V, state_bytes_of(req->cfg));
       if (e == hipSuccess)
         e = chase::launch_gaussian(seq->V, req->cfg.n, req->cfg.n, nb, req->cfg.seed ^ 0x5eedULL,
-                                   ctx->stream);
+                                   ctx->stream, req->cfg.real_symmetric ? 1 : 2);
       if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
       if (e != hipSuccess) {
         (void)hipGetLastError();

@@ -13,6 +13,8 @@
 //                     (sort); the new column order is applied on the device by one gather.
 // LANCZOS (Alg. 6) runs first: the b_sup run and the n_vec DoS runs are independent, so they
 // advance together as one block product per step.
+// The same loop serves complex Hermitian H (complex128 data, Z routines) and real symmetric H
+// (float64 data, D routines, real product kernel): w_ = values per element (2 or 1).
 
 #include <algorithm>
 #include <cmath>
@@ -39,37 +41,38 @@ struct Layout {
 
 size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
 
-Layout make_layout(int64_t n, int64_t nb, int64_t nv, int64_t k, bool mixed) {
+Layout make_layout(int64_t n, int64_t nb, int64_t nv, int64_t k, bool mixed, int w) {
   Layout L{};
+  const size_t es = 8 * static_cast<size_t>(w);  // bytes per element
   size_t off = 0;
   auto take = [&](size_t bytes) {
     size_t o = off;
     off = align256(off + bytes);
     return o;
   };
-  const size_t blk = static_cast<size_t>(n) * nb * 16;
+  const size_t blk = static_cast<size_t>(n) * nb * es;
   L.V = take(blk);
   L.W = take(blk);
   L.AQ = take(blk);
   L.X = take(blk);
-  L.G = take(static_cast<size_t>(nb) * nb * 16);
-  L.T = take(static_cast<size_t>(nb) * nb * 16);
+  L.G = take(static_cast<size_t>(nb) * nb * es);
+  L.T = take(static_cast<size_t>(nb) * nb * es);
   L.lam = take(nb * 8);
   L.res = take(nb * 8);
   L.evE = take(nb * 8);
   L.perm = take(nb * 4);
   L.info = take(64);
-  L.U = take(static_cast<size_t>(n) * nv * (k + 1) * 16);
-  L.Wl = take(static_cast<size_t>(n) * nv * 16);
+  L.U = take(static_cast<size_t>(n) * nv * (k + 1) * es);
+  L.Wl = take(static_cast<size_t>(n) * nv * es);
   L.lal = take(static_cast<size_t>(nv) * k * 8);
   L.lbe = take(static_cast<size_t>(nv) * k * 8);
   L.zero = take(static_cast<size_t>(nv) * 8);
-  L.Z = take(static_cast<size_t>(k) * nb * 16);
-  L.tau = take(nb * 16);
-  if (mixed) {
-    L.H32 = take(static_cast<size_t>(n) * n * 8);
-    L.V32 = take(static_cast<size_t>(n) * nb * 8);
-    L.W32 = take(static_cast<size_t>(n) * nb * 8);
+  L.Z = take(static_cast<size_t>(k) * nb * es);
+  L.tau = take(nb * es);
+  if (mixed) {  // FP32 copies: planar complex64 or real float32 H, and two blocks
+    L.H32 = take(static_cast<size_t>(n) * n * 4 * w);
+    L.V32 = take(static_cast<size_t>(n) * nb * 4 * w);
+    L.W32 = take(static_cast<size_t>(n) * nb * 4 * w);
   }
   L.total = off;
   return L;
@@ -98,12 +101,15 @@ class Solver {
   Layout L_{};
   char* base_ = nullptr;
   int64_t n_ = 0, nb_ = 0;
+  int w_ = 2;             // values per element: 2 complex, 1 real
+  bool real_ = false;
   hipStream_t s_ = nullptr;
   chase_stats st_{};
   int fallbacks_ = 0;
 
   template <typename P> P* at(size_t off) { return reinterpret_cast<P*>(base_ + off); }
-  double* col(size_t off, int64_t c) { return at<double>(off) + 2 * c * n_; }
+  double* col(size_t off, int64_t c) { return at<double>(off) + w_ * c * n_; }
+  size_t es() const { return 8 * static_cast<size_t>(w_); }
 
   int blas(rocblas_status s, const char* what) {
     if (s != rocblas_status_success)
@@ -116,9 +122,21 @@ class Solver {
       return set_error(ctx_, CHASE_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
     return CHASE_OK;
   }
-  int zgemm(rocblas_operation ta, rocblas_operation tb, int64_t m, int64_t nn, int64_t k,
-            double ar, const double* A, int64_t lda, const double* B, int64_t ldb, double br,
-            double* C, int64_t ldc) {
+  // C <- ar op(A) op(B) + br C with real scalars; conjugate transpose is the transpose for real
+  // data.
+  int gemm(rocblas_operation ta, rocblas_operation tb, int64_t m, int64_t nn, int64_t k,
+           double ar, const double* A, int64_t lda, const double* B, int64_t ldb, double br,
+           double* C, int64_t ldc) {
+    if (real_) {
+      auto rt = [](rocblas_operation o) {
+        return o == rocblas_operation_conjugate_transpose ? rocblas_operation_transpose : o;
+      };
+      return blas(rocblas_dgemm(ctx_->blas, rt(ta), rt(tb), static_cast<rocblas_int>(m),
+                                static_cast<rocblas_int>(nn), static_cast<rocblas_int>(k), &ar, A,
+                                static_cast<rocblas_int>(lda), B, static_cast<rocblas_int>(ldb),
+                                &br, C, static_cast<rocblas_int>(ldc)),
+                  "dgemm");
+    }
     const rocblas_double_complex al(ar, 0.0), be(br, 0.0);
     return blas(rocblas_zgemm(ctx_->blas, ta, tb, static_cast<rocblas_int>(m),
                               static_cast<rocblas_int>(nn), static_cast<rocblas_int>(k), &al,
@@ -129,6 +147,15 @@ class Solver {
                               reinterpret_cast<rocblas_double_complex*>(C),
                               static_cast<rocblas_int>(ldc)),
                 "zgemm");
+  }
+  // OUT <- alpha H X + gamma X + beta OUT with the product kernel of the element type.
+  hipError_t product(const double* H, int64_t ldh, const double* X, int64_t ldx, double* OUT,
+                     int64_t ldo, int64_t ncols, double alpha, double beta, double gamma) {
+    if (real_)
+      return launch_hemm_step_real<double>(H, ldh, n_, X, ldx, OUT, ldo, ncols, alpha, beta,
+                                           gamma, ctx_->prod, s_);
+    return launch_hemm_step<double>(H, ldh, n_, X, ldx, OUT, ldo, ncols, alpha, beta, gamma,
+                                    ctx_->prod, s_);
   }
   int lanczos(const double* H, int64_t ldh, double* V);
   int cgs(int64_t nlock, int64_t nact);
@@ -154,25 +181,25 @@ int Solver::lanczos(const double* H, int64_t ldh, double* V) {
   double* U = at<double>(L_.U);
   int rc;
   if (cfg_.lanczos_start) {
-    rc = hip(hipMemcpyAsync(U, cfg_.lanczos_start, static_cast<size_t>(n_) * nv * 16,
+    rc = hip(hipMemcpyAsync(U, cfg_.lanczos_start, static_cast<size_t>(n_) * nv * es(),
                             hipMemcpyDeviceToDevice, s_),
              "copy lanczos start");
   } else {
-    rc = hip(launch_gaussian(U, n_, n_, nv, cfg_.seed, s_), "gaussian");
+    rc = hip(launch_gaussian(U, n_, n_, nv, cfg_.seed, s_, w_), "gaussian");
   }
   if (rc) return rc;
-  if ((rc = hip(launch_normalize(U, n_, n_, nv, s_), "normalize"))) return rc;
+  if ((rc = hip(launch_normalize(U, n_, n_, nv, s_, w_), "normalize"))) return rc;
   if ((rc = hip(hipMemsetAsync(at<double>(L_.zero), 0, nv * 8, s_), "memset"))) return rc;
   double* Wl = at<double>(L_.Wl);
   for (int j = 0; j < k; ++j) {
-    double* Uj = U + 2 * static_cast<int64_t>(j) * nv * n_;
-    const double* Up = j > 0 ? U + 2 * static_cast<int64_t>(j - 1) * nv * n_ : Uj;
+    double* Uj = U + w_ * static_cast<int64_t>(j) * nv * n_;
+    const double* Up = j > 0 ? U + w_ * static_cast<int64_t>(j - 1) * nv * n_ : Uj;
     const double* bp = j > 0 ? at<double>(L_.lbe) + (j - 1) * nv : at<double>(L_.zero);
-    if ((rc = hip(launch_hemm_step<double>(H, ldh, n_, Uj, n_, Wl, n_, nv, 1.0, 0.0, 0.0, ctx_->prod, s_),
-                  "lanczos product")))
+    if ((rc = hip(product(H, ldh, Uj, n_, Wl, n_, nv, 1.0, 0.0, 0.0), "lanczos product")))
       return rc;
-    if ((rc = hip(launch_lanczos_step(Uj, Up, Wl, Uj + 2 * nv * n_, n_, n_, nv, bp,
-                                      at<double>(L_.lal) + j * nv, at<double>(L_.lbe) + j * nv, s_),
+    if ((rc = hip(launch_lanczos_step(Uj, Up, Wl, Uj + w_ * nv * n_, n_, n_, nv, bp,
+                                      at<double>(L_.lal) + j * nv, at<double>(L_.lbe) + j * nv, s_,
+                                      w_),
                   "lanczos step")))
       return rc;
   }
@@ -210,15 +237,15 @@ int Solver::lanczos(const double* H, int64_t ldh, double* V) {
     if (static_cast<int64_t>(sel.size()) > nb_) sel.resize(nb_);
     const int64_t r = static_cast<int64_t>(sel.size());
     if (r > 0) {
-      std::vector<double> Zh(static_cast<size_t>(r1.k) * r * 2, 0.0);  // k x r complex, col-major
+      std::vector<double> Zh(static_cast<size_t>(r1.k) * r * w_, 0.0);  // k x r, col-major
       for (int64_t q = 0; q < r; ++q)
-        for (int j = 0; j < r1.k; ++j) Zh[2 * (j + q * r1.k)] = r1.evecs[j * r1.k + sel[q]];
+        for (int j = 0; j < r1.k; ++j) Zh[w_ * (j + q * r1.k)] = r1.evecs[j * r1.k + sel[q]];
       if ((rc = hip(hipMemcpyAsync(at<double>(L_.Z), Zh.data(), Zh.size() * 8,
                                    hipMemcpyHostToDevice, s_), "h2d")))
         return rc;
       // basis of DoS run 1: columns U_j[:, 1], j < k, stride nv*n between consecutive j
-      if ((rc = zgemm(rocblas_operation_none, rocblas_operation_none, n_, r, r1.k, 1.0,
-                      U + 2 * n_, nv * n_, at<double>(L_.Z), r1.k, 0.0, V, n_)))
+      if ((rc = gemm(rocblas_operation_none, rocblas_operation_none, n_, r, r1.k, 1.0,
+                      U + w_ * n_, nv * n_, at<double>(L_.Z), r1.k, 0.0, V, n_)))
         return rc;
       if ((rc = hip(hipStreamSynchronize(s_), "sync"))) return rc;
     }
@@ -232,10 +259,10 @@ int Solver::cgs(int64_t nlock, int64_t nact) {
   double* Y = at<double>(L_.V);
   double* A = col(L_.V, nlock);
   double* T = at<double>(L_.T);
-  int rc = zgemm(rocblas_operation_conjugate_transpose, rocblas_operation_none, nlock, nact, n_, 1.0,
+  int rc = gemm(rocblas_operation_conjugate_transpose, rocblas_operation_none, nlock, nact, n_, 1.0,
                  Y, n_, A, n_, 0.0, T, nb_);
   if (rc) return rc;
-  return zgemm(rocblas_operation_none, rocblas_operation_none, n_, nact, nlock, -1.0, Y, n_, T, nb_,
+  return gemm(rocblas_operation_none, rocblas_operation_none, n_, nact, nlock, -1.0, Y, n_, T, nb_,
                1.0, A, n_);
 }
 
@@ -246,29 +273,48 @@ int Solver::cholqr(int64_t nact, bool shift, bool* ok) {
   double* A = col(L_.V, n_ == 0 ? 0 : (nb_ - nact));
   double* G = at<double>(L_.G);
   const double one = 1.0, zero = 0.0;
-  int rc = blas(rocblas_zherk(ctx_->blas, rocblas_fill_upper, rocblas_operation_conjugate_transpose,
-                              static_cast<rocblas_int>(nact), static_cast<rocblas_int>(n_), &one,
-                              reinterpret_cast<const rocblas_double_complex*>(A),
-                              static_cast<rocblas_int>(n_), &zero,
-                              reinterpret_cast<rocblas_double_complex*>(G),
-                              static_cast<rocblas_int>(nb_)),
-                "zherk");
+  int rc = real_
+               ? blas(rocblas_dsyrk(ctx_->blas, rocblas_fill_upper, rocblas_operation_transpose,
+                                    static_cast<rocblas_int>(nact), static_cast<rocblas_int>(n_),
+                                    &one, A, static_cast<rocblas_int>(n_), &zero, G,
+                                    static_cast<rocblas_int>(nb_)),
+                      "dsyrk")
+               : blas(rocblas_zherk(ctx_->blas, rocblas_fill_upper,
+                                    rocblas_operation_conjugate_transpose,
+                                    static_cast<rocblas_int>(nact), static_cast<rocblas_int>(n_),
+                                    &one, reinterpret_cast<const rocblas_double_complex*>(A),
+                                    static_cast<rocblas_int>(n_), &zero,
+                                    reinterpret_cast<rocblas_double_complex*>(G),
+                                    static_cast<rocblas_int>(nb_)),
+                      "zherk");
   if (rc) return rc;
   if (shift) {
     const double s = 11.0 * (static_cast<double>(n_) * nact + static_cast<double>(nact) * (nact + 1)) *
                      kEps * static_cast<double>(nact);
-    if ((rc = hip(launch_add_diag(G, nb_, nact, s, s_), "add_diag"))) return rc;
+    if ((rc = hip(launch_add_diag(G, nb_, nact, s, s_, w_), "add_diag"))) return rc;
   }
-  if ((rc = blas(rocsolver_zpotrf(ctx_->blas, rocblas_fill_upper, static_cast<rocblas_int>(nact),
-                                  reinterpret_cast<rocblas_double_complex*>(G),
-                                  static_cast<rocblas_int>(nb_), at<rocblas_int>(L_.info)),
-                 "zpotrf")))
-    return rc;
+  rc = real_ ? blas(rocsolver_dpotrf(ctx_->blas, rocblas_fill_upper, static_cast<rocblas_int>(nact),
+                                     G, static_cast<rocblas_int>(nb_), at<rocblas_int>(L_.info)),
+                    "dpotrf")
+             : blas(rocsolver_zpotrf(ctx_->blas, rocblas_fill_upper, static_cast<rocblas_int>(nact),
+                                     reinterpret_cast<rocblas_double_complex*>(G),
+                                     static_cast<rocblas_int>(nb_), at<rocblas_int>(L_.info)),
+                    "zpotrf");
+  if (rc) return rc;
   int info = 0;
   if ((rc = read_info(&info))) return rc;
   if (info != 0) {
     *ok = false;
     return CHASE_OK;
+  }
+  if (real_) {
+    rc = blas(rocblas_dtrsm(ctx_->blas, rocblas_side_right, rocblas_fill_upper,
+                            rocblas_operation_none, rocblas_diagonal_non_unit,
+                            static_cast<rocblas_int>(n_), static_cast<rocblas_int>(nact), &one, G,
+                            static_cast<rocblas_int>(nb_), A, static_cast<rocblas_int>(n_)),
+              "dtrsm");
+    *ok = true;
+    return rc;
   }
   const rocblas_double_complex al(1.0, 0.0);
   rc = blas(rocblas_ztrsm(ctx_->blas, rocblas_side_right, rocblas_fill_upper, rocblas_operation_none,
@@ -287,10 +333,26 @@ int Solver::householder(int64_t nlock, int64_t nact) {
   ++fallbacks_;
   const int64_t ncol = nlock + nact;
   double* Wb = at<double>(L_.W);
-  int rc = hip(hipMemcpyAsync(Wb, at<double>(L_.V), static_cast<size_t>(n_) * ncol * 16,
+  int rc = hip(hipMemcpyAsync(Wb, at<double>(L_.V), static_cast<size_t>(n_) * ncol * es(),
                               hipMemcpyDeviceToDevice, s_),
                "copy");
   if (rc) return rc;
+  if (real_) {
+    double* tau = at<double>(L_.tau);
+    if ((rc = blas(rocsolver_dgeqrf(ctx_->blas, static_cast<rocblas_int>(n_),
+                                    static_cast<rocblas_int>(ncol), Wb,
+                                    static_cast<rocblas_int>(n_), tau),
+                   "dgeqrf")))
+      return rc;
+    if ((rc = blas(rocsolver_dorgqr(ctx_->blas, static_cast<rocblas_int>(n_),
+                                    static_cast<rocblas_int>(ncol), static_cast<rocblas_int>(ncol),
+                                    Wb, static_cast<rocblas_int>(n_), tau),
+                   "dorgqr")))
+      return rc;
+    return hip(hipMemcpyAsync(col(L_.V, nlock), Wb + nlock * n_,
+                              static_cast<size_t>(n_) * nact * es(), hipMemcpyDeviceToDevice, s_),
+               "copy");
+  }
   auto* tau = at<rocblas_double_complex>(L_.tau);
   if ((rc = blas(rocsolver_zgeqrf(ctx_->blas, static_cast<rocblas_int>(n_),
                                   static_cast<rocblas_int>(ncol),
@@ -313,7 +375,7 @@ int Solver::orthogonalize(int64_t nlock, int64_t nact) {
   int rc;
   double* A = col(L_.V, nlock);
   if ((rc = cgs(nlock, nact))) return rc;
-  if ((rc = hip(launch_normalize(A, n_, n_, nact, s_), "normalize"))) return rc;
+  if ((rc = hip(launch_normalize(A, n_, n_, nact, s_, w_), "normalize"))) return rc;
   bool ok = true;
   if ((rc = cholqr(nact, true, &ok))) return rc;
   if (ok) {
@@ -332,6 +394,20 @@ int Solver::filter(const double* H, int64_t ldh, int64_t nlock, int64_t nact,
   int rc;
   int64_t mv = 0;
   if (n32 > 0) {
+    float* V32 = at<float>(L_.V32);
+    if (real_) {  // real float32 filter on the float32 copy of H
+      if ((rc = hip(launch_convert_f64_to_f32(col(L_.V, nlock), n_, V32, n_, n_, n32, s_), "cvt")))
+        return rc;
+      if ((rc = hip(run_filter<float>(at<float>(L_.H32), n_, n_, V32, at<float>(L_.W32), n_, n32,
+                                      m.data(), b_sup_, mu_1_, mu_b_, ctx_->prod, s_, &mv, 3),
+                    "filter real fp32")))
+        return rc;
+      st_.filter_matvecs += mv;
+      if ((rc = hip(launch_convert_f32_to_f64(V32, n_, col(L_.V, nlock), n_, n_, n32, s_), "cvt")))
+        return rc;
+    }
+  }
+  if (n32 > 0 && !real_) {
     float* V32 = at<float>(L_.V32);
     if ((rc = hip(launch_convert_c128_to_c64(col(L_.V, nlock), n_, V32, n_, n_, n32, s_), "cvt")))
       return rc;
@@ -352,7 +428,14 @@ int Solver::filter(const double* H, int64_t ldh, int64_t nlock, int64_t nact,
     if ((rc = hip(launch_convert_c64_to_c128(V32, n_, col(L_.V, nlock), n_, n_, n32, s_), "cvt")))
       return rc;
   }
-  if (nact - n32 > 0) {
+  if (nact - n32 > 0 && real_) {
+    if ((rc = hip(run_filter<double>(H, ldh, n_, col(L_.V, nlock + n32), col(L_.W, nlock + n32), n_,
+                                     nact - n32, m.data() + n32, b_sup_, mu_1_, mu_b_, ctx_->prod,
+                                     s_, &mv, 3),
+                  "filter real fp64")))
+      return rc;
+    st_.filter_matvecs += mv;
+  } else if (nact - n32 > 0) {
     if (batcher_) {
       const auto prods = filter_schedule(nact - n32, m.data() + n32, b_sup_, mu_1_, mu_b_);
       mv = 0;
@@ -377,12 +460,14 @@ int Solver::run(const void* Hv, int64_t ldh, void* Vuser, int64_t ldv, double* r
   const double* H = static_cast<const double*>(Hv);
   n_ = cfg_.n;
   nb_ = cfg_.nev + cfg_.nex;
+  real_ = cfg_.real_symmetric != 0;
+  w_ = real_ ? 1 : 2;
   s_ = ctx_->stream;
   const bool mixed = cfg_.precision == CHASE_MIXED;
   const bool need_dos = !cfg_.approx && !cfg_.have_mu;
   const int64_t nv = need_dos ? 1 + cfg_.num_lanczos : 1;
   const int64_t k = std::min<int64_t>(cfg_.lanczos_iter, n_);
-  L_ = make_layout(n_, nb_, nv, k, mixed);
+  L_ = make_layout(n_, nb_, nv, k, mixed, w_);
   int rc = ensure_workspace(ctx_, L_.total);
   if (rc) return rc;
   base_ = static_cast<char*>(ctx_->ws);
@@ -417,12 +502,16 @@ int Solver::run(const void* Hv, int64_t ldh, void* Vuser, int64_t ldv, double* r
 
   (void)hipEventRecord(ev[6], s_);
   // state: V (ld n) <- user block
-  if ((rc = hip(hipMemcpy2DAsync(at<double>(L_.V), n_ * 16, Vuser, ldv * 16, n_ * 16, nb_,
+  if ((rc = hip(hipMemcpy2DAsync(at<double>(L_.V), n_ * es(), Vuser, ldv * es(), n_ * es(), nb_,
                                  hipMemcpyDeviceToDevice, s_),
                 "copy V")))
     return rc;
-  if (mixed && (rc = hip(launch_convert_c128_to_planar32(H, ldh, at<float>(L_.H32), n_, n_, s_),
-                         "convert H")))
+  if (mixed && real_ &&
+      (rc = hip(launch_convert_f64_to_f32(H, ldh, at<float>(L_.H32), n_, n_, n_, s_), "convert H")))
+    return rc;
+  if (mixed && !real_ &&
+      (rc = hip(launch_convert_c128_to_planar32(H, ldh, at<float>(L_.H32), n_, n_, s_),
+                "convert H")))
     return rc;
 
   // ---------------------------------------------------------------- LANCZOS (Alg. 1 line 2)
@@ -481,35 +570,39 @@ int Solver::run(const void* Hv, int64_t ldh, void* Vuser, int64_t ldv, double* r
     double* Q = col(L_.V, nlock);
     double* AQ = at<double>(L_.AQ);
     double* G = at<double>(L_.G);
-    if ((rc = hip(launch_hemm_step<double>(H, ldh, n_, Q, n_, AQ, n_, nact, 1.0, 0.0, 0.0, ctx_->prod, s_),
-                  "H Q")))
-      return rc;
+    if ((rc = hip(product(H, ldh, Q, n_, AQ, n_, nact, 1.0, 0.0, 0.0), "H Q"))) return rc;
     st_.matvecs += nact;
-    if ((rc = zgemm(rocblas_operation_conjugate_transpose, rocblas_operation_none, nact, nact, n_,
+    if ((rc = gemm(rocblas_operation_conjugate_transpose, rocblas_operation_none, nact, nact, n_,
                     1.0, Q, n_, AQ, n_, 0.0, G, nb_)))
       return rc;
-    if ((rc = hip(launch_herm_sym(G, nb_, nact, s_), "sym"))) return rc;
-    if ((rc = blas(rocsolver_zheevd(ctx_->blas, rocblas_evect_original, rocblas_fill_upper,
-                                    static_cast<rocblas_int>(nact),
-                                    reinterpret_cast<rocblas_double_complex*>(G),
-                                    static_cast<rocblas_int>(nb_), at<double>(L_.lam),
-                                    at<double>(L_.evE), at<rocblas_int>(L_.info)),
-                   "zheevd")))
-      return rc;
+    if ((rc = hip(launch_herm_sym(G, nb_, nact, s_, w_), "sym"))) return rc;
+    rc = real_ ? blas(rocsolver_dsyevd(ctx_->blas, rocblas_evect_original, rocblas_fill_upper,
+                                       static_cast<rocblas_int>(nact), G,
+                                       static_cast<rocblas_int>(nb_), at<double>(L_.lam),
+                                       at<double>(L_.evE), at<rocblas_int>(L_.info)),
+                      "dsyevd")
+               : blas(rocsolver_zheevd(ctx_->blas, rocblas_evect_original, rocblas_fill_upper,
+                                       static_cast<rocblas_int>(nact),
+                                       reinterpret_cast<rocblas_double_complex*>(G),
+                                       static_cast<rocblas_int>(nb_), at<double>(L_.lam),
+                                       at<double>(L_.evE), at<rocblas_int>(L_.info)),
+                      "zheevd");
+    if (rc) return rc;
     double* Wb = at<double>(L_.W);
     double* Xb = at<double>(L_.X);
-    if ((rc = zgemm(rocblas_operation_none, rocblas_operation_none, n_, nact, nact, 1.0, Q, n_, G,
+    if ((rc = gemm(rocblas_operation_none, rocblas_operation_none, n_, nact, nact, 1.0, Q, n_, G,
                     nb_, 0.0, Wb, n_)))
       return rc;
-    if ((rc = zgemm(rocblas_operation_none, rocblas_operation_none, n_, nact, nact, 1.0, AQ, n_, G,
+    if ((rc = gemm(rocblas_operation_none, rocblas_operation_none, n_, nact, nact, 1.0, AQ, n_, G,
                     nb_, 0.0, Xb, n_)))
       return rc;
     (void)hipEventRecord(ev[3], s_);
     // residuals (line 8)
-    if ((rc = hip(launch_resid(Xb, Wb, at<double>(L_.lam), n_, n_, nact, at<double>(L_.res), s_),
+    if ((rc = hip(launch_resid(Xb, Wb, at<double>(L_.lam), n_, n_, nact, at<double>(L_.res), s_,
+                               w_),
                   "resid")))
       return rc;
-    if ((rc = hip(hipMemcpyAsync(Q, Wb, static_cast<size_t>(n_) * nact * 16,
+    if ((rc = hip(hipMemcpyAsync(Q, Wb, static_cast<size_t>(n_) * nact * es(),
                                  hipMemcpyDeviceToDevice, s_),
                   "copy")))
       return rc;
@@ -600,8 +693,9 @@ int Solver::run(const void* Hv, int64_t ldh, void* Vuser, int64_t ldv, double* r
     if ((rc = hip(hipMemcpyAsync(at<int>(L_.perm), perm.data(), nact * 4, hipMemcpyHostToDevice, s_),
                   "h2d")))
       return rc;
-    if ((rc = hip(launch_gather(Q, n_, Wb, n_, n_, at<int>(L_.perm), nact, s_), "gather"))) return rc;
-    if ((rc = hip(hipMemcpyAsync(Q, Wb, static_cast<size_t>(n_) * nact * 16,
+    if ((rc = hip(launch_gather(Q, n_, Wb, n_, n_, at<int>(L_.perm), nact, s_, w_), "gather")))
+      return rc;
+    if ((rc = hip(hipMemcpyAsync(Q, Wb, static_cast<size_t>(n_) * nact * es(),
                                  hipMemcpyDeviceToDevice, s_),
                   "copy")))
       return rc;
@@ -643,10 +737,10 @@ int Solver::run(const void* Hv, int64_t ldh, void* Vuser, int64_t ldv, double* r
                 "h2d")))
     return rc;
   if ((rc = hip(launch_gather(at<double>(L_.V), n_, at<double>(L_.W), n_, n_, at<int>(L_.perm), nb_,
-                              s_),
+                              s_, w_),
                 "gather")))
     return rc;
-  if ((rc = hip(hipMemcpy2DAsync(Vuser, ldv * 16, at<double>(L_.W), n_ * 16, n_ * 16, nb_,
+  if ((rc = hip(hipMemcpy2DAsync(Vuser, ldv * es(), at<double>(L_.W), n_ * es(), n_ * es(), nb_,
                                  hipMemcpyDeviceToDevice, s_),
                 "copy out")))
     return rc;
@@ -657,7 +751,8 @@ int Solver::run(const void* Hv, int64_t ldh, void* Vuser, int64_t ldv, double* r
   st_.nconv = static_cast<int32_t>(nlock);
   st_.qr_fallbacks = fallbacks_;
   st_.matvecs += st_.filter_matvecs;
-  st_.filter_flops = 8.0 * static_cast<double>(n_) * static_cast<double>(n_) *
+  // 8 n^2 flops per complex matvec, 2 n^2 per real one
+  st_.filter_flops = (real_ ? 2.0 : 8.0) * static_cast<double>(n_) * static_cast<double>(n_) *
                      static_cast<double>(st_.filter_matvecs);
   st_.b_sup = b_sup_;
   st_.mu_1 = mu_1_;
@@ -688,6 +783,8 @@ int check_config(chase_ctx* ctx, const chase_config* cfg) {
       (!(cfg->switch_resid > 0.0) || cfg->deg_max_fp32 < 2 || cfg->deg_max_fp32 > 64))
     return set_error(ctx, CHASE_EINVAL, "switch_resid > 0 and deg_max_fp32 in [2, 64]");
   if (!(cfg->dos_sigma > 0.0)) return set_error(ctx, CHASE_EINVAL, "dos_sigma must be positive");
+  if (cfg->real_symmetric != 0 && cfg->real_symmetric != 1)
+    return set_error(ctx, CHASE_EINVAL, "real_symmetric must be 0 or 1");
   if (cfg->have_mu && !cfg->approx &&
       !(std::isfinite(cfg->mu_1) && std::isfinite(cfg->mu_nevnex) && cfg->mu_1 < cfg->mu_nevnex))
     return set_error(ctx, CHASE_EINVAL, "need finite mu_1 < mu_nevnex");
@@ -708,8 +805,9 @@ int solve_with(chase_ctx* ctx, const chase_config* cfg, const void* H, int64_t l
       if (!std::isfinite(ritzv[i])) return set_error(ctx, CHASE_EINVAL, "ritzv must be finite");
   const char* ph = static_cast<const char*>(H);
   const char* pv = static_cast<const char*>(V);
-  const size_t hb = (static_cast<size_t>(cfg->n - 1) * ldh + cfg->n) * 16;
-  const size_t vb = (static_cast<size_t>(nb - 1) * ldv + cfg->n) * 16;
+  const size_t es = cfg->real_symmetric ? 8 : 16;
+  const size_t hb = (static_cast<size_t>(cfg->n - 1) * ldh + cfg->n) * es;
+  const size_t vb = (static_cast<size_t>(nb - 1) * ldv + cfg->n) * es;
   if (ph < pv + vb && pv < ph + hb) return set_error(ctx, CHASE_EINVAL, "H and V overlap");
   if ((rc = hip_ok(ctx))) return rc;
   Solver s(ctx, *cfg, batcher);
@@ -742,7 +840,8 @@ size_t chase_workspace_bytes(const chase_config* cfg) {
   const int64_t nb = cfg->nev + cfg->nex;
   const int64_t nv = cfg->approx ? 1 : 1 + std::max<int64_t>(cfg->num_lanczos, 1);
   const int64_t k = std::min<int64_t>(std::max(cfg->lanczos_iter, 1), cfg->n);
-  return make_layout(cfg->n, nb, nv, k, cfg->precision == CHASE_MIXED).total;
+  return make_layout(cfg->n, nb, nv, k, cfg->precision == CHASE_MIXED,
+                     cfg->real_symmetric ? 1 : 2).total;
 }
 
 int chase_solve(chase_ctx* ctx, const chase_config* cfg, const void* H, int64_t ldh, void* V,
@@ -760,13 +859,14 @@ int chase_seq_create(chase_ctx* ctx, const chase_config* cfg, chase_seq** out) {
   s->ctx = ctx;
   s->cfg = *cfg;
   const int64_t nb = cfg->nev + cfg->nex;
-  if (hipMalloc(&s->V, static_cast<size_t>(cfg->n) * nb * 16) != hipSuccess) {
+  const int w = cfg->real_symmetric ? 1 : 2;
+  if (hipMalloc(&s->V, static_cast<size_t>(cfg->n) * nb * 8 * w) != hipSuccess) {
     (void)hipGetLastError();
     delete s;
     return set_error(ctx, CHASE_ENOMEM, "sequence state allocation failed");
   }
   // start block of problem 1: counter-based Gaussian from the seed
-  hipError_t e = launch_gaussian(s->V, cfg->n, cfg->n, nb, cfg->seed ^ 0x5eedULL, ctx->stream);
+  hipError_t e = launch_gaussian(s->V, cfg->n, cfg->n, nb, cfg->seed ^ 0x5eedULL, ctx->stream, w);
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
   if (e != hipSuccess) {
     (void)hipFree(s->V);

@@ -61,6 +61,18 @@ def hermitian_from(Q: np.ndarray, lam: np.ndarray) -> np.ndarray:
     return 0.5 * (H + H.conj().T)
 
 
+def haar_orthogonal(n: int, g: np.random.Generator) -> np.ndarray:
+    """Real Haar-distributed orthogonal matrix: QR of a real Gaussian with the sign fix."""
+    Q, R = np.linalg.qr(g.standard_normal((n, n)))
+    return Q * np.sign(np.diag(R))[None, :]
+
+
+def symmetric_from(Q: np.ndarray, lam: np.ndarray) -> np.ndarray:
+    """Real symmetric Q diag(lam) Q^T, symmetrised."""
+    H = (Q * lam[None, :]) @ Q.T
+    return 0.5 * (H + H.T)
+
+
 def hermitian(n: int, lam: np.ndarray, seed: int) -> np.ndarray:
     """Column-major-ready (Fortran order) complex128 H with spectrum lam."""
     Q = haar_unitary(n, rng(seed))
@@ -193,6 +205,31 @@ def hermitian_torch_fast(n: int, lam: np.ndarray, seed: int, device: str = "cuda
     d = torch.as_tensor(dh, device=device)
     H.mul_(d[:, None])
     H.mul_(d.conj()[None, :])
+    return H
+
+
+def symmetric_torch_fast(n: int, lam: np.ndarray, seed: int, device: str = "cuda",
+                         reflectors: int = 4):
+    """Real symmetric counterpart of ``hermitian_torch_fast``: Q = D P_r ... P_1 with real unit
+    Gaussian reflector vectors and random signs D, built in place (one n x n float64 buffer).
+    Symmetric, so the row-major tensor read column-major is the same matrix."""
+    import torch
+
+    g = rng(seed)
+    U = g.standard_normal((reflectors, n))
+    U /= np.linalg.norm(U, axis=1, keepdims=True)
+    d = np.where(g.standard_normal(n) < 0, -1.0, 1.0)
+    H = torch.diag(torch.as_tensor(lam, device=device, dtype=torch.float64))
+    for j in range(reflectors):
+        u = torch.as_tensor(U[j], device=device)
+        Hu = H @ u
+        w = Hu - torch.dot(u, Hu) * u
+        H.addr_(u, w, alpha=-2.0)
+        H.addr_(w, u, alpha=-2.0)
+        del Hu, w, u
+    dd = torch.as_tensor(d, device=device)
+    H.mul_(dd[:, None])
+    H.mul_(dd[None, :])
     return H
 
 

@@ -45,7 +45,7 @@ int main(void) {
   F(chase_config, approx) F(chase_config, tol) F(chase_config, precision)
   F(chase_config, switch_resid) F(chase_config, dos_sigma) F(chase_config, seed)
   F(chase_config, lanczos_start) F(chase_config, have_mu) F(chase_config, mu_nevnex)
-  F(chase_config, verbose)
+  F(chase_config, verbose) F(chase_config, real_symmetric)
   F(chase_stats, matvecs) F(chase_stats, filter_flops) F(chase_stats, norm_est)
   return 0;
 }
@@ -60,7 +60,7 @@ int main(void) {
     assert int(vals["sizeof_config"]) == ctypes.sizeof(capi.chase_config)
     assert int(vals["sizeof_stats"]) == ctypes.sizeof(capi.chase_stats)
     for f in ["approx", "tol", "precision", "switch_resid", "dos_sigma", "seed", "lanczos_start",
-              "have_mu", "mu_nevnex", "verbose"]:
+              "have_mu", "mu_nevnex", "verbose", "real_symmetric"]:
         assert int(vals[f]) == getattr(capi.chase_config, f).offset, f
     for f in ["matvecs", "filter_flops", "norm_est"]:
         assert int(vals[f]) == getattr(capi.chase_stats, f).offset, f
@@ -86,6 +86,10 @@ def test_workspace_bytes_is_pure_host():
     cfg = capi.config(10000, 500, 100)
     b = capi.lib().chase_workspace_bytes(ctypes.byref(cfg))
     assert b >= 3 * 10000 * 600 * 16
+    # real symmetric data: 8-byte elements, so about half the complex workspace
+    cfg.real_symmetric = 1
+    br = capi.lib().chase_workspace_bytes(ctypes.byref(cfg))
+    assert 3 * 10000 * 600 * 8 <= br < 0.6 * b
 
 
 def test_create_without_gpu_fails_cleanly():

@@ -145,3 +145,20 @@ def test_structured_generator_closed_form():
         W[:, a] *= p_lib(lam, int(deg[a]), 1.1, lam[0], lam[15])
     ref = wl.apply_colmajor_q(U, d, W)
     assert np.linalg.norm(got - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
+def test_filter_on_real_symmetric_matrix():
+    # Real symmetric H (the real instance of the method): the oracle's filter of a real block
+    # is real and equals Q diag(p_m(lam)) Q^T V.
+    n, nb = 90, 6
+    g = wl.rng(12)
+    lam = wl.spectrum_uniform(n, g)
+    Q = wl.haar_orthogonal(n, g)
+    A = wl.symmetric_from(Q, lam)
+    V = g.standard_normal((n, nb))
+    deg = np.array([2, 4, 6, 10, 20, 36])
+    out = ch.filter_columns(A, V, deg, 1.05, lam[0], lam[12])
+    assert np.max(np.abs(out.imag)) == 0.0
+    for a in range(nb):
+        ref = Q @ (p_lib(lam, int(deg[a]), 1.05, lam[0], lam[12]) * (Q.T @ V[:, a]))
+        assert np.linalg.norm(out[:, a].real - ref) <= 1e-12 * np.linalg.norm(ref)

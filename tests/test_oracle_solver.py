@@ -177,3 +177,18 @@ def test_sequence_warm_start_and_weyl():
             assert np.max(np.abs(r["ritzv"][:nev] - prev)) <= 1.01e-3 * np.max(np.abs(lam)) * 1.01
         prev = r["ritzv"][:nev]
     assert res[-1]["iterations"] <= res[0]["iterations"]
+
+
+def test_solve_real_symmetric_prescribed_spectrum():
+    # The real instance: real symmetric A, real start block; the oracle (complex arithmetic on a
+    # real problem) must return the prescribed eigenvalues and real-representable vectors.
+    n, nev, nex = 200, 10, 5
+    g = wl.rng(71)
+    lam = wl.spectrum_uniform(n, g)
+    A = wl.symmetric_from(wl.haar_orthogonal(n, g), lam)
+    p = chase.ChaseParams(nev=nev, nex=nex, optim=True)
+    r = chase.solve(A, p, g.standard_normal((n, nev + nex)), g.standard_normal((n, 5)))
+    _check_solution(A, lam, r, nev)
+    assert np.max(np.abs(r["V"][:, :nev].imag)) <= 1e-12
+    sigma = 0.5 * (r["ritzv"][nev - 1] + r["ritzv"][nev])
+    assert _inertia_count(A, sigma) == nev
