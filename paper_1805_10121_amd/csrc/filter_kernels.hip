@@ -827,12 +827,8 @@ __device__ __forceinline__ void tile_coords(int64_t t, int tiles_n, int* tile_m,
   *tile_n = static_cast<int>(t % tiles_n);
 }
 
-__device__ __forceinline__ int64_t sk_start(int64_t p, int64_t units, int64_t P) {
-  return p * units / P;
-}
-__device__ __forceinline__ int64_t sk_owner(int64_t u, int64_t units, int64_t P) {
-  return ((u + 1) * P - 1) / units;  // max p with sk_start(p) <= u
-}
+// The integer schedule (sk_start, sk_owner, sk_segment, sk_slot, sk_fixup_tile, xcd_order) is
+// shared with the host and checked on the CPU; it lives in host_logic.h.
 
 template <typename T, class C, int OCC, bool V16>
 __global__ __launch_bounds__(kThreads, OCC) void hemm_sk_kernel(
@@ -846,7 +842,7 @@ __global__ __launch_bounds__(kThreads, OCC) void hemm_sk_kernel(
   // Workgroups are dealt round-robin to the 8 XCDs (each with its own L2); q renumbers them so
   // that the workgroups of one XCD hold consecutive tiles, i.e. the column tiles of the same
   // row panels, which then stream the same H stages through that XCD's L2 at the same time.
-  const int64_t q = (P % 8 == 0) ? (p % 8) * (P / 8) + p / 8 : p;
+  const int64_t q = xcd_order(p, P);
   for (int64_t t = q; t < dp_tiles; t += P) {
     int tile_m, tile_n;
     tile_coords(t, tiles_n, &tile_m, &tile_n);
@@ -859,13 +855,12 @@ __global__ __launch_bounds__(kThreads, OCC) void hemm_sk_kernel(
   }
   if (units == 0) return;
   const int64_t u0 = sk_start(p, units, P), u1 = sk_start(p + 1, units, P);
-  const int64_t t_first = u0 / nk;
   constexpr int TE = C::BMC * C::BNC;  // output elements per tile
   int64_t u = u0;
   while (u < u1) {
-    const int64_t tr = u / nk;  // tile index within the stream-K part
-    const int ka = static_cast<int>(u - tr * nk);
-    const int kb = static_cast<int>(min(static_cast<int64_t>(nk), ka + (u1 - u)));
+    const SkSegment sg = sk_segment(u, u1, nk);
+    const int64_t tr = sg.tile;  // tile index within the stream-K part
+    const int ka = sg.ka, kb = sg.kb;
     const int64_t t = dp_tiles + tr;
     int tile_m, tile_n;
     tile_coords(t, tiles_n, &tile_m, &tile_n);
@@ -878,7 +873,7 @@ __global__ __launch_bounds__(kThreads, OCC) void hemm_sk_kernel(
       });
     } else {
       constexpr int EW = elem_width<C>();
-      T* dst = partial + EW * (p * 2 + (tr == t_first ? 0 : 1)) * TE;
+      T* dst = partial + EW * (p * 2 + sk_slot(p, tr, units, P, nk)) * TE;
       tile_foreach<T, C>(f, [&](int r, int c, T hre, T him) {
         dst[EW * (r + c * C::BMC)] = hre;
         if constexpr (EW == 2) dst[EW * (r + c * C::BMC) + 1] = him;
@@ -895,12 +890,8 @@ __global__ __launch_bounds__(kThreads) void hemm_fixup_kernel(
     const T* __restrict__ X, int64_t ldx, T* __restrict__ OUT, int64_t ldo, int n, int ncols,
     T alpha, T beta, T gamma, int tiles_m, int nk, int64_t dp_tiles, int64_t units, int64_t P,
     const T* __restrict__ partial) {
-  const int64_t q = blockIdx.x;
-  if (q == 0 || units == 0) return;
-  const int64_t uq = sk_start(q, units, P);
-  if (uq >= units || uq % nk == 0) return;
-  const int64_t tr = uq / nk;
-  if (sk_start(q - 1, units, P) > tr * nk) return;  // an earlier boundary handles this tile
+  const int64_t tr = sk_fixup_tile(blockIdx.x, units, P, nk);
+  if (tr < 0) return;
   const int64_t pf = sk_owner(tr * nk, units, P), pl = sk_owner((tr + 1) * nk - 1, units, P);
   const int64_t t = dp_tiles + tr;
   int tile_m, tile_n;
@@ -914,7 +905,7 @@ __global__ __launch_bounds__(kThreads) void hemm_fixup_kernel(
       const int64_t a = sk_start(pp, units, P), b = sk_start(pp + 1, units, P);
       if (a >= b) continue;  // empty range
       constexpr int EW = elem_width<C>();
-      const T* src = partial + EW * (pp * 2 + (a / nk == tr ? 0 : 1)) * TE;
+      const T* src = partial + EW * (pp * 2 + sk_slot(pp, tr, units, P, nk)) * TE;
       hre += src[EW * e];
       if constexpr (EW == 2) him += src[EW * e + 1];
     }
@@ -976,9 +967,9 @@ hipError_t launch_sk(const T* H, int64_t ldh, int64_t n, const T* X, int64_t ldx
   const int tiles_n = static_cast<int>((ncols + C::BNC - 1) / C::BNC);
   const int nk = static_cast<int>((n + C::KT - 1) / C::KT);
   const int64_t tiles = static_cast<int64_t>(tiles_m) * tiles_n;
-  int64_t dp_tiles = hybrid ? (tiles / P) * P : 0;
-  int64_t units = (tiles - dp_tiles) * nk;
-  if (dp_tiles == 0 && P > units) P = units;
+  const SkPlan plan = sk_plan(tiles, nk, P, hybrid);
+  const int64_t dp_tiles = plan.dp_tiles, units = plan.units;
+  P = plan.P;
   hipLaunchKernelGGL((hemm_sk_kernel<T, C, OCC, V16>), dim3(static_cast<unsigned>(P)), dim3(kThreads), 0,
                      stream, H, ldh, static_cast<int>(n), X, ldx, OUT, ldo,
                      static_cast<int>(ncols), alpha, beta, gamma, tiles_m, nk, dp_tiles, units,

@@ -12,6 +12,59 @@
 
 namespace chase {
 
+// ---------------------------------------------------------------------------------------------
+// Integer schedule of the product kernel's stream-K part (constexpr, so the kernels use these
+// same functions).  U work units (tile, K stage), numbered tile-major, are split over P
+// persistent workgroups: workgroup p owns [sk_start(p), sk_start(p + 1)).
+constexpr int64_t sk_start(int64_t p, int64_t units, int64_t P) { return p * units / P; }
+// The workgroup whose range contains unit u (the largest p with sk_start(p) <= u).
+constexpr int64_t sk_owner(int64_t u, int64_t units, int64_t P) {
+  return ((u + 1) * P - 1) / units;
+}
+// One segment of a workgroup's range: the units of one tile, K stages [ka, kb).
+struct SkSegment {
+  int64_t tile;
+  int ka, kb;
+};
+constexpr SkSegment sk_segment(int64_t u, int64_t u1, int nk) {
+  const int64_t tr = u / nk;
+  const int ka = static_cast<int>(u - tr * nk);
+  const int64_t rest = static_cast<int64_t>(ka) + (u1 - u);
+  return {tr, ka, static_cast<int>(rest < nk ? rest : nk)};
+}
+// Partial-sum slot of workgroup p's segment in split tile tr: 0 for the tile holding its first
+// unit, 1 for the tile holding its last.
+constexpr int sk_slot(int64_t p, int64_t tr, int64_t units, int64_t P, int nk) {
+  return sk_start(p, units, P) / nk == tr ? 0 : 1;
+}
+// The split tile that fixup workgroup q completes, or -1: q completes the tile containing its
+// first unit when that unit is not the tile's first and no earlier workgroup's range starts
+// inside the same tile.
+constexpr int64_t sk_fixup_tile(int64_t q, int64_t units, int64_t P, int nk) {
+  if (q == 0 || units == 0) return -1;
+  const int64_t uq = sk_start(q, units, P);
+  if (uq >= units || uq % nk == 0) return -1;
+  const int64_t tr = uq / nk;
+  if (sk_start(q - 1, units, P) > tr * nk) return -1;
+  return tr;
+}
+// Hybrid plan for `tiles` output tiles of nk K stages on P persistent workgroups: the first
+// dp_tiles = whole rounds of tiles go data-parallel, the rest is split as stream-K units; with
+// no data-parallel round, P shrinks to the unit count so that no workgroup is idle.
+struct SkPlan {
+  int64_t dp_tiles, units, P;
+};
+constexpr SkPlan sk_plan(int64_t tiles, int nk, int64_t P, bool hybrid) {
+  const int64_t dp = hybrid ? (tiles / P) * P : 0;
+  const int64_t units = (tiles - dp) * nk;
+  return {dp, units, (dp == 0 && P > units) ? units : P};
+}
+// Workgroup p's position in the data-parallel tile order: the workgroups dealt to one of the 8
+// XCDs (round-robin by index) get consecutive positions.
+constexpr int64_t xcd_order(int64_t p, int64_t P) {
+  return (P % 8 == 0) ? (p % 8) * (P / 8) + p / 8 : p;
+}
+
 // One product of Algorithm 4: OUT[:, col0:col0+ncols] <- alpha H X + gamma X + beta OUT where
 // (X, OUT) = (V, W) when from_v, else (W, V).
 struct FilterProduct {

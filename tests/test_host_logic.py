@@ -131,3 +131,87 @@ def test_tridiagonal_eigensolver_and_dos_match_oracle(exe):
     lo, mub = map(float, _run(exe, f"dos {nv} {k} {float(b_sup)!r} 0.25 {50 / n!r} " + flat).split())
     assert lo == pytest.approx(mu1_ref, abs=1e-13)
     assert mub == pytest.approx(mub_ref, abs=1e-9)
+
+
+SCHED_DRIVER = r"""
+#include <cstdio>
+#include <vector>
+#include "host_logic.h"
+using namespace chase;
+// Exhaustive check of the product kernel's stream-K schedule over many shapes: every unit has
+// exactly one owner; each workgroup writes at most one partial per slot; every split tile gets
+// exactly one fixup workgroup, whose contributor range [pf, pl] and slot choice match what the
+// contributors wrote; tiles finished in place get no fixup; the XCD order is a permutation.
+int main() {
+  long checked = 0;
+  const int nks[] = {1, 2, 3, 7, 16, 63, 625, 1250};
+  const long Ps[] = {1, 2, 3, 8, 64, 256, 512, 768, 1024};
+  for (long tiles = 1; tiles <= 3000; tiles = tiles < 40 ? tiles + 1 : tiles * 3 / 2 + 1)
+    for (int nk : nks)
+      for (long P0 : Ps)
+        for (int hybrid = 0; hybrid < 2; ++hybrid) {
+          const SkPlan pl = sk_plan(tiles, nk, P0, hybrid);
+          if (pl.P < 1 || pl.dp_tiles % P0 != 0 || pl.dp_tiles > tiles) return 1;
+          if (pl.units != (tiles - pl.dp_tiles) * nk) return 2;
+          if (pl.units == 0) continue;
+          const long U = pl.units, P = pl.P, T = tiles - pl.dp_tiles;
+          std::vector<int> owner(U, -1);
+          std::vector<int> contributors(T, 0), written(2 * P, -1);
+          for (long p = 0; p < P; ++p) {
+            const long u0 = sk_start(p, U, P), u1 = sk_start(p + 1, U, P);
+            for (long u = u0; u < u1; ++u) {
+              if (owner[u] != -1 || sk_owner(u, U, P) != p) return 3;
+              owner[u] = p;
+            }
+            long u = u0;
+            while (u < u1) {
+              const SkSegment sg = sk_segment(u, u1, nk);
+              if (sg.ka < 0 || sg.kb <= sg.ka || sg.kb > nk) return 4;
+              ++contributors[sg.tile];
+              if (!(sg.ka == 0 && sg.kb == nk)) {  // partial: one slot per segment
+                const int slot = sk_slot(p, sg.tile, U, P, nk);
+                if (written[2 * p + slot] != -1) return 5;
+                written[2 * p + slot] = static_cast<int>(sg.tile);
+              }
+              u = sg.tile * nk + sg.kb;
+            }
+          }
+          for (long u = 0; u < U; ++u)
+            if (owner[u] == -1) return 6;
+          std::vector<int> fixups(T, 0);
+          for (long q = 0; q < P; ++q) {
+            const long tr = sk_fixup_tile(q, U, P, nk);
+            if (tr < 0) continue;
+            ++fixups[tr];
+            const long pf = sk_owner(tr * nk, U, P), pl2 = sk_owner((tr + 1) * nk - 1, U, P);
+            for (long pp = pf; pp <= pl2; ++pp) {
+              const long a = sk_start(pp, U, P), b = sk_start(pp + 1, U, P);
+              if (a >= b) continue;
+              if (written[2 * pp + sk_slot(pp, tr, U, P, nk)] != tr) return 7;
+            }
+          }
+          for (long t = 0; t < T; ++t)
+            if ((contributors[t] > 1) != (fixups[t] == 1) || fixups[t] > 1) return 8;
+          std::vector<char> seen(P0, 0);
+          for (long p = 0; p < P0; ++p) {
+            const long q = xcd_order(p, P0);
+            if (q < 0 || q >= P0 || seen[q]) return 9;
+            seen[q] = 1;
+          }
+          ++checked;
+        }
+  printf("%ld\n", checked);
+  return 0;
+}
+"""
+
+
+def test_stream_k_schedule_exhaustive():
+    d = tempfile.mkdtemp()
+    src = os.path.join(d, "sched.cpp")
+    out = os.path.join(d, "sched")
+    open(src, "w").write(SCHED_DRIVER)
+    subprocess.run(["g++", "-std=c++17", "-O2", "-I", CSRC, src, "-o", out], check=True)
+    r = subprocess.run([out], capture_output=True, text=True)
+    assert r.returncode == 0, f"schedule check {r.returncode}"
+    assert int(r.stdout) > 1000
