@@ -121,7 +121,7 @@ void chase_config_init(chase_config* cfg, int64_t n, int64_t nev, int64_t nex);
 /* Create a context on HIP device `device`.  hip_stream: a hipStream_t to order all work on, or
    NULL for a stream owned by the context.  Allocates a fixed partial-sum scratch for the
    stream-K schedule of the product kernel (two tile-sized slots per persistent workgroup:
-   64 MiB on a 256-CU device) and a rocBLAS handle; the solver workspace comes later. */
+   128 MiB on a 256-CU device) and a rocBLAS handle; the solver workspace comes later. */
 int chase_create(chase_ctx** out, int device, void* hip_stream);
 void chase_destroy(chase_ctx* ctx);
 
