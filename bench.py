@@ -338,8 +338,10 @@ def run_ablation(cfg_id=1, degrees=(8, 12, 16, 20, 24, 28, 32, 36)):
     lam = wl.spectrum_for(cfg_id)
     if n <= 2000:
         dH = capi.to_device(wl.hermitian(n, lam, 1000 * cfg_id + 1))
-    else:
+    elif n <= 10000:
         dH = wl.hermitian_torch(n, lam, seed=1000 * cfg_id + 1)
+    else:
+        dH = wl.hermitian_torch_fast(n, lam, seed=1000 * cfg_id + 1)
     V0 = wl.start_block(n, nev + nex, 1000 * cfg_id + 500)
     ctx = capi.Context(0)
     rows = []
@@ -383,6 +385,8 @@ def main():
                     help="sequence: problems (default: the config's); serving: per sequence (8)")
     ap.add_argument("--config", type=int, choices=[3, 5], default=3,
                     help="sequence workload: order-20000 (3) or order-60000 (5) sequence")
+    ap.add_argument("--ablation-configs", type=int, nargs="*", default=[1, 2], choices=[1, 2, 3],
+                    help="ablation workload: which configs to run")
     ap.add_argument("--modes", nargs="*", default=["fp64", "mixed"], choices=["fp64", "mixed"],
                     help="sequence workload: which filters to run")
     ap.add_argument("--switch-resid", type=float, nargs="*", default=[1e-6],
@@ -421,7 +425,7 @@ def main():
         print(json.dumps(run_sequence(args)), flush=True)
         return
     if args.workload == "ablation":
-        out = {"config1": run_ablation(1), "config2": run_ablation(2)}
+        out = {f"config{c}": run_ablation(c) for c in args.ablation_configs}
         print(json.dumps(out), flush=True)
         return
     if args.workload == "serving":
