@@ -506,6 +506,27 @@ def main():
         },
     }
 
+    # thin blocks (the Lanczos block, a filter's last columns) are HBM-bound: H read per product
+    thin = []
+    for nc in (5, 16):
+        dX = dV[:nc]
+        dO = dW[:nc]
+        ctx.chase_hemm_step(capi.CHASE_FP64, dH, n, n, dX, n, dO, n, nc, 1.0, 0.0, 0.0)
+        torch.cuda.synchronize()
+        reps = 20
+        ev0.record(stream)
+        for _ in range(reps):
+            ctx.chase_hemm_step(capi.CHASE_FP64, dH, n, n, dX, n, dO, n, nc, 1.0, 0.0, 0.0)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / reps
+        hbytes = 16.0 * n * n + 32.0 * n * nc   # H once, X read, OUT written
+        thin.append({"ncols": nc, "ms_per_product": round(ms, 4),
+                     "algorithmic_GBps": round(hbytes / (ms * 1e-3) / 1e9, 1),
+                     "frac_of_hbm_peak": round(hbytes / (ms * 1e-3) / 8e12, 4)})
+    out["thin_products"] = thin
+    log(f"bench: thin products {thin}")
+
     if not args.no_fp32:
         h32 = torch.empty((n, n), dtype=torch.complex64, device="cuda")
         v32 = torch.empty((nb, n), dtype=torch.complex64, device="cuda")
@@ -544,6 +565,10 @@ def main():
             "iterations": st.iterations, "matvecs": st.matvecs,
             "filter_tflops": round(st.filter_flops / (st.filter_ms * 1e-3) / 1e12, 3),
             "filter_share": round(st.filter_ms / st.total_ms, 3),
+            "phase_ms": {"lanczos": round(st.lanczos_ms, 1), "filter": round(st.filter_ms, 1),
+                         "orthogonalize": round(st.ortho_ms, 1),
+                         "rayleigh_ritz": round(st.rr_ms, 1), "residuals": round(st.resid_ms, 1),
+                         "total": round(st.total_ms, 1)},
             "max_eig_error_over_normH": float(np.max(np.abs(ritzv[:cfg["nev"]] - lam[:cfg["nev"]])) / normH),
             "max_resid_over_normH": float(np.max(resid[:cfg["nev"]]) / normH),
         }

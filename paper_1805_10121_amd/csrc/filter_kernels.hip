@@ -1008,6 +1008,10 @@ namespace {
 template <typename T>
 using WideTile = Tile<T, 64, 64, 16, 2, 2, sizeof(T) == 4 ? 8 : 2, 0, false, -1, sizeof(T) == 4 ? 0 : 1>;
 template <typename T> using NarrowTile = Tile<T, 64, 32, 16, 4, 1, sizeof(T) == 4 ? 8 : 2>;
+// FP64 thin tile for <= 16 columns (the Lanczos block, a filter's last columns): 128 complex
+// rows x 16 columns, so a thin product pads half as many columns as the narrow tile and its
+// MFMA work drops below the time to stream H.
+using ThinTile64 = Tile<double, 128, 16, 16, 4, 1, 2>;
 // FP64 slim tile: 32 columns, K stages of 8, four workgroups per CU (125 VGPRs, 25 KB LDS); the
 // next stage's global loads and LDS stores are both interleaved with MFMAs.  Padding the
 // columns to 32 instead of 64 wastes less work on ragged widths, but it moves more operand data
@@ -1074,6 +1078,7 @@ size_t product_scratch_bytes(int cus) {
   b = std::max(b, sk_scratch_bytes<float, WideTile<float>>(slots));
   b = std::max(b, sk_scratch_bytes<double, NarrowTile<double>>(slots));
   b = std::max(b, sk_scratch_bytes<double, SlimTile64>(static_cast<int64_t>(cus) * kOccSlim));
+  b = std::max(b, sk_scratch_bytes<double, ThinTile64>(slots));
   b = std::max(b, sk_scratch_bytes<double, RealTile<double>>(slots));
   b = std::max(b, sk_scratch_bytes<double, RealThinTile<double>>(slots));
   return b;
@@ -1106,6 +1111,9 @@ hipError_t launch_hemm_step(const T* H, int64_t ldh, int64_t n, const T* X, int6
   if constexpr (sizeof(T) == 8) {
     // Columns padded to whole tiles: 32-wide slim tiles when that saves more than their lower
     // per-flop rate costs.
+    if (ncols <= 16)
+      return launch_sched<T, ThinTile64>(H, ldh, n, X, ldx, OUT, ldo, ncols, alpha, beta, gamma,
+                                         ps, stream);
     if (ncols <= 32)
       return launch_sched<T, NarrowTile<T>>(H, ldh, n, X, ldx, OUT, ldo, ncols, alpha, beta,
                                             gamma, ps, stream);

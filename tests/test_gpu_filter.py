@@ -46,6 +46,8 @@ def _relerr(a, b):
     (333, 17, -1.3, 0.5, 0.1),     # ragged rows, K tail and a partial column tile
     (129, 130, 2.0, 1.0, -0.5),
     (1000, 1, 1.0, -1.0, 0.0),
+    (200, 5, 0.9, 0.4, -0.2),       # thin tile (<= 16 columns): Lanczos block width
+    (515, 16, -0.6, 1.0, 0.3),      # thin tile, full width, ragged rows and K tail
 ])
 def test_hemm_step_fp64(ctx, n, nb, alpha, beta, gamma):
     import torch
@@ -93,7 +95,7 @@ DEGREE_PATTERNS = {
 
 
 @pytest.mark.parametrize("pattern", list(DEGREE_PATTERNS))
-@pytest.mark.parametrize("n,nb", [(1000, 70), (333, 65), (130, 1)])
+@pytest.mark.parametrize("n,nb", [(1000, 70), (333, 65), (130, 1), (333, 12)])
 def test_filter_fp64_parity(ctx, pattern, n, nb):
     import torch
     from paper_1805_10121_amd import capi
