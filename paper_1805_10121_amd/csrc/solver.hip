@@ -159,17 +159,11 @@ class Solver {
   }
   int lanczos(const double* H, int64_t ldh, double* V);
   int cgs(int64_t nlock, int64_t nact);
-  int cholqr(int64_t nact, bool shift, bool* ok);
+  int cholqr(int64_t nact, bool shift, int slot);
   int householder(int64_t nlock, int64_t nact);
   int orthogonalize(int64_t nlock, int64_t nact);
   int filter(const double* H, int64_t ldh, int64_t nlock, int64_t nact,
              const std::vector<int>& m, const std::vector<int>& prec);
-  int read_info(int* out) {
-    int rc = hip(hipMemcpyAsync(out, at<int>(L_.info), sizeof(int), hipMemcpyDeviceToHost, s_),
-                 "info");
-    if (rc) return rc;
-    return hip(hipStreamSynchronize(s_), "sync");
-  }
 
   double b_sup_ = 0, mu_1_ = 0, mu_b_ = 0, norm_est_ = 0;
 };
@@ -269,63 +263,45 @@ int Solver::cgs(int64_t nlock, int64_t nact) {
 // One (optionally shifted) Cholesky QR pass on the active block: G = A^H A (+ s I) = R^H R,
 // A <- A R^-1.  Shift as in shifted CholeskyQR3 (Fukaya et al.) with ||A||_2^2 <= nact for
 // unit columns.
-int Solver::cholqr(int64_t nact, bool shift, bool* ok) {
+int Solver::cholqr(int64_t nact, bool shift, int slot) {
   double* A = col(L_.V, n_ == 0 ? 0 : (nb_ - nact));
   double* G = at<double>(L_.G);
-  const double one = 1.0, zero = 0.0;
-  int rc = real_
-               ? blas(rocblas_dsyrk(ctx_->blas, rocblas_fill_upper, rocblas_operation_transpose,
-                                    static_cast<rocblas_int>(nact), static_cast<rocblas_int>(n_),
-                                    &one, A, static_cast<rocblas_int>(n_), &zero, G,
-                                    static_cast<rocblas_int>(nb_)),
-                      "dsyrk")
-               : blas(rocblas_zherk(ctx_->blas, rocblas_fill_upper,
-                                    rocblas_operation_conjugate_transpose,
-                                    static_cast<rocblas_int>(nact), static_cast<rocblas_int>(n_),
-                                    &one, reinterpret_cast<const rocblas_double_complex*>(A),
-                                    static_cast<rocblas_int>(n_), &zero,
-                                    reinterpret_cast<rocblas_double_complex*>(G),
-                                    static_cast<rocblas_int>(nb_)),
-                      "zherk");
+  // Gram matrix by GEMM (both triangles; rocBLAS's GEMM is faster than its HERK at these shapes)
+  int rc = gemm(rocblas_operation_conjugate_transpose, rocblas_operation_none, nact, nact, n_, 1.0,
+                A, n_, A, n_, 0.0, G, nb_);
   if (rc) return rc;
   if (shift) {
     const double s = 11.0 * (static_cast<double>(n_) * nact + static_cast<double>(nact) * (nact + 1)) *
                      kEps * static_cast<double>(nact);
     if ((rc = hip(launch_add_diag(G, nb_, nact, s, s_, w_), "add_diag"))) return rc;
   }
+  rocblas_int* info = at<rocblas_int>(L_.info) + slot;
   rc = real_ ? blas(rocsolver_dpotrf(ctx_->blas, rocblas_fill_upper, static_cast<rocblas_int>(nact),
-                                     G, static_cast<rocblas_int>(nb_), at<rocblas_int>(L_.info)),
+                                     G, static_cast<rocblas_int>(nb_), info),
                     "dpotrf")
              : blas(rocsolver_zpotrf(ctx_->blas, rocblas_fill_upper, static_cast<rocblas_int>(nact),
                                      reinterpret_cast<rocblas_double_complex*>(G),
-                                     static_cast<rocblas_int>(nb_), at<rocblas_int>(L_.info)),
+                                     static_cast<rocblas_int>(nb_), info),
                     "zpotrf");
   if (rc) return rc;
-  int info = 0;
-  if ((rc = read_info(&info))) return rc;
-  if (info != 0) {
-    *ok = false;
-    return CHASE_OK;
-  }
-  if (real_) {
-    rc = blas(rocblas_dtrsm(ctx_->blas, rocblas_side_right, rocblas_fill_upper,
-                            rocblas_operation_none, rocblas_diagonal_non_unit,
-                            static_cast<rocblas_int>(n_), static_cast<rocblas_int>(nact), &one, G,
-                            static_cast<rocblas_int>(nb_), A, static_cast<rocblas_int>(n_)),
-              "dtrsm");
-    *ok = true;
-    return rc;
-  }
+  // The factorisation status is read once per orthonormalisation (see orthogonalize); a failed
+  // factorisation makes this solve produce garbage that is then discarded.
+  const double one = 1.0;
+  if (real_)
+    return blas(rocblas_dtrsm(ctx_->blas, rocblas_side_right, rocblas_fill_upper,
+                              rocblas_operation_none, rocblas_diagonal_non_unit,
+                              static_cast<rocblas_int>(n_), static_cast<rocblas_int>(nact), &one, G,
+                              static_cast<rocblas_int>(nb_), A, static_cast<rocblas_int>(n_)),
+                "dtrsm");
   const rocblas_double_complex al(1.0, 0.0);
-  rc = blas(rocblas_ztrsm(ctx_->blas, rocblas_side_right, rocblas_fill_upper, rocblas_operation_none,
-                          rocblas_diagonal_non_unit, static_cast<rocblas_int>(n_),
-                          static_cast<rocblas_int>(nact), &al,
-                          reinterpret_cast<const rocblas_double_complex*>(G),
-                          static_cast<rocblas_int>(nb_), reinterpret_cast<rocblas_double_complex*>(A),
-                          static_cast<rocblas_int>(n_)),
-            "ztrsm");
-  *ok = true;
-  return rc;
+  return blas(rocblas_ztrsm(ctx_->blas, rocblas_side_right, rocblas_fill_upper,
+                            rocblas_operation_none, rocblas_diagonal_non_unit,
+                            static_cast<rocblas_int>(n_), static_cast<rocblas_int>(nact), &al,
+                            reinterpret_cast<const rocblas_double_complex*>(G),
+                            static_cast<rocblas_int>(nb_),
+                            reinterpret_cast<rocblas_double_complex*>(A),
+                            static_cast<rocblas_int>(n_)),
+              "ztrsm");
 }
 
 // Householder QR of [Y V] (the paper's ORTHOGONALIZE), keeping the columns after Y.
@@ -371,20 +347,32 @@ int Solver::householder(int64_t nlock, int64_t nact) {
              "copy");
 }
 
+// The three Cholesky factorisations report their status into three slots that are read with
+// one synchronisation at the end; if any failed, the filtered block is restored from its copy in
+// W and orthonormalised by Householder QR instead.
 int Solver::orthogonalize(int64_t nlock, int64_t nact) {
   int rc;
   double* A = col(L_.V, nlock);
+  double* B = col(L_.W, nlock);  // W is free between the filter and Rayleigh-Ritz
+  if ((rc = hip(hipMemcpyAsync(B, A, static_cast<size_t>(n_) * nact * es(),
+                               hipMemcpyDeviceToDevice, s_), "copy")))
+    return rc;
   if ((rc = cgs(nlock, nact))) return rc;
   if ((rc = hip(launch_normalize(A, n_, n_, nact, s_, w_), "normalize"))) return rc;
-  bool ok = true;
-  if ((rc = cholqr(nact, true, &ok))) return rc;
-  if (ok) {
-    if ((rc = cgs(nlock, nact))) return rc;
-    if ((rc = cholqr(nact, false, &ok))) return rc;
-  }
-  if (ok && (rc = cholqr(nact, false, &ok))) return rc;
-  if (!ok) return householder(nlock, nact);
-  return CHASE_OK;
+  if ((rc = cholqr(nact, true, 0))) return rc;
+  if ((rc = cgs(nlock, nact))) return rc;
+  if ((rc = cholqr(nact, false, 1))) return rc;
+  if ((rc = cholqr(nact, false, 2))) return rc;
+  int info[3] = {0, 0, 0};
+  if ((rc = hip(hipMemcpyAsync(info, at<int>(L_.info), sizeof(info), hipMemcpyDeviceToHost, s_),
+                "info")))
+    return rc;
+  if ((rc = hip(hipStreamSynchronize(s_), "sync"))) return rc;
+  if (info[0] == 0 && info[1] == 0 && info[2] == 0) return CHASE_OK;
+  if ((rc = hip(hipMemcpyAsync(A, B, static_cast<size_t>(n_) * nact * es(),
+                               hipMemcpyDeviceToDevice, s_), "copy")))
+    return rc;
+  return householder(nlock, nact);
 }
 
 int Solver::filter(const double* H, int64_t ldh, int64_t nlock, int64_t nact,

@@ -162,6 +162,19 @@ def test_real_solve_prescribed_spectrum_and_oracle(ctx, precision):
     assert np.max(np.abs(ritzv[:nev] - r["ritzv"][:nev])) <= 1e-10 * np.max(np.abs(lam))
 
 
+def test_real_householder_fallback(ctx):
+    n, nev, nex = 200, 10, 5
+    g = wl.rng(67)
+    lam = wl.spectrum_uniform(n, g)
+    H = wl.symmetric_from(wl.haar_orthogonal(n, g), lam)
+    V0 = g.standard_normal((n, nev + nex))
+    V0[:, -1] = 0.0
+    rc, st, ritzv, resid, Y = _real_solve(ctx, H, np.asfortranarray(V0), g.standard_normal((n, 5)),
+                                          nev=nev, optim=1, intersperse=0)
+    assert rc == 0 and st.qr_fallbacks >= 1
+    _check(H, lam, ritzv, Y, nev)
+
+
 def test_real_warm_start_exact_vectors_one_iteration(ctx):
     n, nev, nex = 150, 8, 4
     g = wl.rng(91)

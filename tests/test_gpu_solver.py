@@ -151,6 +151,22 @@ def test_verbose_iteration_lines(ctx, capfd):
     assert np.array_equal(r0, r1)
 
 
+def test_householder_fallback(ctx):
+    # A zero start column stays zero through the filter; the unshifted Cholesky QR pass then
+    # meets a singular Gram matrix, so the orthonormalisation falls back to Householder QR of
+    # [Y V] (from the saved filtered block) and the solve still converges.
+    n, nev, nex = 200, 10, 5
+    g = wl.rng(66)
+    lam = wl.spectrum_uniform(n, g)
+    H = wl.hermitian_from(wl.haar_unitary(n, g), lam)
+    V0 = wl.complex_gaussian(g, n, nev + nex)
+    V0[:, -1] = 0.0
+    rc, st, ritzv, resid, Y = _gpu_solve(ctx, H, V0, wl.complex_gaussian(g, n, 5), nev=nev,
+                                         optim=1, intersperse=0)
+    assert rc == 0 and st.qr_fallbacks >= 1
+    _check(H, lam, ritzv, Y, nev)
+
+
 def test_max_iter_partial(ctx):
     from paper_1805_10121_amd import capi
 
