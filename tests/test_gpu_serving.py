@@ -101,3 +101,59 @@ def test_budget_and_sequence_rules():
     assert rc == 0 and np.max(np.abs(ritzv[:nev] - lam[:nev])) <= 1e-10
     srv.close()
     torch.cuda.synchronize()
+
+
+def test_real_sequence_in_server_matches_direct():
+    # A real symmetric sequence served beside complex ones gives the same Ritz values, bitwise,
+    # as the same sequence solved directly with chase_seq_* (real products run on the worker's
+    # stream, outside the cross-solve batcher).
+    import torch
+    from paper_1805_10121_amd import capi
+
+    n, nev, nex = 400, 16, 6
+    g = wl.rng(21)
+    lam = wl.spectrum_uniform(n, g)
+    H0 = wl.symmetric_from(wl.haar_orthogonal(n, g), lam)
+    Hs = [H0]
+    for _ in range(2):
+        E = g.standard_normal((n, n))
+        E = 0.5 * (E + E.T)
+        Hs.append(Hs[-1] + 1e-3 * E / np.max(np.abs(np.linalg.eigvalsh(E))))
+    cfg = capi.config(n, nev, nex, optim=1, seed=31, real_symmetric=1)
+    dev = [capi.to_device(H) for H in Hs]
+    torch.cuda.synchronize()
+    ctx = capi.Context(0)
+    seq = capi.Sequence(ctx, cfg)
+    direct = []
+    for dH in dev:
+        r, s = np.zeros(nev + nex), np.zeros(nev + nex)
+        seq.chase_seq_solve(dH, n, r, s)
+        direct.append(r.copy())
+    seq.close()
+    ctx.close()
+    seqs = _sequences()
+    cplx = {sid: [capi.to_device(H) for H in seqs[sid][3]] for sid in (11, 13)}
+    torch.cuda.synchronize()
+    srv = capi.Server(0, mem_budget_bytes=8 << 30, workers=4)
+    tickets = []
+    for k in range(3):
+        tickets.append(("real", k, srv.chase_server_submit(99, cfg, dev[k], n)))
+        for sid in (11, 13):
+            cn, cnev, cnex, _ = seqs[sid]
+            ccfg = capi.config(cn, cnev, cnex, optim=1, seed=77 + sid)
+            tickets.append((sid, k, srv.chase_server_submit(sid, ccfg, cplx[sid][k], cn)))
+    served = {}
+    for sid, k, t in tickets:
+        rc, ritzv, resid, st, lat = srv.chase_server_poll(t, wait=True)
+        assert rc == 0
+        if sid == "real":
+            served[k] = ritzv.copy()
+            ev = np.linalg.eigvalsh(Hs[k])
+            assert np.max(np.abs(ritzv[:nev] - ev[:nev])) <= 1e-10 * np.max(np.abs(ev))
+    ptr, ld = srv.chase_server_vectors(99)
+    Y = capi.device_block_to_host(ptr, ld, n, nev + nex, dtype=np.float64)
+    srv.close()
+    for k in range(3):
+        assert np.array_equal(served[k], direct[k])
+    Yn = Y[:, :nev]
+    assert np.linalg.norm(Yn.T @ Yn - np.eye(nev)) <= 1e-12 * nev ** 0.5
