@@ -42,7 +42,9 @@ typedef enum {
 
 typedef enum {
   CHASE_FP64 = 0,   /* complex128 buffers, FP64 MFMA with FP64 accumulation                     */
-  CHASE_FP32 = 1,   /* complex64 buffers, FP32 MFMA with FP32 accumulation                      */
+  CHASE_FP32 = 1,   /* complex64 buffers, FP32 MFMA with FP32 accumulation.  chase_solve: the
+                       whole solve in single precision (the paper's C / S instances, Sec. 5.1):
+                       complex64 H and V, or float32 with real_symmetric = 1                   */
   CHASE_MIXED = 2,  /* chase_solve only: FP32 filter while a vector's relative residual exceeds
                        switch_resid, FP64 afterwards; everything outside the filter stays FP64 */
   CHASE_FP32_3M = 3, /* chase_filter / chase_hemm_step: H is "planar complex64" -- two real
@@ -75,7 +77,7 @@ typedef struct chase_config {
   int32_t lanczos_iter;  /* k of Alg. 6                                               25          */
   int32_t num_lanczos;   /* n_vec of Alg. 6                                           4           */
 
-  int32_t precision;     /* chase_precision, FP64 or MIXED                            FP64        */
+  int32_t precision;     /* chase_precision: FP64, FP32 (single-precision solve) or MIXED  FP64  */
   double switch_resid;   /* MIXED: relative residual below which a vector is filtered in FP64
                                                                                       1e-6        */
   int32_t deg_max_fp32;  /* MIXED: DEGMAX for FP32-filtered vectors (Table 1 SP value) 18         */
@@ -86,16 +88,16 @@ typedef struct chase_config {
                             leading columns of the start block (Alg. 6 line 13)      1           */
   double dos_sigma;      /* Gaussian width of the DoS (Sec. 4.2), on the [-1, 1] scale 0.25      */
   uint64_t seed;         /* seed of the counter-based generator for Lanczos start vectors   0    */
-  const void* lanczos_start; /* optional device complex128 n x (1 + num_lanczos) block (ld = n)
-                            of Lanczos start vectors; NULL: drawn from seed                NULL  */
+  const void* lanczos_start; /* optional device n x (1 + num_lanczos) block (ld = n) of Lanczos
+                            start vectors in the element type of V; NULL: drawn from seed  NULL */
   int32_t have_mu;       /* cold start only: 1 = use mu_1 / mu_nevnex below instead of the DoS
                             estimates (Alg. 1 input "estimates mu_1 and mu_{nev+nex}")    0     */
   double mu_1, mu_nevnex;
   int32_t verbose;       /* 1: one line per outer iteration on stderr (locked pairs, largest
                             active residual, FP32 columns, elapsed time)                  0     */
-  int32_t real_symmetric;/* 1: H is real symmetric float64 and V is real float64 (the paper's
-                            real instance); leading dimensions count real elements.  0: complex
-                            Hermitian complex128                                          0     */
+  int32_t real_symmetric;/* 1: H is real symmetric and V real, float64 (float32 under CHASE_FP32)
+                            (the paper's real instances); leading dimensions count real elements.
+                            0: complex Hermitian complex128 (complex64 under CHASE_FP32)    0    */
 } chase_config;
 
 /* Counters and timings of one solve (Sec. 6 reports iterations, matvecs and filter time). */
@@ -117,6 +119,11 @@ typedef struct chase_ctx chase_ctx;
 
 /* Fill cfg with the Table 1 defaults for the given sizes.  No device work. */
 void chase_config_init(chase_config* cfg, int64_t n, int64_t nev, int64_t nex);
+
+/* The same with Table 1's single-precision defaults (tol 1e-5, deg_max 18, deg 10, k = 12) and
+   precision = CHASE_FP32, for a solve on complex64 (or, with real_symmetric = 1, float32) data.
+   No device work; a NULL cfg is ignored. */
+void chase_config_init_fp32(chase_config* cfg, int64_t n, int64_t nev, int64_t nex);
 
 /* Create a context on HIP device `device`.  hip_stream: a hipStream_t to order all work on, or
    NULL for a stream owned by the context.  Allocates a fixed partial-sum scratch for the
@@ -184,8 +191,12 @@ int chase_convert_c64_to_c128(chase_ctx* ctx, const void* src, int64_t ld_src, v
 /*
  * Algorithm 1: the nev smallest eigenpairs of H.
  *
- *   H      device complex128, n x n, ldh >= n, full Hermitian storage, read only.
- *   V      device complex128, n x (nev+nex), ldv >= n.
+ * Element type of H and V ("the solve's element type"): complex128 (precision FP64 or MIXED),
+ * complex64 (FP32); with real_symmetric = 1 float64 or float32 instead.  Leading dimensions count
+ * elements.  Ritz values, residuals and stats are double in every case.
+ *
+ *   H      device, n x n, ldh >= n, full Hermitian (symmetric) storage, read only.
+ *   V      device, n x (nev+nex), ldv >= n.
  *          In, approx = 0: the random start block (Alg. 1 input V-hat).
  *          In, approx = 1: approximate eigenvectors, e.g. the previous solution in a sequence.
  *          Out: columns [0, nev) eigenvectors of ritzv[0..nev) (ascending), then the remaining
@@ -208,7 +219,8 @@ int chase_solve(chase_ctx* ctx, const chase_config* cfg, const void* H, int64_t 
  */
 typedef struct chase_seq chase_seq;
 int chase_seq_create(chase_ctx* ctx, const chase_config* cfg, chase_seq** out);
-/* Solve the next problem H (device complex128, ldh >= n).  ritzv / resid: host, nev+nex. */
+/* Solve the next problem H (device, the solve's element type, ldh >= n).  ritzv / resid: host,
+   nev+nex. */
 int chase_seq_solve(chase_seq* seq, const void* H, int64_t ldh, double* ritzv, double* resid,
                     chase_stats* stats);
 /* Borrowed device pointer to the current n x (nev+nex) vectors (valid until the next call). */
@@ -222,15 +234,17 @@ void chase_seq_destroy(chase_seq* seq);
  * Each request is one problem of a sequence identified by seq_id.  Problems of one sequence run
  * in submission order; the first is solved cold (cfg->approx as given), every later one is warm
  * started from the previous solution, which stays in device memory (the sequence state:
- * n x (nev+nex) complex128 vectors and the Ritz values).  A request is started when its sequence
- * is idle and the device memory it needs -- the sequence state if new, plus the growth of a
- * worker's workspace (chase_workspace_bytes) -- fits in mem_budget_bytes beside what is already
- * held.  Up to `workers` requests run at once, each on its own stream; the products of all
- * filter calls in flight are grouped into shared launches.  A request's results are bitwise the
- * same whatever else runs beside it.
+ * n x (nev+nex) vectors of the solve's element type and the Ritz values).  A request is started
+ * when its sequence is idle and the device memory it needs -- the sequence state if new, plus
+ * the growth of a worker's workspace (chase_workspace_bytes) -- fits in mem_budget_bytes beside
+ * what is already held.  Up to `workers` requests run at once, each on its own stream; the
+ * filter products of all complex FP64 and MIXED requests in flight are grouped into shared
+ * launches (real and FP32 requests run theirs on their worker's stream).  A request's results
+ * are bitwise the same whatever else runs beside it.
  *
- * H: device complex128, n x n, ldh >= n, owned by the caller and kept valid and unchanged until
- * the request's ticket reports done.  n, nev and nex must stay the same within a sequence.
+ * H: device, the solve's element type, n x n, ldh >= n, owned by the caller and kept valid and
+ * unchanged until the request's ticket reports done.  n, nev and nex must stay the same within a
+ * sequence.
  * Sequence states are held until chase_server_end_sequence or chase_server_destroy.
  */
 typedef struct chase_server chase_server;

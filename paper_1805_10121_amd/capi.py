@@ -61,6 +61,7 @@ class chase_stats(ctypes.Structure):
 
 _PROTOTYPES = {
     "chase_config_init": (None, [ctypes.POINTER(chase_config), _i64, _i64, _i64]),
+    "chase_config_init_fp32": (None, [ctypes.POINTER(chase_config), _i64, _i64, _i64]),
     "chase_create": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int, _vp]),
     "chase_destroy": (None, [_vp]),
     "chase_last_error": (ctypes.c_char_p, [_vp]),
@@ -136,6 +137,17 @@ def _check(ctx, rc):
 def config(n, nev, nex, **kw) -> chase_config:
     cfg = chase_config()
     lib().chase_config_init(ctypes.byref(cfg), n, nev, nex)
+    return _apply(cfg, kw)
+
+
+def config_fp32(n, nev, nex, **kw) -> chase_config:
+    """Table 1's single-precision defaults with precision = CHASE_FP32."""
+    cfg = chase_config()
+    lib().chase_config_init_fp32(ctypes.byref(cfg), n, nev, nex)
+    return _apply(cfg, kw)
+
+
+def _apply(cfg, kw):
     for k, v in kw.items():
         if not hasattr(cfg, k):
             raise KeyError(k)

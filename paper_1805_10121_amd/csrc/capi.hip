@@ -126,6 +126,17 @@ void chase_config_init(chase_config* cfg, int64_t n, int64_t nev, int64_t nex) {
   cfg->real_symmetric = 0;
 }
 
+void chase_config_init_fp32(chase_config* cfg, int64_t n, int64_t nev, int64_t nex) {
+  if (!cfg) return;
+  chase_config_init(cfg, n, nev, nex);
+  // Table 1, single-precision values
+  cfg->tol = 1e-5;
+  cfg->deg_max = 18;
+  cfg->deg = 10;
+  cfg->lanczos_iter = 12;
+  cfg->precision = CHASE_FP32;
+}
+
 int chase_create(chase_ctx** out, int device, void* hip_stream) {
   if (!out) return CHASE_EINVAL;
   *out = nullptr;

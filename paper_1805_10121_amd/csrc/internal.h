@@ -80,21 +80,26 @@ hipError_t launch_convert_f64_to_f32(const double* src, int64_t lds, float* dst,
 hipError_t launch_convert_f32_to_f64(const float* src, int64_t lds, double* dst, int64_t ldd,
                                      int64_t rows, int64_t cols, hipStream_t stream);
 
-// Outer-loop helpers (loop_kernels.hip).  w = values per element: 2 for complex128 data
-// (interleaved doubles), 1 for real float64 data; leading dimensions count elements.
-hipError_t launch_lanczos_step(const double* U, const double* Up, double* W, double* Un, int64_t n,
-                               int64_t ld, int64_t nv, const double* beta_prev, double* alpha_out,
-                               double* beta_out, hipStream_t s, int w = 2);
-hipError_t launch_normalize(double* X, int64_t n, int64_t ld, int64_t cols, hipStream_t s,
-                            int w = 2);
-hipError_t launch_resid(const double* AV, const double* V, const double* lam, int64_t n, int64_t ld,
-                        int64_t cols, double* out, hipStream_t s, int w = 2);
-hipError_t launch_gather(const double* src, int64_t lds, double* dst, int64_t ldd, int64_t n,
-                         const int* perm, int64_t cols, hipStream_t s, int w = 2);
-hipError_t launch_herm_sym(double* G, int64_t ld, int64_t m, hipStream_t s, int w = 2);
-hipError_t launch_add_diag(double* G, int64_t ld, int64_t m, double v, hipStream_t s, int w = 2);
-hipError_t launch_gaussian(double* X, int64_t n, int64_t ld, int64_t cols, uint64_t seed,
-                           hipStream_t s, int w = 2);
+// Outer-loop helpers (loop_kernels.hip), for double (complex128 / float64) and float (complex64
+// / float32) vectors.  w = values per element: 2 for interleaved complex data, 1 for real data;
+// leading dimensions count elements.  Scalars (Lanczos coefficients, residual norms) are double.
+#define CHASE_LOOP_DECL(R)                                                                      \
+  hipError_t launch_lanczos_step(const R* U, const R* Up, R* W, R* Un, int64_t n, int64_t ld,   \
+                                 int64_t nv, const double* beta_prev, double* alpha_out,        \
+                                 double* beta_out, hipStream_t s, int w = 2);                   \
+  hipError_t launch_normalize(R* X, int64_t n, int64_t ld, int64_t cols, hipStream_t s,         \
+                              int w = 2);                                                       \
+  hipError_t launch_resid(const R* AV, const R* V, const R* lam, int64_t n, int64_t ld,         \
+                          int64_t cols, double* out, hipStream_t s, int w = 2);                 \
+  hipError_t launch_gather(const R* src, int64_t lds, R* dst, int64_t ldd, int64_t n,           \
+                           const int* perm, int64_t cols, hipStream_t s, int w = 2);            \
+  hipError_t launch_herm_sym(R* G, int64_t ld, int64_t m, hipStream_t s, int w = 2);            \
+  hipError_t launch_add_diag(R* G, int64_t ld, int64_t m, double v, hipStream_t s, int w = 2);  \
+  hipError_t launch_gaussian(R* X, int64_t n, int64_t ld, int64_t cols, uint64_t seed,          \
+                             hipStream_t s, int w = 2);
+CHASE_LOOP_DECL(double)
+CHASE_LOOP_DECL(float)
+#undef CHASE_LOOP_DECL
 
 // ----------------------------------------------------------------------------- filter driver
 
@@ -156,6 +161,15 @@ class Batcher;
 int solve_with(chase_ctx* ctx, const chase_config* cfg, const void* H, int64_t ldh, void* V,
                int64_t ldv, double* ritzv, double* resid, chase_stats* stats, Batcher* batcher);
 int check_config(chase_ctx* ctx, const chase_config* cfg);
+// Layout of a solve's H and V elements: bytes per real scalar (8, or 4 for CHASE_FP32) and
+// values per element (2 complex, 1 real symmetric).
+inline int solve_scalar_bytes(const chase_config& c) { return c.precision == CHASE_FP32 ? 4 : 8; }
+inline int solve_width(const chase_config& c) { return c.real_symmetric ? 1 : 2; }
+inline size_t solve_elem_bytes(const chase_config& c) {
+  return static_cast<size_t>(solve_scalar_bytes(c)) * solve_width(c);
+}
+// Gaussian start block for a solve's V in the solve's own element type.
+hipError_t launch_start_block(void* V, const chase_config& c, uint64_t seed, hipStream_t s);
 }  // namespace chase
 
 #define CHASE_HIP_TRY(ctx, expr)                                                            \

@@ -270,7 +270,7 @@ namespace {
 
 size_t state_bytes_of(const chase_config& c) {
   return static_cast<size_t>(c.n) * static_cast<size_t>(c.nev + c.nex) *
-         (c.real_symmetric ? 8 : 16);
+         chase::solve_elem_bytes(c);
 }
 
 size_t ws_bytes_of(const chase_config& c, bool warm) {
@@ -340,8 +340,7 @@ void chase_server::worker(int w) {
       hipError_t e = hipSetDevice(device);
       if (e == hipSuccess) e = hipMalloc(&seq->V, state_bytes_of(req->cfg));
       if (e == hipSuccess)
-        e = chase::launch_gaussian(seq->V, req->cfg.n, req->cfg.n, nb, req->cfg.seed ^ 0x5eedULL,
-                                   ctx->stream, req->cfg.real_symmetric ? 1 : 2);
+        e = chase::launch_start_block(seq->V, req->cfg, req->cfg.seed ^ 0x5eedULL, ctx->stream);
       if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
       if (e != hipSuccess) {
         (void)hipGetLastError();
@@ -426,17 +425,24 @@ int chase_server_submit(chase_server* s, uint64_t seq_id, const chase_config* cf
     s->last_error = "NULL H or ldh < n";
     return CHASE_EINVAL;
   }
+  // the resident state is n x (nev+nex) elements of one type: sizes and element type are fixed
+  // for the life of a sequence
+  auto same_state = [&](const chase_config& c) {
+    return c.n == cfg->n && c.nev == cfg->nev && c.nex == cfg->nex &&
+           c.real_symmetric == cfg->real_symmetric &&
+           solve_scalar_bytes(c) == solve_scalar_bytes(*cfg);
+  };
+  const char* kStateMsg =
+      "n, nev, nex, real_symmetric and the element precision must stay the same within a sequence";
   auto sit = s->seqs.find(seq_id);
-  if (sit != s->seqs.end() &&
-      (sit->second.cfg.n != cfg->n || sit->second.cfg.nev != cfg->nev ||
-       sit->second.cfg.nex != cfg->nex)) {
-    s->last_error = "n, nev, nex must stay the same within a sequence";
+  if (sit != s->seqs.end() && !same_state(sit->second.cfg)) {
+    s->last_error = kStateMsg;
     return CHASE_EINVAL;
   }
   for (uint64_t t : s->queue) {
     const auto& r = s->reqs[t];
-    if (r.seq == seq_id && (r.cfg.n != cfg->n || r.cfg.nev != cfg->nev || r.cfg.nex != cfg->nex)) {
-      s->last_error = "n, nev, nex must stay the same within a sequence";
+    if (r.seq == seq_id && !same_state(r.cfg)) {
+      s->last_error = kStateMsg;
       return CHASE_EINVAL;
     }
   }

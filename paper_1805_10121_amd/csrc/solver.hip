@@ -32,8 +32,6 @@
 namespace chase {
 namespace {
 
-constexpr double kEps = 1.1102230246251565e-16;  // 2^-53
-
 struct Layout {
   size_t V, W, AQ, X, G, T, lam, res, evE, perm, info, U, Wl, lal, lbe, zero, Z, tau, H32, V32, W32;
   size_t total;
@@ -41,9 +39,9 @@ struct Layout {
 
 size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
 
-Layout make_layout(int64_t n, int64_t nb, int64_t nv, int64_t k, bool mixed, int w) {
+Layout make_layout(int64_t n, int64_t nb, int64_t nv, int64_t k, bool mixed, int w, int esz) {
   Layout L{};
-  const size_t es = 8 * static_cast<size_t>(w);  // bytes per element
+  const size_t es = static_cast<size_t>(esz) * w;  // bytes per element (esz: bytes per scalar)
   size_t off = 0;
   auto take = [&](size_t bytes) {
     size_t o = off;
@@ -68,7 +66,7 @@ Layout make_layout(int64_t n, int64_t nb, int64_t nv, int64_t k, bool mixed, int
   L.lbe = take(static_cast<size_t>(nv) * k * 8);
   L.zero = take(static_cast<size_t>(nv) * 8);
   L.Z = take(static_cast<size_t>(k) * nb * es);
-  L.tau = take(nb * es);
+  L.tau = take(nb * 16);
   if (mixed) {  // FP32 copies: planar complex64 or real float32 H, and two blocks
     L.H32 = take(static_cast<size_t>(n) * n * 4 * w);
     L.V32 = take(static_cast<size_t>(n) * nb * 4 * w);
@@ -86,6 +84,7 @@ struct Timer {
   }
 };
 
+template <typename R>  // device scalar: double (complex128 / float64) or float (complex64 / float32)
 class Solver {
  public:
   Solver(chase_ctx* ctx, const chase_config& cfg, Batcher* batcher)
@@ -108,8 +107,11 @@ class Solver {
   int fallbacks_ = 0;
 
   template <typename P> P* at(size_t off) { return reinterpret_cast<P*>(base_ + off); }
-  double* col(size_t off, int64_t c) { return at<double>(off) + w_ * c * n_; }
-  size_t es() const { return 8 * static_cast<size_t>(w_); }
+  R* col(size_t off, int64_t c) { return at<R>(off) + w_ * c * n_; }
+  size_t es() const { return sizeof(R) * static_cast<size_t>(w_); }
+  static constexpr bool kF64 = sizeof(R) == 8;
+  // unit roundoff of R
+  static constexpr double kU = kF64 ? 1.1102230246251565e-16 : 5.9604644775390625e-08;
 
   int blas(rocblas_status s, const char* what) {
     if (s != rocblas_status_success)
@@ -125,54 +127,66 @@ class Solver {
   // C <- ar op(A) op(B) + br C with real scalars; conjugate transpose is the transpose for real
   // data.
   int gemm(rocblas_operation ta, rocblas_operation tb, int64_t m, int64_t nn, int64_t k,
-           double ar, const double* A, int64_t lda, const double* B, int64_t ldb, double br,
-           double* C, int64_t ldc) {
+           double ar, const R* A, int64_t lda, const R* B, int64_t ldb, double br, R* C,
+           int64_t ldc) {
+    const rocblas_int im = static_cast<rocblas_int>(m), in = static_cast<rocblas_int>(nn),
+                      ik = static_cast<rocblas_int>(k), ia = static_cast<rocblas_int>(lda),
+                      ib = static_cast<rocblas_int>(ldb), ic = static_cast<rocblas_int>(ldc);
     if (real_) {
       auto rt = [](rocblas_operation o) {
         return o == rocblas_operation_conjugate_transpose ? rocblas_operation_transpose : o;
       };
-      return blas(rocblas_dgemm(ctx_->blas, rt(ta), rt(tb), static_cast<rocblas_int>(m),
-                                static_cast<rocblas_int>(nn), static_cast<rocblas_int>(k), &ar, A,
-                                static_cast<rocblas_int>(lda), B, static_cast<rocblas_int>(ldb),
-                                &br, C, static_cast<rocblas_int>(ldc)),
-                  "dgemm");
+      if constexpr (kF64) {
+        return blas(rocblas_dgemm(ctx_->blas, rt(ta), rt(tb), im, in, ik, &ar, A, ia, B, ib, &br,
+                                  C, ic),
+                    "dgemm");
+      } else {
+        const float af = static_cast<float>(ar), bf = static_cast<float>(br);
+        return blas(rocblas_sgemm(ctx_->blas, rt(ta), rt(tb), im, in, ik, &af, A, ia, B, ib, &bf,
+                                  C, ic),
+                    "sgemm");
+      }
+    }
+    if constexpr (!kF64) {
+      const rocblas_float_complex al(static_cast<float>(ar), 0.f), be(static_cast<float>(br), 0.f);
+      return blas(rocblas_cgemm(ctx_->blas, ta, tb, im, in, ik, &al,
+                                reinterpret_cast<const rocblas_float_complex*>(A), ia,
+                                reinterpret_cast<const rocblas_float_complex*>(B), ib, &be,
+                                reinterpret_cast<rocblas_float_complex*>(C), ic),
+                  "cgemm");
     }
     const rocblas_double_complex al(ar, 0.0), be(br, 0.0);
-    return blas(rocblas_zgemm(ctx_->blas, ta, tb, static_cast<rocblas_int>(m),
-                              static_cast<rocblas_int>(nn), static_cast<rocblas_int>(k), &al,
-                              reinterpret_cast<const rocblas_double_complex*>(A),
-                              static_cast<rocblas_int>(lda),
-                              reinterpret_cast<const rocblas_double_complex*>(B),
-                              static_cast<rocblas_int>(ldb), &be,
-                              reinterpret_cast<rocblas_double_complex*>(C),
-                              static_cast<rocblas_int>(ldc)),
+    return blas(rocblas_zgemm(ctx_->blas, ta, tb, im, in, ik, &al,
+                              reinterpret_cast<const rocblas_double_complex*>(A), ia,
+                              reinterpret_cast<const rocblas_double_complex*>(B), ib, &be,
+                              reinterpret_cast<rocblas_double_complex*>(C), ic),
                 "zgemm");
   }
   // OUT <- alpha H X + gamma X + beta OUT with the product kernel of the element type.
-  hipError_t product(const double* H, int64_t ldh, const double* X, int64_t ldx, double* OUT,
-                     int64_t ldo, int64_t ncols, double alpha, double beta, double gamma) {
+  hipError_t product(const R* H, int64_t ldh, const R* X, int64_t ldx, R* OUT, int64_t ldo,
+                     int64_t ncols, double alpha, double beta, double gamma) {
+    const R a = static_cast<R>(alpha), b = static_cast<R>(beta), g = static_cast<R>(gamma);
     if (real_)
-      return launch_hemm_step_real<double>(H, ldh, n_, X, ldx, OUT, ldo, ncols, alpha, beta,
-                                           gamma, ctx_->prod, s_);
-    return launch_hemm_step<double>(H, ldh, n_, X, ldx, OUT, ldo, ncols, alpha, beta, gamma,
-                                    ctx_->prod, s_);
+      return launch_hemm_step_real<R>(H, ldh, n_, X, ldx, OUT, ldo, ncols, a, b, g, ctx_->prod, s_);
+    return launch_hemm_step<R>(H, ldh, n_, X, ldx, OUT, ldo, ncols, a, b, g, ctx_->prod, s_);
   }
-  int lanczos(const double* H, int64_t ldh, double* V);
+  int lanczos(const R* H, int64_t ldh, R* V);
   int cgs(int64_t nlock, int64_t nact);
   int cholqr(int64_t nact, bool shift, int slot);
   int householder(int64_t nlock, int64_t nact);
   int orthogonalize(int64_t nlock, int64_t nact);
-  int filter(const double* H, int64_t ldh, int64_t nlock, int64_t nact,
+  int filter(const R* H, int64_t ldh, int64_t nlock, int64_t nact,
              const std::vector<int>& m, const std::vector<int>& prec);
 
   double b_sup_ = 0, mu_1_ = 0, mu_b_ = 0, norm_est_ = 0;
 };
 
-int Solver::lanczos(const double* H, int64_t ldh, double* V) {
+template <typename R>
+int Solver<R>::lanczos(const R* H, int64_t ldh, R* V) {
   const bool need_dos = !cfg_.approx && !cfg_.have_mu;
   const int64_t nv = need_dos ? 1 + cfg_.num_lanczos : 1;
   const int k = static_cast<int>(std::min<int64_t>(cfg_.lanczos_iter, n_));
-  double* U = at<double>(L_.U);
+  R* U = at<R>(L_.U);
   int rc;
   if (cfg_.lanczos_start) {
     rc = hip(hipMemcpyAsync(U, cfg_.lanczos_start, static_cast<size_t>(n_) * nv * es(),
@@ -184,10 +198,10 @@ int Solver::lanczos(const double* H, int64_t ldh, double* V) {
   if (rc) return rc;
   if ((rc = hip(launch_normalize(U, n_, n_, nv, s_, w_), "normalize"))) return rc;
   if ((rc = hip(hipMemsetAsync(at<double>(L_.zero), 0, nv * 8, s_), "memset"))) return rc;
-  double* Wl = at<double>(L_.Wl);
+  R* Wl = at<R>(L_.Wl);
   for (int j = 0; j < k; ++j) {
-    double* Uj = U + w_ * static_cast<int64_t>(j) * nv * n_;
-    const double* Up = j > 0 ? U + w_ * static_cast<int64_t>(j - 1) * nv * n_ : Uj;
+    R* Uj = U + w_ * static_cast<int64_t>(j) * nv * n_;
+    const R* Up = j > 0 ? U + w_ * static_cast<int64_t>(j - 1) * nv * n_ : Uj;
     const double* bp = j > 0 ? at<double>(L_.lbe) + (j - 1) * nv : at<double>(L_.zero);
     if ((rc = hip(product(H, ldh, Uj, n_, Wl, n_, nv, 1.0, 0.0, 0.0), "lanczos product")))
       return rc;
@@ -231,15 +245,16 @@ int Solver::lanczos(const double* H, int64_t ldh, double* V) {
     if (static_cast<int64_t>(sel.size()) > nb_) sel.resize(nb_);
     const int64_t r = static_cast<int64_t>(sel.size());
     if (r > 0) {
-      std::vector<double> Zh(static_cast<size_t>(r1.k) * r * w_, 0.0);  // k x r, col-major
+      std::vector<R> Zh(static_cast<size_t>(r1.k) * r * w_, R(0));  // k x r, col-major
       for (int64_t q = 0; q < r; ++q)
-        for (int j = 0; j < r1.k; ++j) Zh[w_ * (j + q * r1.k)] = r1.evecs[j * r1.k + sel[q]];
-      if ((rc = hip(hipMemcpyAsync(at<double>(L_.Z), Zh.data(), Zh.size() * 8,
+        for (int j = 0; j < r1.k; ++j)
+          Zh[w_ * (j + q * r1.k)] = static_cast<R>(r1.evecs[j * r1.k + sel[q]]);
+      if ((rc = hip(hipMemcpyAsync(at<R>(L_.Z), Zh.data(), Zh.size() * sizeof(R),
                                    hipMemcpyHostToDevice, s_), "h2d")))
         return rc;
       // basis of DoS run 1: columns U_j[:, 1], j < k, stride nv*n between consecutive j
       if ((rc = gemm(rocblas_operation_none, rocblas_operation_none, n_, r, r1.k, 1.0,
-                      U + w_ * n_, nv * n_, at<double>(L_.Z), r1.k, 0.0, V, n_)))
+                      U + w_ * n_, nv * n_, at<R>(L_.Z), r1.k, 0.0, V, n_)))
         return rc;
       if ((rc = hip(hipStreamSynchronize(s_), "sync"))) return rc;
     }
@@ -248,11 +263,12 @@ int Solver::lanczos(const double* H, int64_t ldh, double* V) {
 }
 
 // Block classical Gram-Schmidt of the active block against the locked prefix Y = V[:, :nlock].
-int Solver::cgs(int64_t nlock, int64_t nact) {
+template <typename R>
+int Solver<R>::cgs(int64_t nlock, int64_t nact) {
   if (nlock == 0) return CHASE_OK;
-  double* Y = at<double>(L_.V);
-  double* A = col(L_.V, nlock);
-  double* T = at<double>(L_.T);
+  R* Y = at<R>(L_.V);
+  R* A = col(L_.V, nlock);
+  R* T = at<R>(L_.T);
   int rc = gemm(rocblas_operation_conjugate_transpose, rocblas_operation_none, nlock, nact, n_, 1.0,
                  Y, n_, A, n_, 0.0, T, nb_);
   if (rc) return rc;
@@ -263,97 +279,111 @@ int Solver::cgs(int64_t nlock, int64_t nact) {
 // One (optionally shifted) Cholesky QR pass on the active block: G = A^H A (+ s I) = R^H R,
 // A <- A R^-1.  Shift as in shifted CholeskyQR3 (Fukaya et al.) with ||A||_2^2 <= nact for
 // unit columns.
-int Solver::cholqr(int64_t nact, bool shift, int slot) {
-  double* A = col(L_.V, n_ == 0 ? 0 : (nb_ - nact));
-  double* G = at<double>(L_.G);
+template <typename R>
+int Solver<R>::cholqr(int64_t nact, bool shift, int slot) {
+  R* A = col(L_.V, n_ == 0 ? 0 : (nb_ - nact));
+  R* G = at<R>(L_.G);
   // Gram matrix by GEMM (both triangles; rocBLAS's GEMM is faster than its HERK at these shapes)
   int rc = gemm(rocblas_operation_conjugate_transpose, rocblas_operation_none, nact, nact, n_, 1.0,
                 A, n_, A, n_, 0.0, G, nb_);
   if (rc) return rc;
   if (shift) {
     const double s = 11.0 * (static_cast<double>(n_) * nact + static_cast<double>(nact) * (nact + 1)) *
-                     kEps * static_cast<double>(nact);
+                     kU * static_cast<double>(nact);
     if ((rc = hip(launch_add_diag(G, nb_, nact, s, s_, w_), "add_diag"))) return rc;
   }
   rocblas_int* info = at<rocblas_int>(L_.info) + slot;
-  rc = real_ ? blas(rocsolver_dpotrf(ctx_->blas, rocblas_fill_upper, static_cast<rocblas_int>(nact),
-                                     G, static_cast<rocblas_int>(nb_), info),
-                    "dpotrf")
-             : blas(rocsolver_zpotrf(ctx_->blas, rocblas_fill_upper, static_cast<rocblas_int>(nact),
-                                     reinterpret_cast<rocblas_double_complex*>(G),
-                                     static_cast<rocblas_int>(nb_), info),
-                    "zpotrf");
+  const rocblas_int ia = static_cast<rocblas_int>(nact), ig = static_cast<rocblas_int>(nb_),
+                    in = static_cast<rocblas_int>(n_);
+  if constexpr (kF64)
+    rc = real_ ? blas(rocsolver_dpotrf(ctx_->blas, rocblas_fill_upper, ia, G, ig, info), "dpotrf")
+               : blas(rocsolver_zpotrf(ctx_->blas, rocblas_fill_upper, ia,
+                                       reinterpret_cast<rocblas_double_complex*>(G), ig, info),
+                      "zpotrf");
+  else
+    rc = real_ ? blas(rocsolver_spotrf(ctx_->blas, rocblas_fill_upper, ia, G, ig, info), "spotrf")
+               : blas(rocsolver_cpotrf(ctx_->blas, rocblas_fill_upper, ia,
+                                       reinterpret_cast<rocblas_float_complex*>(G), ig, info),
+                      "cpotrf");
   if (rc) return rc;
   // The factorisation status is read once per orthonormalisation (see orthogonalize); a failed
   // factorisation makes this solve produce garbage that is then discarded.
-  const double one = 1.0;
-  if (real_)
-    return blas(rocblas_dtrsm(ctx_->blas, rocblas_side_right, rocblas_fill_upper,
-                              rocblas_operation_none, rocblas_diagonal_non_unit,
-                              static_cast<rocblas_int>(n_), static_cast<rocblas_int>(nact), &one, G,
-                              static_cast<rocblas_int>(nb_), A, static_cast<rocblas_int>(n_)),
-                "dtrsm");
-  const rocblas_double_complex al(1.0, 0.0);
-  return blas(rocblas_ztrsm(ctx_->blas, rocblas_side_right, rocblas_fill_upper,
-                            rocblas_operation_none, rocblas_diagonal_non_unit,
-                            static_cast<rocblas_int>(n_), static_cast<rocblas_int>(nact), &al,
-                            reinterpret_cast<const rocblas_double_complex*>(G),
-                            static_cast<rocblas_int>(nb_),
-                            reinterpret_cast<rocblas_double_complex*>(A),
-                            static_cast<rocblas_int>(n_)),
-              "ztrsm");
+  if constexpr (!kF64) {
+    const float one = 1.f;
+    const rocblas_float_complex al(1.f, 0.f);
+    if (real_)
+      return blas(rocblas_strsm(ctx_->blas, rocblas_side_right, rocblas_fill_upper,
+                                rocblas_operation_none, rocblas_diagonal_non_unit, in, ia, &one, G,
+                                ig, A, in),
+                  "strsm");
+    return blas(rocblas_ctrsm(ctx_->blas, rocblas_side_right, rocblas_fill_upper,
+                              rocblas_operation_none, rocblas_diagonal_non_unit, in, ia, &al,
+                              reinterpret_cast<const rocblas_float_complex*>(G), ig,
+                              reinterpret_cast<rocblas_float_complex*>(A), in),
+                "ctrsm");
+  } else {
+    const double one = 1.0;
+    const rocblas_double_complex al(1.0, 0.0);
+    if (real_)
+      return blas(rocblas_dtrsm(ctx_->blas, rocblas_side_right, rocblas_fill_upper,
+                                rocblas_operation_none, rocblas_diagonal_non_unit, in, ia, &one, G,
+                                ig, A, in),
+                  "dtrsm");
+    return blas(rocblas_ztrsm(ctx_->blas, rocblas_side_right, rocblas_fill_upper,
+                              rocblas_operation_none, rocblas_diagonal_non_unit, in, ia, &al,
+                              reinterpret_cast<const rocblas_double_complex*>(G), ig,
+                              reinterpret_cast<rocblas_double_complex*>(A), in),
+                "ztrsm");
+  }
 }
 
 // Householder QR of [Y V] (the paper's ORTHOGONALIZE), keeping the columns after Y.
-int Solver::householder(int64_t nlock, int64_t nact) {
+template <typename R>
+int Solver<R>::householder(int64_t nlock, int64_t nact) {
   ++fallbacks_;
   const int64_t ncol = nlock + nact;
-  double* Wb = at<double>(L_.W);
-  int rc = hip(hipMemcpyAsync(Wb, at<double>(L_.V), static_cast<size_t>(n_) * ncol * es(),
+  R* Wb = at<R>(L_.W);
+  int rc = hip(hipMemcpyAsync(Wb, at<R>(L_.V), static_cast<size_t>(n_) * ncol * es(),
                               hipMemcpyDeviceToDevice, s_),
                "copy");
   if (rc) return rc;
-  if (real_) {
-    double* tau = at<double>(L_.tau);
-    if ((rc = blas(rocsolver_dgeqrf(ctx_->blas, static_cast<rocblas_int>(n_),
-                                    static_cast<rocblas_int>(ncol), Wb,
-                                    static_cast<rocblas_int>(n_), tau),
-                   "dgeqrf")))
-      return rc;
-    if ((rc = blas(rocsolver_dorgqr(ctx_->blas, static_cast<rocblas_int>(n_),
-                                    static_cast<rocblas_int>(ncol), static_cast<rocblas_int>(ncol),
-                                    Wb, static_cast<rocblas_int>(n_), tau),
-                   "dorgqr")))
-      return rc;
-    return hip(hipMemcpyAsync(col(L_.V, nlock), Wb + nlock * n_,
-                              static_cast<size_t>(n_) * nact * es(), hipMemcpyDeviceToDevice, s_),
-               "copy");
+  const rocblas_int in = static_cast<rocblas_int>(n_), ic = static_cast<rocblas_int>(ncol);
+  if constexpr (kF64) {
+    if (real_) {
+      double* tau = at<double>(L_.tau);
+      if ((rc = blas(rocsolver_dgeqrf(ctx_->blas, in, ic, Wb, in, tau), "dgeqrf"))) return rc;
+      if ((rc = blas(rocsolver_dorgqr(ctx_->blas, in, ic, ic, Wb, in, tau), "dorgqr"))) return rc;
+    } else {
+      auto* Wz = reinterpret_cast<rocblas_double_complex*>(Wb);
+      auto* tau = at<rocblas_double_complex>(L_.tau);
+      if ((rc = blas(rocsolver_zgeqrf(ctx_->blas, in, ic, Wz, in, tau), "zgeqrf"))) return rc;
+      if ((rc = blas(rocsolver_zungqr(ctx_->blas, in, ic, ic, Wz, in, tau), "zungqr"))) return rc;
+    }
+  } else {
+    if (real_) {
+      float* tau = at<float>(L_.tau);
+      if ((rc = blas(rocsolver_sgeqrf(ctx_->blas, in, ic, Wb, in, tau), "sgeqrf"))) return rc;
+      if ((rc = blas(rocsolver_sorgqr(ctx_->blas, in, ic, ic, Wb, in, tau), "sorgqr"))) return rc;
+    } else {
+      auto* Wc = reinterpret_cast<rocblas_float_complex*>(Wb);
+      auto* tau = at<rocblas_float_complex>(L_.tau);
+      if ((rc = blas(rocsolver_cgeqrf(ctx_->blas, in, ic, Wc, in, tau), "cgeqrf"))) return rc;
+      if ((rc = blas(rocsolver_cungqr(ctx_->blas, in, ic, ic, Wc, in, tau), "cungqr"))) return rc;
+    }
   }
-  auto* tau = at<rocblas_double_complex>(L_.tau);
-  if ((rc = blas(rocsolver_zgeqrf(ctx_->blas, static_cast<rocblas_int>(n_),
-                                  static_cast<rocblas_int>(ncol),
-                                  reinterpret_cast<rocblas_double_complex*>(Wb),
-                                  static_cast<rocblas_int>(n_), tau),
-                 "zgeqrf")))
-    return rc;
-  if ((rc = blas(rocsolver_zungqr(ctx_->blas, static_cast<rocblas_int>(n_),
-                                  static_cast<rocblas_int>(ncol), static_cast<rocblas_int>(ncol),
-                                  reinterpret_cast<rocblas_double_complex*>(Wb),
-                                  static_cast<rocblas_int>(n_), tau),
-                 "zungqr")))
-    return rc;
-  return hip(hipMemcpyAsync(col(L_.V, nlock), Wb + 2 * nlock * n_,
-                            static_cast<size_t>(n_) * nact * 16, hipMemcpyDeviceToDevice, s_),
+  return hip(hipMemcpyAsync(col(L_.V, nlock), Wb + w_ * nlock * n_,
+                            static_cast<size_t>(n_) * nact * es(), hipMemcpyDeviceToDevice, s_),
              "copy");
 }
 
 // The three Cholesky factorisations report their status into three slots that are read with
 // one synchronisation at the end; if any failed, the filtered block is restored from its copy in
 // W and orthonormalised by Householder QR instead.
-int Solver::orthogonalize(int64_t nlock, int64_t nact) {
+template <typename R>
+int Solver<R>::orthogonalize(int64_t nlock, int64_t nact) {
   int rc;
-  double* A = col(L_.V, nlock);
-  double* B = col(L_.W, nlock);  // W is free between the filter and Rayleigh-Ritz
+  R* A = col(L_.V, nlock);
+  R* B = col(L_.W, nlock);  // W is free between the filter and Rayleigh-Ritz
   if ((rc = hip(hipMemcpyAsync(B, A, static_cast<size_t>(n_) * nact * es(),
                                hipMemcpyDeviceToDevice, s_), "copy")))
     return rc;
@@ -375,8 +405,19 @@ int Solver::orthogonalize(int64_t nlock, int64_t nact) {
   return householder(nlock, nact);
 }
 
-int Solver::filter(const double* H, int64_t ldh, int64_t nlock, int64_t nact,
-                   const std::vector<int>& m, const std::vector<int>& prec) {
+template <typename R>
+int Solver<R>::filter(const R* H, int64_t ldh, int64_t nlock, int64_t nact,
+                      const std::vector<int>& m, const std::vector<int>& prec) {
+  if constexpr (!kF64) {  // all-FP32 solve: every column in the data's own precision
+    int64_t mv = 0;
+    const int rc = hip(run_filter<float>(H, ldh, n_, col(L_.V, nlock), col(L_.W, nlock), n_, nact,
+                                         m.data(), b_sup_, mu_1_, mu_b_, ctx_->prod, s_, &mv,
+                                         real_ ? 3 : 1),
+                       "filter fp32");
+    if (rc) return rc;
+    st_.filter_matvecs += mv;
+    return CHASE_OK;
+  } else {
   int64_t n32 = 0;
   while (n32 < nact && prec[n32] == 1) ++n32;
   int rc;
@@ -441,11 +482,13 @@ int Solver::filter(const double* H, int64_t ldh, int64_t nlock, int64_t nact,
     st_.filter_matvecs += mv;
   }
   return CHASE_OK;
+  }
 }
 
-int Solver::run(const void* Hv, int64_t ldh, void* Vuser, int64_t ldv, double* ritzv, double* resid,
+template <typename R>
+int Solver<R>::run(const void* Hv, int64_t ldh, void* Vuser, int64_t ldv, double* ritzv, double* resid,
                 chase_stats* stats) {
-  const double* H = static_cast<const double*>(Hv);
+  const R* H = static_cast<const R*>(Hv);
   n_ = cfg_.n;
   nb_ = cfg_.nev + cfg_.nex;
   real_ = cfg_.real_symmetric != 0;
@@ -455,7 +498,7 @@ int Solver::run(const void* Hv, int64_t ldh, void* Vuser, int64_t ldv, double* r
   const bool need_dos = !cfg_.approx && !cfg_.have_mu;
   const int64_t nv = need_dos ? 1 + cfg_.num_lanczos : 1;
   const int64_t k = std::min<int64_t>(cfg_.lanczos_iter, n_);
-  L_ = make_layout(n_, nb_, nv, k, mixed, w_);
+  L_ = make_layout(n_, nb_, nv, k, mixed, w_, static_cast<int>(sizeof(R)));
   int rc = ensure_workspace(ctx_, L_.total);
   if (rc) return rc;
   base_ = static_cast<char*>(ctx_->ws);
@@ -490,21 +533,24 @@ int Solver::run(const void* Hv, int64_t ldh, void* Vuser, int64_t ldv, double* r
 
   (void)hipEventRecord(ev[6], s_);
   // state: V (ld n) <- user block
-  if ((rc = hip(hipMemcpy2DAsync(at<double>(L_.V), n_ * es(), Vuser, ldv * es(), n_ * es(), nb_,
+  if ((rc = hip(hipMemcpy2DAsync(at<R>(L_.V), n_ * es(), Vuser, ldv * es(), n_ * es(), nb_,
                                  hipMemcpyDeviceToDevice, s_),
                 "copy V")))
     return rc;
-  if (mixed && real_ &&
-      (rc = hip(launch_convert_f64_to_f32(H, ldh, at<float>(L_.H32), n_, n_, n_, s_), "convert H")))
-    return rc;
-  if (mixed && !real_ &&
-      (rc = hip(launch_convert_c128_to_planar32(H, ldh, at<float>(L_.H32), n_, n_, s_),
-                "convert H")))
-    return rc;
+  if constexpr (kF64) {
+    if (mixed && real_ &&
+        (rc = hip(launch_convert_f64_to_f32(H, ldh, at<float>(L_.H32), n_, n_, n_, s_),
+                  "convert H")))
+      return rc;
+    if (mixed && !real_ &&
+        (rc = hip(launch_convert_c128_to_planar32(H, ldh, at<float>(L_.H32), n_, n_, s_),
+                  "convert H")))
+      return rc;
+  }
 
   // ---------------------------------------------------------------- LANCZOS (Alg. 1 line 2)
   (void)hipEventRecord(ev[0], s_);
-  if ((rc = lanczos(H, ldh, at<double>(L_.V)))) return rc;
+  if ((rc = lanczos(H, ldh, at<R>(L_.V)))) return rc;
   (void)hipEventRecord(ev[1], s_);
   if (cfg_.approx) {
     double lo = ritzv[0], hi = ritzv[0];
@@ -541,6 +587,7 @@ int Solver::run(const void* Hv, int64_t ldh, void* Vuser, int64_t ldv, double* r
   std::vector<double> hist_res(nb_, INFINITY);
   std::vector<char> hist_fp32(nb_, mixed ? 1 : 0), lock64(nb_, 0);
   std::vector<double> lam_act(nb_, 0.0), res_act(nb_, 0.0), lam_lock, res_lock;
+  std::vector<R> lam_dev(nb_);
   std::vector<int> perm(nb_);
   int it = 0;
   while (nlock < cfg_.nev && it < cfg_.max_iter) {
@@ -555,29 +602,38 @@ int Solver::run(const void* Hv, int64_t ldh, void* Vuser, int64_t ldv, double* r
     if ((rc = orthogonalize(nlock, nact))) return rc;                       // lines 5-6
     (void)hipEventRecord(ev[2], s_);
     // RAYLEIGH-RITZ (line 7, Alg. 2)
-    double* Q = col(L_.V, nlock);
-    double* AQ = at<double>(L_.AQ);
-    double* G = at<double>(L_.G);
+    R* Q = col(L_.V, nlock);
+    R* AQ = at<R>(L_.AQ);
+    R* G = at<R>(L_.G);
     if ((rc = hip(product(H, ldh, Q, n_, AQ, n_, nact, 1.0, 0.0, 0.0), "H Q"))) return rc;
     st_.matvecs += nact;
     if ((rc = gemm(rocblas_operation_conjugate_transpose, rocblas_operation_none, nact, nact, n_,
                     1.0, Q, n_, AQ, n_, 0.0, G, nb_)))
       return rc;
     if ((rc = hip(launch_herm_sym(G, nb_, nact, s_, w_), "sym"))) return rc;
-    rc = real_ ? blas(rocsolver_dsyevd(ctx_->blas, rocblas_evect_original, rocblas_fill_upper,
-                                       static_cast<rocblas_int>(nact), G,
-                                       static_cast<rocblas_int>(nb_), at<double>(L_.lam),
-                                       at<double>(L_.evE), at<rocblas_int>(L_.info)),
-                      "dsyevd")
-               : blas(rocsolver_zheevd(ctx_->blas, rocblas_evect_original, rocblas_fill_upper,
-                                       static_cast<rocblas_int>(nact),
-                                       reinterpret_cast<rocblas_double_complex*>(G),
-                                       static_cast<rocblas_int>(nb_), at<double>(L_.lam),
-                                       at<double>(L_.evE), at<rocblas_int>(L_.info)),
-                      "zheevd");
+    {
+      const rocblas_int ia = static_cast<rocblas_int>(nact), ig = static_cast<rocblas_int>(nb_);
+      R* lam = at<R>(L_.lam);
+      R* evE = at<R>(L_.evE);
+      rocblas_int* inf = at<rocblas_int>(L_.info);
+      const auto ev = rocblas_evect_original;
+      const auto up = rocblas_fill_upper;
+      if constexpr (kF64)
+        rc = real_ ? blas(rocsolver_dsyevd(ctx_->blas, ev, up, ia, G, ig, lam, evE, inf), "dsyevd")
+                   : blas(rocsolver_zheevd(ctx_->blas, ev, up, ia,
+                                           reinterpret_cast<rocblas_double_complex*>(G), ig, lam,
+                                           evE, inf),
+                          "zheevd");
+      else
+        rc = real_ ? blas(rocsolver_ssyevd(ctx_->blas, ev, up, ia, G, ig, lam, evE, inf), "ssyevd")
+                   : blas(rocsolver_cheevd(ctx_->blas, ev, up, ia,
+                                           reinterpret_cast<rocblas_float_complex*>(G), ig, lam,
+                                           evE, inf),
+                          "cheevd");
+    }
     if (rc) return rc;
-    double* Wb = at<double>(L_.W);
-    double* Xb = at<double>(L_.X);
+    R* Wb = at<R>(L_.W);
+    R* Xb = at<R>(L_.X);
     if ((rc = gemm(rocblas_operation_none, rocblas_operation_none, n_, nact, nact, 1.0, Q, n_, G,
                     nb_, 0.0, Wb, n_)))
       return rc;
@@ -586,7 +642,7 @@ int Solver::run(const void* Hv, int64_t ldh, void* Vuser, int64_t ldv, double* r
       return rc;
     (void)hipEventRecord(ev[3], s_);
     // residuals (line 8)
-    if ((rc = hip(launch_resid(Xb, Wb, at<double>(L_.lam), n_, n_, nact, at<double>(L_.res), s_,
+    if ((rc = hip(launch_resid(Xb, Wb, at<R>(L_.lam), n_, n_, nact, at<double>(L_.res), s_,
                                w_),
                   "resid")))
       return rc;
@@ -595,7 +651,7 @@ int Solver::run(const void* Hv, int64_t ldh, void* Vuser, int64_t ldv, double* r
                   "copy")))
       return rc;
     int info = 0;
-    if ((rc = hip(hipMemcpyAsync(lam_act.data(), at<double>(L_.lam), nact * 8,
+    if ((rc = hip(hipMemcpyAsync(lam_dev.data(), at<R>(L_.lam), nact * sizeof(R),
                                  hipMemcpyDeviceToHost, s_), "d2h")))
       return rc;
     if ((rc = hip(hipMemcpyAsync(res_act.data(), at<double>(L_.res), nact * 8,
@@ -610,7 +666,8 @@ int Solver::run(const void* Hv, int64_t ldh, void* Vuser, int64_t ldv, double* r
     st_.ortho_ms += elapsed(1, 2);
     st_.rr_ms += elapsed(2, 3);
     st_.resid_ms += elapsed(3, 4);
-    if (info != 0) return set_error(ctx_, CHASE_ENUMERIC, "zheevd did not converge");
+    if (info != 0) return set_error(ctx_, CHASE_ENUMERIC, "Rayleigh-Ritz eigensolver did not converge");
+    for (int64_t a = 0; a < nact; ++a) lam_act[a] = static_cast<double>(lam_dev[a]);
     for (int64_t a = 0; a < nact; ++a)
       if (!std::isfinite(lam_act[a]) || !std::isfinite(res_act[a]))
         return set_error(ctx_, CHASE_ENUMERIC, "NaN/Inf in Ritz values or residuals");
@@ -724,11 +781,11 @@ int Solver::run(const void* Hv, int64_t ldh, void* Vuser, int64_t ldv, double* r
   if ((rc = hip(hipMemcpyAsync(at<int>(L_.perm), perm.data(), nb_ * 4, hipMemcpyHostToDevice, s_),
                 "h2d")))
     return rc;
-  if ((rc = hip(launch_gather(at<double>(L_.V), n_, at<double>(L_.W), n_, n_, at<int>(L_.perm), nb_,
+  if ((rc = hip(launch_gather(at<R>(L_.V), n_, at<R>(L_.W), n_, n_, at<int>(L_.perm), nb_,
                               s_, w_),
                 "gather")))
     return rc;
-  if ((rc = hip(hipMemcpy2DAsync(Vuser, ldv * es(), at<double>(L_.W), n_ * es(), n_ * es(), nb_,
+  if ((rc = hip(hipMemcpy2DAsync(Vuser, ldv * es(), at<R>(L_.W), n_ * es(), n_ * es(), nb_,
                                  hipMemcpyDeviceToDevice, s_),
                 "copy out")))
     return rc;
@@ -765,8 +822,9 @@ int check_config(chase_ctx* ctx, const chase_config* cfg) {
   if (cfg->max_iter < 1) return set_error(ctx, CHASE_EINVAL, "max_iter must be >= 1");
   if (cfg->lanczos_iter < 1 || cfg->num_lanczos < 1)
     return set_error(ctx, CHASE_EINVAL, "lanczos_iter and num_lanczos must be >= 1");
-  if (cfg->precision != CHASE_FP64 && cfg->precision != CHASE_MIXED)
-    return set_error(ctx, CHASE_EINVAL, "precision must be CHASE_FP64 or CHASE_MIXED");
+  if (cfg->precision != CHASE_FP64 && cfg->precision != CHASE_MIXED &&
+      cfg->precision != CHASE_FP32)
+    return set_error(ctx, CHASE_EINVAL, "precision must be CHASE_FP64, CHASE_FP32 or CHASE_MIXED");
   if (cfg->precision == CHASE_MIXED &&
       (!(cfg->switch_resid > 0.0) || cfg->deg_max_fp32 < 2 || cfg->deg_max_fp32 > 64))
     return set_error(ctx, CHASE_EINVAL, "switch_resid > 0 and deg_max_fp32 in [2, 64]");
@@ -793,13 +851,24 @@ int solve_with(chase_ctx* ctx, const chase_config* cfg, const void* H, int64_t l
       if (!std::isfinite(ritzv[i])) return set_error(ctx, CHASE_EINVAL, "ritzv must be finite");
   const char* ph = static_cast<const char*>(H);
   const char* pv = static_cast<const char*>(V);
-  const size_t es = cfg->real_symmetric ? 8 : 16;
+  const size_t es = solve_elem_bytes(*cfg);
   const size_t hb = (static_cast<size_t>(cfg->n - 1) * ldh + cfg->n) * es;
   const size_t vb = (static_cast<size_t>(nb - 1) * ldv + cfg->n) * es;
   if (ph < pv + vb && pv < ph + hb) return set_error(ctx, CHASE_EINVAL, "H and V overlap");
   if ((rc = hip_ok(ctx))) return rc;
-  Solver s(ctx, *cfg, batcher);
+  if (cfg->precision == CHASE_FP32) {  // products never batched: the batcher groups FP64 work
+    Solver<float> s(ctx, *cfg, nullptr);
+    return s.run(H, ldh, V, ldv, ritzv, resid, stats);
+  }
+  Solver<double> s(ctx, *cfg, batcher);
   return s.run(H, ldh, V, ldv, ritzv, resid, stats);
+}
+
+hipError_t launch_start_block(void* V, const chase_config& c, uint64_t seed, hipStream_t s) {
+  const int64_t nb = c.nev + c.nex;
+  if (c.precision == CHASE_FP32)
+    return launch_gaussian(static_cast<float*>(V), c.n, c.n, nb, seed, s, solve_width(c));
+  return launch_gaussian(static_cast<double*>(V), c.n, c.n, nb, seed, s, solve_width(c));
 }
 
 int hip_ok(chase_ctx* ctx) {
@@ -814,7 +883,7 @@ int hip_ok(chase_ctx* ctx) {
 struct chase_seq {
   chase_ctx* ctx = nullptr;
   chase_config cfg{};
-  double* V = nullptr;  // n x (nev + nex), ld n, device resident between problems
+  void* V = nullptr;  // n x (nev + nex), ld n, device resident between problems
   std::vector<double> ritzv;
   int64_t solved = 0;
 };
@@ -828,8 +897,8 @@ size_t chase_workspace_bytes(const chase_config* cfg) {
   const int64_t nb = cfg->nev + cfg->nex;
   const int64_t nv = cfg->approx ? 1 : 1 + std::max<int64_t>(cfg->num_lanczos, 1);
   const int64_t k = std::min<int64_t>(std::max(cfg->lanczos_iter, 1), cfg->n);
-  return make_layout(cfg->n, nb, nv, k, cfg->precision == CHASE_MIXED,
-                     cfg->real_symmetric ? 1 : 2).total;
+  return make_layout(cfg->n, nb, nv, k, cfg->precision == CHASE_MIXED, solve_width(*cfg),
+                     solve_scalar_bytes(*cfg)).total;
 }
 
 int chase_solve(chase_ctx* ctx, const chase_config* cfg, const void* H, int64_t ldh, void* V,
@@ -847,14 +916,13 @@ int chase_seq_create(chase_ctx* ctx, const chase_config* cfg, chase_seq** out) {
   s->ctx = ctx;
   s->cfg = *cfg;
   const int64_t nb = cfg->nev + cfg->nex;
-  const int w = cfg->real_symmetric ? 1 : 2;
-  if (hipMalloc(&s->V, static_cast<size_t>(cfg->n) * nb * 8 * w) != hipSuccess) {
+  if (hipMalloc(&s->V, static_cast<size_t>(cfg->n) * nb * solve_elem_bytes(*cfg)) != hipSuccess) {
     (void)hipGetLastError();
     delete s;
     return set_error(ctx, CHASE_ENOMEM, "sequence state allocation failed");
   }
   // start block of problem 1: counter-based Gaussian from the seed
-  hipError_t e = launch_gaussian(s->V, cfg->n, cfg->n, nb, cfg->seed ^ 0x5eedULL, ctx->stream, w);
+  hipError_t e = launch_start_block(s->V, *cfg, cfg->seed ^ 0x5eedULL, ctx->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
   if (e != hipSuccess) {
     (void)hipFree(s->V);

@@ -92,6 +92,32 @@ def test_workspace_bytes_is_pure_host():
     assert 3 * 10000 * 600 * 8 <= br < 0.6 * b
 
 
+def test_config_init_fp32_table1_single_precision():
+    # Table 1: the values in parentheses are the single-precision defaults
+    from paper_1805_10121_amd import capi
+
+    c = capi.config_fp32(1000, 40, 10)
+    d = capi.config(1000, 40, 10)
+    assert c.precision == capi.CHASE_FP32
+    assert (c.tol, c.deg_max, c.deg, c.lanczos_iter) == (1e-5, 18, 10, 12)
+    assert (c.max_iter, c.deg_extra, c.num_lanczos, c.optim, c.approx) == (25, 2, 4, 0, 0)
+    for f in ("switch_resid", "deg_max_fp32", "resid_relative", "intersperse", "dos_sigma",
+              "seed", "have_mu", "verbose", "real_symmetric"):
+        assert getattr(c, f) == getattr(d, f), f
+    capi.lib().chase_config_init_fp32(None, 1, 1, 0)  # NULL is ignored
+
+
+def test_workspace_bytes_fp32_half_of_fp64():
+    from paper_1805_10121_amd import capi
+
+    for real in (0, 1):
+        c64 = capi.config(5000, 200, 40, lanczos_iter=12, real_symmetric=real)
+        c32 = capi.config_fp32(5000, 200, 40, real_symmetric=real)
+        b64 = capi.lib().chase_workspace_bytes(ctypes.byref(c64))
+        b32 = capi.lib().chase_workspace_bytes(ctypes.byref(c32))
+        assert 0.45 * b64 <= b32 <= 0.55 * b64
+
+
 def test_create_without_gpu_fails_cleanly():
     import torch
     from paper_1805_10121_amd import capi

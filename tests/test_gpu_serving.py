@@ -157,3 +157,52 @@ def test_real_sequence_in_server_matches_direct():
         assert np.array_equal(served[k], direct[k])
     Yn = Y[:, :nev]
     assert np.linalg.norm(Yn.T @ Yn - np.eye(nev)) <= 1e-12 * nev ** 0.5
+
+
+def test_fp32_sequence_in_server_matches_direct():
+    # A single-precision (complex64) sequence served beside FP64 ones gives bitwise the Ritz
+    # values of the same sequence solved directly; switching its precision is refused.
+    import torch
+    from paper_1805_10121_amd import capi
+
+    n, nev, nex = 400, 16, 6
+    seqs = _sequences()
+    g = wl.rng(23)
+    lam = wl.spectrum_uniform(n, g)
+    Hs = wl.sequence(n, lam, 3, 1e-3, 523)
+    cfg = capi.config_fp32(n, nev, nex, optim=1, seed=33)
+    dev = [capi.to_device(H).to(torch.complex64) for H in Hs]
+    torch.cuda.synchronize()
+    ctx = capi.Context(0)
+    seq = capi.Sequence(ctx, cfg)
+    direct = []
+    for dH in dev:
+        r, s = np.zeros(nev + nex), np.zeros(nev + nex)
+        seq.chase_seq_solve(dH, n, r, s)
+        direct.append(r.copy())
+    seq.close()
+    ctx.close()
+    cplx = {sid: [capi.to_device(H) for H in seqs[sid][3]] for sid in (11, 13)}
+    torch.cuda.synchronize()
+    srv = capi.Server(0, mem_budget_bytes=8 << 30, workers=4)
+    tickets = []
+    for k in range(3):
+        tickets.append(("fp32", k, srv.chase_server_submit(98, cfg, dev[k], n)))
+        for sid in (11, 13):
+            cn, cnev, cnex, _ = seqs[sid]
+            ccfg = capi.config(cn, cnev, cnex, optim=1, seed=77 + sid)
+            tickets.append((sid, k, srv.chase_server_submit(sid, ccfg, cplx[sid][k], cn)))
+    # the sequence's state is complex64: a complex128 request for it is refused
+    with pytest.raises(capi.ChaseError):
+        srv.chase_server_submit(98, capi.config(n, nev, nex, optim=1), cplx[13][0], n)
+    served = {}
+    for sid, k, t in tickets:
+        rc, ritzv, resid, st, lat = srv.chase_server_poll(t, wait=True)
+        assert rc == 0
+        if sid == "fp32":
+            served[k] = ritzv.copy()
+            ev = np.linalg.eigvalsh(Hs[k])
+            assert np.max(np.abs(ritzv[:nev] - ev[:nev])) <= 2e-5 * np.max(np.abs(ev))
+    srv.close()
+    for k in range(3):
+        assert np.array_equal(served[k], direct[k])
