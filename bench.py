@@ -568,7 +568,7 @@ def main():
         out["solve"] = {
             "status": rc, "time_s": round(t_solve, 4), "solves_per_s": round(1.0 / t_solve, 4),
             "first_solve_in_process_s": round(times[0], 4),
-            "iterations": st.iterations, "matvecs": st.matvecs,
+            "iterations": st.iterations, "matvecs": st.matvecs, "qr_fallbacks": st.qr_fallbacks,
             "filter_tflops": round(st.filter_flops / (st.filter_ms * 1e-3) / 1e12, 3),
             "filter_share": round(st.filter_ms / st.total_ms, 3),
             "phase_ms": {"lanczos": round(st.lanczos_ms, 1), "filter": round(st.filter_ms, 1),
@@ -580,6 +580,35 @@ def main():
         }
         log(f"bench: solve {t_solve:.3f} s, {st.iterations} iterations")
         del dV0
+        # the same problem solved wholly in single precision (complex64 H and block) with
+        # Table 1's single-precision defaults (tol 1e-5, deg 10, deg_max 18, k 12)
+        h32 = torch.empty((n, n), dtype=torch.complex64, device="cuda")
+        ctx.chase_convert_c128_to_c64(dH, n, h32, n, n, n)
+        cfg32 = capi.config_fp32(n, cfg["nev"], cfg["nex"], optim=1, seed=2600)
+        times32 = []
+        for _ in range(2):
+            dV0 = capi.to_device(V).to(torch.complex64)
+            ritzv, resid = np.zeros(nb), np.zeros(nb)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rc32, st32 = ctx.chase_solve(cfg32, h32, n, dV0, n, ritzv, resid)
+            times32.append(time.perf_counter() - t0)
+        out["solve_fp32"] = {
+            "status": rc32, "time_s": round(times32[1], 4),
+            "first_solve_in_process_s": round(times32[0], 4), "tol": cfg32.tol,
+            "iterations": st32.iterations, "matvecs": st32.matvecs,
+            "qr_fallbacks": st32.qr_fallbacks,
+            "filter_tflops": round(st32.filter_flops / (st32.filter_ms * 1e-3) / 1e12, 3),
+            "phase_ms": {"lanczos": round(st32.lanczos_ms, 1),
+                         "filter": round(st32.filter_ms, 1),
+                         "orthogonalize": round(st32.ortho_ms, 1),
+                         "rayleigh_ritz": round(st32.rr_ms, 1),
+                         "residuals": round(st32.resid_ms, 1), "total": round(st32.total_ms, 1)},
+            "max_eig_error_over_normH": float(np.max(np.abs(ritzv[:cfg["nev"]] - lam[:cfg["nev"]])) / normH),
+            "max_resid_over_normH": float(np.max(resid[:cfg["nev"]]) / normH),
+            "workload": "the solve above in complex64 with Table 1's single-precision defaults"}
+        log(f"bench: fp32 solve {times32[1]:.3f} s, {st32.iterations} iterations")
+        del dV0, h32
 
     if not args.no_n20000:
         # the same filter at the order-20000 shape (1200 columns, degrees 2..36)

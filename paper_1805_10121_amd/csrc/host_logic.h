@@ -65,6 +65,23 @@ constexpr int64_t xcd_order(int64_t p, int64_t P) {
   return (P % 8 == 0) ? (p % 8) * (P / 8) + p / 8 : p;
 }
 
+// K-slices of a Gram product A^H B (m1 x m2 result, k rows) computed as a batch of slice
+// products plus a sum: enough slices that about 512 output tiles of 64 x 64 are in flight
+// (tall-skinny shapes leave most of the GPU idle otherwise), at most 16, each at least 256 rows.
+constexpr int64_t gram_slices(int64_t m1, int64_t m2, int64_t k) {
+  const int64_t tiles = ((m1 + 63) / 64) * ((m2 + 63) / 64);
+  int64_t p = tiles > 0 ? (512 + tiles - 1) / tiles : 1;
+  if (p > 16) p = 16;
+  if (p > k / 256) p = k / 256;
+  return p < 1 ? 1 : p;
+}
+// Elements of the slice buffer reserved for Gram products of at most nb x nb; a product whose
+// slices would not fit uses fewer slices (never fewer than 1: the buffer holds nb * nb).
+constexpr int64_t gram_buffer_elems(int64_t nb) {
+  const int64_t a = 16 * nb * nb, b = (int64_t{1} << 21) + nb * nb;
+  return a < b ? a : b;
+}
+
 // One product of Algorithm 4: OUT[:, col0:col0+ncols] <- alpha H X + gamma X + beta OUT where
 // (X, OUT) = (V, W) when from_v, else (W, V).
 struct FilterProduct {

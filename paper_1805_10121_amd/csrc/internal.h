@@ -95,6 +95,8 @@ hipError_t launch_convert_f32_to_f64(const float* src, int64_t lds, double* dst,
                            const int* perm, int64_t cols, hipStream_t s, int w = 2);            \
   hipError_t launch_herm_sym(R* G, int64_t ld, int64_t m, hipStream_t s, int w = 2);            \
   hipError_t launch_add_diag(R* G, int64_t ld, int64_t m, double v, hipStream_t s, int w = 2);  \
+  hipError_t launch_sum_slices(const R* P, int64_t m1, int64_t m2, int64_t stride, int p, R* G,  \
+                              int64_t ldg, hipStream_t s, int w = 2);                           \
   hipError_t launch_gaussian(R* X, int64_t n, int64_t ld, int64_t cols, uint64_t seed,          \
                              hipStream_t s, int w = 2);
 CHASE_LOOP_DECL(double)

@@ -157,6 +157,21 @@ __global__ void add_diag_kernel(R* __restrict__ G, int64_t ld, int64_t m, double
   if (i < m) G[W * (i + i * ld)] += static_cast<R>(s);
 }
 
+// G = sum over s of the slices P_s (m1 x m2 elements, ld m1, stride elements apart), summed in
+// FP64 in slice order; one thread per scalar of G.
+template <typename R, int W>
+__global__ void sum_slices_kernel(const R* __restrict__ P, int64_t m1, int64_t m2, int64_t stride,
+                                  int p, R* __restrict__ G, int64_t ldg) {
+  const int64_t rows = W * m1, total = rows * m2;
+  for (int64_t t = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; t < total;
+       t += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int64_t r = t % rows, c = t / rows;
+    double acc = 0.0;
+    for (int q = 0; q < p; ++q) acc += static_cast<double>(P[W * stride * q + r + c * rows]);
+    G[r + c * W * ldg] = static_cast<R>(acc);
+  }
+}
+
 // SplitMix64 (Steele, Lea, Flood 2014) applied to a counter, then Box-Muller.
 __device__ __forceinline__ uint64_t splitmix64(uint64_t z) {
   z += 0x9E3779B97F4A7C15ULL;
@@ -239,6 +254,14 @@ hipError_t add_diag_t(R* G, int64_t ld, int64_t m, double v, hipStream_t s, int 
   return hipGetLastError();
 }
 template <typename R>
+hipError_t sum_slices_t(const R* P, int64_t m1, int64_t m2, int64_t stride, int p, R* G,
+                        int64_t ldg, hipStream_t s, int w) {
+  if (m1 <= 0 || m2 <= 0) return hipSuccess;
+  hipLaunchKernelGGL(CHASE_BY_W(w, R, sum_slices_kernel), dim3(grid_for(w * m1 * m2)), dim3(256),
+                     0, s, P, m1, m2, stride, p, G, ldg);
+  return hipGetLastError();
+}
+template <typename R>
 hipError_t gaussian_t(R* X, int64_t n, int64_t ld, int64_t cols, uint64_t seed, hipStream_t s,
                       int w) {
   if (cols <= 0 || n <= 0) return hipSuccess;
@@ -271,6 +294,10 @@ hipError_t gaussian_t(R* X, int64_t n, int64_t ld, int64_t cols, uint64_t seed, 
   }                                                                                             \
   hipError_t launch_add_diag(R* G, int64_t ld, int64_t m, double v, hipStream_t s, int w) {     \
     return add_diag_t<R>(G, ld, m, v, s, w);                                                    \
+  }                                                                                             \
+  hipError_t launch_sum_slices(const R* P, int64_t m1, int64_t m2, int64_t stride, int p, R* G,  \
+                              int64_t ldg, hipStream_t s, int w) {                              \
+    return sum_slices_t<R>(P, m1, m2, stride, p, G, ldg, s, w);                                 \
   }                                                                                             \
   hipError_t launch_gaussian(R* X, int64_t n, int64_t ld, int64_t cols, uint64_t seed,          \
                              hipStream_t s, int w) {                                            \

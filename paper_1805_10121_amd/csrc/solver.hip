@@ -5,7 +5,8 @@
 //   ORTHOGONALIZE     Alg. 1 lines 5-6: block Gram-Schmidt against the locked vectors, column
 //                     scaling, shifted Cholesky QR + two Cholesky QR passes; Householder QR of
 //                     [Y V] (rocSOLVER) if a Cholesky factorisation breaks down
-//   RAYLEIGH-RITZ     Alg. 2: H Q with the filter's product kernel, G = Q^H (H Q) (rocBLAS),
+//   RAYLEIGH-RITZ     Alg. 2: H Q with the filter's product kernel, G = Q^H (H Q) (rocBLAS, K
+//                     split into slices so that the tall-skinny product fills the GPU),
 //                     TSOLVE = rocSOLVER zheevd, V = Q Z, H V = (H Q) Z
 //   residuals         Alg. 1 line 8, one fused kernel, then Ritz values and residual norms go to
 //                     the host (the only per-iteration device-to-host transfer of results)
@@ -13,8 +14,9 @@
 //                     (sort); the new column order is applied on the device by one gather.
 // LANCZOS (Alg. 6) runs first: the b_sup run and the n_vec DoS runs are independent, so they
 // advance together as one block product per step.
-// The same loop serves complex Hermitian H (complex128 data, Z routines) and real symmetric H
-// (float64 data, D routines, real product kernel): w_ = values per element (2 or 1).
+// The same loop serves complex Hermitian H (Z routines) and real symmetric H (D routines, real
+// product kernel), w_ = values per element (2 or 1), in double precision (R = double) or wholly in
+// single precision (R = float: complex64 / float32 data, C and S routines).
 
 #include <algorithm>
 #include <cmath>
@@ -33,7 +35,8 @@ namespace chase {
 namespace {
 
 struct Layout {
-  size_t V, W, AQ, X, G, T, lam, res, evE, perm, info, U, Wl, lal, lbe, zero, Z, tau, H32, V32, W32;
+  size_t V, W, AQ, X, G, T, P, lam, res, evE, perm, info, U, Wl, lal, lbe, zero, Z, tau, H32, V32,
+      W32;
   size_t total;
 };
 
@@ -55,6 +58,7 @@ Layout make_layout(int64_t n, int64_t nb, int64_t nv, int64_t k, bool mixed, int
   L.X = take(blk);
   L.G = take(static_cast<size_t>(nb) * nb * es);
   L.T = take(static_cast<size_t>(nb) * nb * es);
+  L.P = take(static_cast<size_t>(gram_buffer_elems(nb)) * es);  // K-slices of Gram products
   L.lam = take(nb * 8);
   L.res = take(nb * 8);
   L.evE = take(nb * 8);
@@ -163,6 +167,63 @@ class Solver {
                 "zgemm");
   }
   // OUT <- alpha H X + gamma X + beta OUT with the product kernel of the element type.
+  // G (ld ldg) <- A^H B for n x m1 A and n x m2 B (ld n): a batch of K-slice products into the
+  // slice buffer, then their sum (one GEMM when the result alone fills the GPU).
+  int gram(int64_t m1, int64_t m2, const R* A, const R* B, R* G, int64_t ldg) {
+    int64_t p = gram_slices(m1, m2, n_);
+    const int64_t cap = gram_buffer_elems(nb_);
+    if (p * m1 * m2 > cap) p = cap / (m1 * m2);
+    const auto ct = rocblas_operation_conjugate_transpose, nn = rocblas_operation_none;
+    if (p <= 1) return gemm(ct, nn, m1, m2, n_, 1.0, A, n_, B, n_, 0.0, G, ldg);
+    const int64_t kc = n_ / p, rem = n_ - p * kc;
+    R* P = at<R>(L_.P);
+    int rc = gemm_sb(m1, m2, kc, A, B, P, p);
+    if (rc) return rc;
+    if (rem > 0 &&
+        (rc = gemm(ct, nn, m1, m2, rem, 1.0, A + w_ * p * kc, n_, B + w_ * p * kc, n_, 1.0, P, m1)))
+      return rc;
+    return hip(launch_sum_slices(P, m1, m2, m1 * m2, static_cast<int>(p), G, ldg, s_, w_),
+               "sum slices");
+  }
+  // Slice q of P (m1 x m2, ld m1) <- A[q kc : (q+1) kc, :]^H B[q kc : (q+1) kc, :], q < p.
+  int gemm_sb(int64_t m1, int64_t m2, int64_t kc, const R* A, const R* B, R* P, int64_t p) {
+    const rocblas_int im = static_cast<rocblas_int>(m1), in = static_cast<rocblas_int>(m2),
+                      ik = static_cast<rocblas_int>(kc), ld = static_cast<rocblas_int>(n_),
+                      bc = static_cast<rocblas_int>(p);
+    const rocblas_stride sk = kc, sp = m1 * m2;
+    const auto nn = rocblas_operation_none;
+    if constexpr (kF64) {
+      if (real_) {
+        const double one = 1.0, zero = 0.0;
+        return blas(rocblas_dgemm_strided_batched(ctx_->blas, rocblas_operation_transpose, nn, im,
+                                                  in, ik, &one, A, ld, sk, B, ld, sk, &zero, P, im,
+                                                  sp, bc),
+                    "dgemm batched");
+      }
+      const rocblas_double_complex one(1.0, 0.0), zero(0.0, 0.0);
+      return blas(rocblas_zgemm_strided_batched(
+                      ctx_->blas, rocblas_operation_conjugate_transpose, nn, im, in, ik, &one,
+                      reinterpret_cast<const rocblas_double_complex*>(A), ld, sk,
+                      reinterpret_cast<const rocblas_double_complex*>(B), ld, sk, &zero,
+                      reinterpret_cast<rocblas_double_complex*>(P), im, sp, bc),
+                  "zgemm batched");
+    } else {
+      if (real_) {
+        const float one = 1.f, zero = 0.f;
+        return blas(rocblas_sgemm_strided_batched(ctx_->blas, rocblas_operation_transpose, nn, im,
+                                                  in, ik, &one, A, ld, sk, B, ld, sk, &zero, P, im,
+                                                  sp, bc),
+                    "sgemm batched");
+      }
+      const rocblas_float_complex one(1.f, 0.f), zero(0.f, 0.f);
+      return blas(rocblas_cgemm_strided_batched(
+                      ctx_->blas, rocblas_operation_conjugate_transpose, nn, im, in, ik, &one,
+                      reinterpret_cast<const rocblas_float_complex*>(A), ld, sk,
+                      reinterpret_cast<const rocblas_float_complex*>(B), ld, sk, &zero,
+                      reinterpret_cast<rocblas_float_complex*>(P), im, sp, bc),
+                  "cgemm batched");
+    }
+  }
   hipError_t product(const R* H, int64_t ldh, const R* X, int64_t ldx, R* OUT, int64_t ldo,
                      int64_t ncols, double alpha, double beta, double gamma) {
     const R a = static_cast<R>(alpha), b = static_cast<R>(beta), g = static_cast<R>(gamma);
@@ -269,8 +330,7 @@ int Solver<R>::cgs(int64_t nlock, int64_t nact) {
   R* Y = at<R>(L_.V);
   R* A = col(L_.V, nlock);
   R* T = at<R>(L_.T);
-  int rc = gemm(rocblas_operation_conjugate_transpose, rocblas_operation_none, nlock, nact, n_, 1.0,
-                 Y, n_, A, n_, 0.0, T, nb_);
+  int rc = gram(nlock, nact, Y, A, T, nb_);
   if (rc) return rc;
   return gemm(rocblas_operation_none, rocblas_operation_none, n_, nact, nlock, -1.0, Y, n_, T, nb_,
                1.0, A, n_);
@@ -283,9 +343,8 @@ template <typename R>
 int Solver<R>::cholqr(int64_t nact, bool shift, int slot) {
   R* A = col(L_.V, n_ == 0 ? 0 : (nb_ - nact));
   R* G = at<R>(L_.G);
-  // Gram matrix by GEMM (both triangles; rocBLAS's GEMM is faster than its HERK at these shapes)
-  int rc = gemm(rocblas_operation_conjugate_transpose, rocblas_operation_none, nact, nact, n_, 1.0,
-                A, n_, A, n_, 0.0, G, nb_);
+  // Gram matrix by K-sliced GEMM (both triangles; faster than HERK at these shapes)
+  int rc = gram(nact, nact, A, A, G, nb_);
   if (rc) return rc;
   if (shift) {
     const double s = 11.0 * (static_cast<double>(n_) * nact + static_cast<double>(nact) * (nact + 1)) *
@@ -607,9 +666,7 @@ int Solver<R>::run(const void* Hv, int64_t ldh, void* Vuser, int64_t ldv, double
     R* G = at<R>(L_.G);
     if ((rc = hip(product(H, ldh, Q, n_, AQ, n_, nact, 1.0, 0.0, 0.0), "H Q"))) return rc;
     st_.matvecs += nact;
-    if ((rc = gemm(rocblas_operation_conjugate_transpose, rocblas_operation_none, nact, nact, n_,
-                    1.0, Q, n_, AQ, n_, 0.0, G, nb_)))
-      return rc;
+    if ((rc = gram(nact, nact, Q, AQ, G, nb_))) return rc;
     if ((rc = hip(launch_herm_sym(G, nb_, nact, s_, w_), "sym"))) return rc;
     {
       const rocblas_int ia = static_cast<rocblas_int>(nact), ig = static_cast<rocblas_int>(nb_);

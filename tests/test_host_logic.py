@@ -215,3 +215,44 @@ def test_stream_k_schedule_exhaustive():
     r = subprocess.run([out], capture_output=True, text=True)
     assert r.returncode == 0, f"schedule check {r.returncode}"
     assert int(r.stdout) > 1000
+
+
+GRAM_DRIVER = r"""
+#include <cstdio>
+#include "host_logic.h"
+using namespace chase;
+// The solver's use of the K-sliced Gram product: slices in [1, 16], each at least 256 rows when
+// there is more than one, and -- after the solver's cap -- all slices inside the reserved buffer
+// for every result shape up to nb x nb (cgs: nlock x nact with nlock + nact = nb).
+int main() {
+  long checked = 0;
+  for (long nb : {1L, 5L, 64L, 70L, 300L, 600L, 1200L, 2400L, 4000L})
+    for (long n : {nb, 2 * nb, 1000L, 10000L, 60000L}) {
+      if (n < nb) continue;
+      const long cap = gram_buffer_elems(nb);
+      if (cap < nb * nb) return 1;
+      for (long m1 = 1; m1 <= nb; m1 += (nb > 64 ? 7 : 1))
+        for (long m2 : {nb - m1 > 0 ? nb - m1 : 1L, m1}) {
+          long p = gram_slices(m1, m2, n);
+          if (p < 1 || p > 16) return 2;
+          if (p > 1 && p * 256 > n) return 3;
+          if (p * m1 * m2 > cap) p = cap / (m1 * m2);
+          if (p < 1 || p * m1 * m2 > cap) return 4;
+          ++checked;
+        }
+    }
+  printf("%ld\n", checked);
+  return 0;
+}
+"""
+
+
+def test_gram_slices_fit_the_buffer():
+    d = tempfile.mkdtemp()
+    src = os.path.join(d, "gram.cpp")
+    out = os.path.join(d, "gram")
+    open(src, "w").write(GRAM_DRIVER)
+    subprocess.run(["g++", "-std=c++17", "-O2", "-I", CSRC, src, "-o", out], check=True)
+    r = subprocess.run([out], capture_output=True, text=True)
+    assert r.returncode == 0, f"gram slice check {r.returncode}"
+    assert int(r.stdout) > 1000
