@@ -898,19 +898,52 @@ __global__ __launch_bounds__(kThreads) void hemm_fixup_kernel(
   tile_coords(t, (ncols + C::BNC - 1) / C::BNC, &tile_m, &tile_n);
   const int i0 = tile_m * C::BMC, j0 = tile_n * C::BNC;
   constexpr int TE = C::BMC * C::BNC;
-  for (int e = threadIdx.x; e < TE; e += kThreads) {
-    const int r = e % C::BMC, c = e / C::BMC;
-    T hre = T(0), him = T(0);
-    for (int64_t pp = pf; pp <= pl; ++pp) {
+  constexpr int EPT = (TE + kThreads - 1) / kThreads;  // elements per thread
+  constexpr int EW = elem_width<C>();
+  // Contributors outer, elements inner.  The slot offsets of up to kThreads contributors at a
+  // time (integer divisions) are found in parallel, one per thread, into LDS; the sum then runs
+  // over them with several contributors' loads in flight.  Every element still adds its slots
+  // in increasing pp (empty ranges contribute nothing).
+  __shared__ int64_t soff[kThreads];
+  T hre[EPT], him[EPT];
+#pragma unroll
+  for (int q = 0; q < EPT; ++q) hre[q] = T(0), him[q] = T(0);
+  for (int64_t c0 = pf; c0 <= pl; c0 += kThreads) {
+    const int cnt = static_cast<int>(pl - c0 + 1 < kThreads ? pl - c0 + 1 : kThreads);
+    __syncthreads();  // the previous chunk's offsets are consumed
+    if (static_cast<int>(threadIdx.x) < cnt) {
+      const int64_t pp = c0 + threadIdx.x;
       const int64_t a = sk_start(pp, units, P), b = sk_start(pp + 1, units, P);
-      if (a >= b) continue;  // empty range
-      constexpr int EW = elem_width<C>();
-      const T* src = partial + EW * (pp * 2 + sk_slot(pp, tr, units, P, nk)) * TE;
-      hre += src[EW * e];
-      if constexpr (EW == 2) him += src[EW * e + 1];
+      soff[threadIdx.x] = a >= b ? int64_t{-1} : EW * (pp * 2 + sk_slot(pp, tr, units, P, nk)) * TE;
     }
+    __syncthreads();
+    for (int j = 0; j < cnt; ++j) {
+      const int64_t o = soff[j];
+      if (o < 0) continue;
+      const T* src = partial + o;
+      // all of this contributor's loads first (distinct registers, one wait), then the sums
+      T vre[EPT], vim[EPT];
+#pragma unroll
+      for (int q = 0; q < EPT; ++q) {
+        const int e = threadIdx.x + q * kThreads;
+        const bool in = TE % kThreads == 0 || e < TE;
+        vre[q] = in ? src[EW * e] : T(0);
+        if constexpr (EW == 2) vim[q] = in ? src[EW * e + 1] : T(0);
+      }
+#pragma unroll
+      for (int q = 0; q < EPT; ++q) {
+        hre[q] += vre[q];
+        if constexpr (EW == 2) him[q] += vim[q];
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < EPT; ++q) {
+    const int e = threadIdx.x + q * kThreads;
+    if (TE % kThreads != 0 && e >= TE) continue;
+    const int r = e % C::BMC, c = e / C::BMC;
     if (i0 + r < n && j0 + c < ncols)
-      store_result<T, C>(X, ldx, OUT, ldo, i0 + r, j0 + c, hre, him, alpha, beta, gamma);
+      store_result<T, C>(X, ldx, OUT, ldo, i0 + r, j0 + c, hre[q], him[q], alpha, beta, gamma);
   }
 }
 
