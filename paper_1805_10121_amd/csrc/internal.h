@@ -101,6 +101,9 @@ hipError_t launch_convert_f32_to_f64(const float* src, int64_t lds, double* dst,
                              hipStream_t s, int w = 2);
 CHASE_LOOP_DECL(double)
 CHASE_LOOP_DECL(float)
+// Interleaved complex64 H (ld lds) -> planar complex64 (Re plane, Im plane at dst + ldd * n).
+hipError_t launch_split_planes_c64(const float* src, int64_t lds, float* dst, int64_t ldd,
+                                   int64_t n, hipStream_t s);
 #undef CHASE_LOOP_DECL
 
 // ----------------------------------------------------------------------------- filter driver

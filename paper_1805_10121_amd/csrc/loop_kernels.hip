@@ -172,6 +172,20 @@ __global__ void sum_slices_kernel(const R* __restrict__ P, int64_t m1, int64_t m
   }
 }
 
+// Interleaved complex64 n x n (ld lds) -> planar: Re plane at dst, Im plane at dst + ldd * n.
+__global__ void split_planes_kernel(const float* __restrict__ src, int64_t lds,
+                                    float* __restrict__ dst, int64_t ldd, int64_t n) {
+  const int64_t total = n * n;
+  float* im = dst + ldd * n;
+  for (int64_t t = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; t < total;
+       t += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int64_t r = t % n, c = t / n;
+    const float2 v = *reinterpret_cast<const float2*>(src + 2 * (r + c * lds));
+    dst[r + c * ldd] = v.x;
+    im[r + c * ldd] = v.y;
+  }
+}
+
 // SplitMix64 (Steele, Lea, Flood 2014) applied to a counter, then Box-Muller.
 __device__ __forceinline__ uint64_t splitmix64(uint64_t z) {
   z += 0x9E3779B97F4A7C15ULL;
@@ -271,6 +285,14 @@ hipError_t gaussian_t(R* X, int64_t n, int64_t ld, int64_t cols, uint64_t seed, 
 }
 
 }  // namespace
+
+hipError_t launch_split_planes_c64(const float* src, int64_t lds, float* dst, int64_t ldd,
+                                   int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(split_planes_kernel, dim3(grid_for(n * n)), dim3(256), 0, s, src, lds, dst,
+                     ldd, n);
+  return hipGetLastError();
+}
 
 #define CHASE_LOOP_API(R)                                                                       \
   hipError_t launch_lanczos_step(const R* U, const R* Up, R* W, R* Un, int64_t n, int64_t ld,   \

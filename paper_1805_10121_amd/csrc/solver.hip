@@ -71,8 +71,10 @@ Layout make_layout(int64_t n, int64_t nb, int64_t nv, int64_t k, bool mixed, int
   L.zero = take(static_cast<size_t>(nv) * 8);
   L.Z = take(static_cast<size_t>(k) * nb * es);
   L.tau = take(nb * 16);
-  if (mixed) {  // FP32 copies: planar complex64 or real float32 H, and two blocks
-    L.H32 = take(static_cast<size_t>(n) * n * 4 * w);
+  // FP32 copy of H: planar complex64 (mixed complex, and single-precision complex for the 3M
+  // product) or real float32 (mixed real); mixed mode also holds two FP32 blocks
+  if (mixed || (esz == 4 && w == 2)) L.H32 = take(static_cast<size_t>(n) * n * 4 * w);
+  if (mixed) {
     L.V32 = take(static_cast<size_t>(n) * nb * 4 * w);
     L.W32 = take(static_cast<size_t>(n) * nb * 4 * w);
   }
@@ -467,12 +469,16 @@ int Solver<R>::orthogonalize(int64_t nlock, int64_t nact) {
 template <typename R>
 int Solver<R>::filter(const R* H, int64_t ldh, int64_t nlock, int64_t nact,
                       const std::vector<int>& m, const std::vector<int>& prec) {
-  if constexpr (!kF64) {  // all-FP32 solve: every column in the data's own precision
+  if constexpr (!kF64) {  // single-precision solve: 3M on the planar copy of H, or real FP32
     int64_t mv = 0;
-    const int rc = hip(run_filter<float>(H, ldh, n_, col(L_.V, nlock), col(L_.W, nlock), n_, nact,
-                                         m.data(), b_sup_, mu_1_, mu_b_, ctx_->prod, s_, &mv,
-                                         real_ ? 3 : 1),
-                       "filter fp32");
+    const int rc =
+        real_ ? hip(run_filter<float>(H, ldh, n_, col(L_.V, nlock), col(L_.W, nlock), n_, nact,
+                                      m.data(), b_sup_, mu_1_, mu_b_, ctx_->prod, s_, &mv, 3),
+                    "filter real fp32")
+              : hip(run_filter<float>(at<float>(L_.H32), n_, n_, col(L_.V, nlock),
+                                      col(L_.W, nlock), n_, nact, m.data(), b_sup_, mu_1_, mu_b_,
+                                      ctx_->prod, s_, &mv, 2),
+                    "filter fp32 3M");
     if (rc) return rc;
     st_.filter_matvecs += mv;
     return CHASE_OK;
@@ -596,6 +602,11 @@ int Solver<R>::run(const void* Hv, int64_t ldh, void* Vuser, int64_t ldv, double
                                  hipMemcpyDeviceToDevice, s_),
                 "copy V")))
     return rc;
+  if constexpr (!kF64) {
+    if (!real_ &&
+        (rc = hip(launch_split_planes_c64(H, ldh, at<float>(L_.H32), n_, n_, s_), "planar H")))
+      return rc;
+  }
   if constexpr (kF64) {
     if (mixed && real_ &&
         (rc = hip(launch_convert_f64_to_f32(H, ldh, at<float>(L_.H32), n_, n_, n_, s_),
