@@ -160,13 +160,14 @@ class Solver {
                                 reinterpret_cast<const rocblas_float_complex*>(B), ib, &be,
                                 reinterpret_cast<rocblas_float_complex*>(C), ic),
                   "cgemm");
+    } else {
+      const rocblas_double_complex al(ar, 0.0), be(br, 0.0);
+      return blas(rocblas_zgemm(ctx_->blas, ta, tb, im, in, ik, &al,
+                                reinterpret_cast<const rocblas_double_complex*>(A), ia,
+                                reinterpret_cast<const rocblas_double_complex*>(B), ib, &be,
+                                reinterpret_cast<rocblas_double_complex*>(C), ic),
+                  "zgemm");
     }
-    const rocblas_double_complex al(ar, 0.0), be(br, 0.0);
-    return blas(rocblas_zgemm(ctx_->blas, ta, tb, im, in, ik, &al,
-                              reinterpret_cast<const rocblas_double_complex*>(A), ia,
-                              reinterpret_cast<const rocblas_double_complex*>(B), ib, &be,
-                              reinterpret_cast<rocblas_double_complex*>(C), ic),
-                "zgemm");
   }
   // OUT <- alpha H X + gamma X + beta OUT with the product kernel of the element type.
   // G (ld ldg) <- A^H B for n x m1 A and n x m2 B (ld n): a batch of K-slice products into the
@@ -240,6 +241,8 @@ class Solver {
   int orthogonalize(int64_t nlock, int64_t nact);
   int filter(const R* H, int64_t ldh, int64_t nlock, int64_t nact,
              const std::vector<int>& m, const std::vector<int>& prec);
+  int filter_mixed(const R* H, int64_t ldh, int64_t nlock, int64_t nact,
+                   const std::vector<int>& m, const std::vector<int>& prec);
 
   double b_sup_ = 0, mu_1_ = 0, mu_b_ = 0, norm_est_ = 0;
 };
@@ -483,6 +486,14 @@ int Solver<R>::filter(const R* H, int64_t ldh, int64_t nlock, int64_t nact,
     st_.filter_matvecs += mv;
     return CHASE_OK;
   } else {
+    return filter_mixed(H, ldh, nlock, nact, m, prec);
+  }
+}
+
+// Double-precision data: the FP32 column group first (mixed mode), then the FP64 group.
+template <typename R>
+int Solver<R>::filter_mixed(const R* H, int64_t ldh, int64_t nlock, int64_t nact,
+                            const std::vector<int>& m, const std::vector<int>& prec) {
   int64_t n32 = 0;
   while (n32 < nact && prec[n32] == 1) ++n32;
   int rc;
@@ -547,7 +558,6 @@ int Solver<R>::filter(const R* H, int64_t ldh, int64_t nlock, int64_t nact,
     st_.filter_matvecs += mv;
   }
   return CHASE_OK;
-  }
 }
 
 template <typename R>
