@@ -117,6 +117,9 @@ def make_sequence_problem(n, lam, k, eps, seed, prev=None, norm=None):
     return prev
 
 
+SEQUENCES = {"n20000": "sequence_n20000", "n60000": "sequence_n60000"}
+
+
 def run_sequence(args):
     """Warm-started sequence (order 20000, nev 1000, nex 200, eps 1e-3 by default): total
     time-to-solution with the plain FP64 filter and with the mixed FP32/FP64 filter."""
@@ -126,13 +129,14 @@ def run_sequence(args):
     from paper_1805_10121_amd import capi
     from paper_1805_10121_amd import workloads as wl
 
-    c = wl.CONFIGS[args.config]
+    name = SEQUENCES[args.sequence]
+    c = wl.WORKLOADS[name]
     n = args.order or c["n"]
     nev = max(1, round(c["nev"] * n / c["n"]))
     nex = max(1, round(c["nex"] * n / c["n"]))
     eps = c["eps"]
     problems = args.problems or c["problems"]
-    lam = wl.spectrum_for(args.config, n=n)
+    lam = wl.spectrum_for(name, n=n)
     norm = float(np.max(np.abs(lam)))
     ctx = capi.Context(0)
     res = {}
@@ -152,7 +156,7 @@ def run_sequence(args):
         H = None
         per = []
         for k in range(problems):
-            H = make_sequence_problem(n, lam, k, eps, 1000 * args.config + 1, prev=H, norm=norm)
+            H = make_sequence_problem(n, lam, k, eps, c["seed"] + 1, prev=H, norm=norm)
             torch.cuda.synchronize()
             ritzv, resid = np.zeros(nev + nex), np.zeros(nev + nex)
             t0 = time.perf_counter()
@@ -205,7 +209,7 @@ class _SeqSource:
         self.sid, self.n, self.eps, self.seed = sid, n, eps, seed
         self.nev = max(1, round(0.05 * n))
         self.nex = max(1, round(0.2 * self.nev))
-        self.lam = wl.spectrum_for(3, n=n, seed=seed)
+        self.lam = wl.spectrum_for("serving", n=n, seed=seed)
         self.norm = float(np.max(np.abs(self.lam)))
         self.prev = None
         self.k = 0
@@ -323,7 +327,7 @@ def run_serving(n_seq=16, problems=8, rates=(0.5, 0.8, 1.0), sizes=(2000, 4000, 
     return out
 
 
-def run_ablation(cfg_id=1, degrees=(8, 12, 16, 20, 24, 28, 32, 36)):
+def run_ablation(name="uniform_n1000", degrees=(8, 12, 16, 20, 24, 28, 32, 36)):
     """Degree-optimisation ablation (the paper's Fig. 1 experiment on a synthetic problem):
     constant degree (optim off) against per-vector degrees (optim on, deg = initial degree),
     reporting filter and total matvecs, iterations and time-to-solution per setting."""
@@ -333,21 +337,22 @@ def run_ablation(cfg_id=1, degrees=(8, 12, 16, 20, 24, 28, 32, 36)):
     from paper_1805_10121_amd import capi
     from paper_1805_10121_amd import workloads as wl
 
-    c = wl.CONFIGS[cfg_id]
+    c = wl.WORKLOADS[name]
+    base = c["seed"]
     n, nev, nex = c["n"], c["nev"], c["nex"]
-    lam = wl.spectrum_for(cfg_id)
+    lam = wl.spectrum_for(name)
     if n <= 2000:
-        dH = capi.to_device(wl.hermitian(n, lam, 1000 * cfg_id + 1))
+        dH = capi.to_device(wl.hermitian(n, lam, base + 1))
     elif n <= 10000:
-        dH = wl.hermitian_torch(n, lam, seed=1000 * cfg_id + 1)
+        dH = wl.hermitian_torch(n, lam, seed=base + 1)
     else:
-        dH = wl.hermitian_torch_fast(n, lam, seed=1000 * cfg_id + 1)
-    V0 = wl.start_block(n, nev + nex, 1000 * cfg_id + 500)
+        dH = wl.hermitian_torch_fast(n, lam, seed=base + 1)
+    V0 = wl.start_block(n, nev + nex, base + 500)
     ctx = capi.Context(0)
     rows = []
     for optim in (0, 1):
         for d in degrees:
-            cfg = capi.config(n, nev, nex, optim=optim, deg=d, seed=1000 * cfg_id + 600)
+            cfg = capi.config(n, nev, nex, optim=optim, deg=d, seed=base + 600)
             dV = capi.to_device(V0)
             ritzv, resid = np.zeros(nev + nex), np.zeros(nev + nex)
             torch.cuda.synchronize()
@@ -361,7 +366,7 @@ def run_ablation(cfg_id=1, degrees=(8, 12, 16, 20, 24, 28, 32, 36)):
                          "time_s": round(dt, 4),
                          "max_eig_error_over_normH": float(
                              np.max(np.abs(ritzv[:nev] - lam[:nev])) / np.max(np.abs(lam)))})
-            log(f"ablation cfg{cfg_id} optim={optim} deg={d}: {rows[-1]}")
+            log(f"ablation {name} optim={optim} deg={d}: {rows[-1]}")
     ctx.close()
     return {"workload": f"degree ablation, problem n={n} nev={nev} nex={nex} (cold start)",
             "rows": rows}
@@ -383,10 +388,13 @@ def main():
                          "a warm-started sequence, plain FP64 against the mixed FP32/FP64 filter")
     ap.add_argument("--problems", type=int, default=None,
                     help="sequence: problems (default: the config's); serving: per sequence (8)")
-    ap.add_argument("--config", type=int, choices=[3, 5], default=3,
-                    help="sequence workload: order-20000 (3) or order-60000 (5) sequence")
-    ap.add_argument("--ablation-configs", type=int, nargs="*", default=[1, 2], choices=[1, 2, 3],
-                    help="ablation workload: which configs to run")
+    ap.add_argument("--sequence", choices=sorted(SEQUENCES), default="n20000",
+                    help="sequence workload: the order-20000 (no gap after nev + nex) or the "
+                         "order-60000 (gap) sequence")
+    ap.add_argument("--ablation-workloads", nargs="*",
+                    default=["uniform_n1000", "clustered_n10000"],
+                    choices=["uniform_n1000", "clustered_n10000", "sequence_n20000"],
+                    help="ablation workload: which problems to run (cold start)")
     ap.add_argument("--modes", nargs="*", default=["fp64", "mixed"], choices=["fp64", "mixed"],
                     help="sequence workload: which filters to run")
     ap.add_argument("--switch-resid", type=float, nargs="*", default=[1e-6],
@@ -402,8 +410,8 @@ def main():
                     help="only run a plain 1 GiB device copy three times (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); multi-GPU sharding of "
-              "the filter is a design note, not part of this build.", file=sys.stderr)
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the library runs the "
+              "filter on a single GPU and has no multi-GPU sharding.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -425,7 +433,7 @@ def main():
         print(json.dumps(run_sequence(args)), flush=True)
         return
     if args.workload == "ablation":
-        out = {f"config{c}": run_ablation(c) for c in args.ablation_configs}
+        out = {w: run_ablation(w) for w in args.ablation_workloads}
         print(json.dumps(out), flush=True)
         return
     if args.workload == "serving":
@@ -433,9 +441,9 @@ def main():
               flush=True)
         return
 
-    cfg = wl.CONFIGS[2]
+    cfg = wl.WORKLOADS["clustered_n10000"]
     n, nb = cfg["n"], cfg["nev"] + cfg["nex"]
-    lam = wl.spectrum_for(2)
+    lam = wl.spectrum_for("clustered_n10000")
     log(f"bench: generating H (n={n}, {args.h_gen}) on the device")
     dH = (wl.hermitian_torch(n, lam, seed=2001) if args.h_gen == "haar"
           else wl.hermitian_torch_fast(n, lam, seed=2001))
@@ -632,7 +640,7 @@ def main():
     if not args.no_n20000:
         # the same filter at the order-20000 shape (1200 columns, degrees 2..36)
         n2, nb2 = 20000, 1200
-        lam2 = wl.spectrum_for(3)
+        lam2 = wl.spectrum_for("sequence_n20000")
         dH2 = wl.hermitian_torch_fast(n2, lam2, seed=3001)
         dV2 = capi.to_device(wl.start_block(n2, nb2, 3500))
         dW2 = torch.empty_like(dV2)

@@ -116,21 +116,30 @@ def sequence(n: int, lam: np.ndarray, n_problems: int, eps: float, seed: int):
 # ----------------------------------------------------------------------------- configs
 # The five synthetic workloads (order n, nev, nex, spectrum).  Seeds: 1000 * id + problem.
 
-CONFIGS = {
-    1: dict(n=1000, nev=50, nex=20, spectrum="uniform", tol=1e-10),
-    2: dict(n=10000, nev=500, nex=100, spectrum="clustered", n_clustered=600, tol=1e-10),
-    3: dict(n=20000, nev=1000, nex=200, spectrum="clustered", n_clustered=600, tol=1e-10,
-            problems=10, eps=1e-3),
-    4: dict(sizes=(2000, 4000, 8000, 16000), sequences=16, problems=8, eps=1e-3, tol=1e-10),
-    5: dict(n=60000, nev=2000, nex=400, spectrum="clustered", n_clustered=2400, tol=1e-10,
-            problems=5, eps=5e-4),
+# The synthetic workloads, by name.  `seed` is the base seed of each workload's generators
+# (spectrum draws use it directly; H, start blocks and Lanczos vectors use offsets from it).
+WORKLOADS = {
+    # one isolated problem, uniform spectrum on [-1, 1]
+    "uniform_n1000": dict(n=1000, nev=50, nex=20, spectrum="uniform", tol=1e-10, seed=1000),
+    # one isolated problem, 600 clustered values below a uniform bulk
+    "clustered_n10000": dict(n=10000, nev=500, nex=100, spectrum="clustered", n_clustered=600,
+                             tol=1e-10, seed=2000),
+    # warm-started sequence whose nev falls inside the bulk (no gap after nev + nex)
+    "sequence_n20000": dict(n=20000, nev=1000, nex=200, spectrum="clustered", n_clustered=600,
+                            tol=1e-10, problems=10, eps=1e-3, seed=3000),
+    # serving: 16 sequences of uneven order
+    "serving": dict(sizes=(2000, 4000, 8000, 16000), sequences=16, problems=8, eps=1e-3,
+                    tol=1e-10, seed=4000),
+    # large warm-started sequence, clustered values scaled to nev (gap after nev + nex)
+    "sequence_n60000": dict(n=60000, nev=2000, nex=400, spectrum="clustered", n_clustered=2400,
+                            tol=1e-10, problems=5, eps=5e-4, seed=5000),
 }
 
 
-def spectrum_for(cfg: int, n: int | None = None, seed: int | None = None) -> np.ndarray:
-    c = CONFIGS[cfg]
+def spectrum_for(name: str, n: int | None = None, seed: int | None = None) -> np.ndarray:
+    c = WORKLOADS[name]
     n = n or c["n"]
-    g = rng(seed if seed is not None else 1000 * cfg)
+    g = rng(seed if seed is not None else c["seed"])
     if c.get("spectrum", "clustered") == "uniform":
         return spectrum_uniform(n, g)
     return spectrum_clustered(n, g, n_clustered=c.get("n_clustered", 600))

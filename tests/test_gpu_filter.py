@@ -212,7 +212,7 @@ def test_filter_full_size_sampled(ctx):
 
     n, nb = 10000, 600
     print("full-size filter: generating H on the device", flush=True)
-    lam = wl.spectrum_for(2)
+    lam = wl.spectrum_for("clustered_n10000")
     dH = wl.hermitian_torch(n, lam, seed=2001)
     V = wl.start_block(n, nb, 2500)
     deg = wl.optimized_degree_profile(nb, 36)
@@ -239,7 +239,7 @@ def test_filter_large_orders_closed_form(ctx, n, nb, profile_max):
     from paper_1805_10121_amd import capi
 
     print(f"large-order filter n={n} nb={nb}: generating", flush=True)
-    lam = wl.spectrum_for(5 if n == 60000 else 3, n=n)
+    lam = wl.spectrum_for("sequence_n60000" if n == 60000 else "sequence_n20000", n=n)
     dH = wl.hermitian_torch_fast(n, lam, seed=7000 + n)
     U, d = wl.structured_unitary(n, 7000 + n)
     V = wl.start_block(n, nb, 7100)

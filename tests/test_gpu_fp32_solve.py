@@ -148,9 +148,9 @@ def test_fp32_config2_full_size(ctx):
     import torch
     from paper_1805_10121_amd import capi
 
-    c = wl.CONFIGS[2]
+    c = wl.WORKLOADS["clustered_n10000"]
     n, nev, nex = c["n"], c["nev"], c["nex"]
-    lam = wl.spectrum_for(2)
+    lam = wl.spectrum_for("clustered_n10000")
     print("fp32 config2: generating H", flush=True)
     dH64 = wl.hermitian_torch(n, lam, seed=2001)
     dH = torch.empty((n, n), dtype=torch.complex64, device="cuda")

@@ -1,6 +1,6 @@
 """GPU solve (chase_solve, chase_seq_*) against the oracle and the prescribed spectra.
 
-Bars (the benchmark spec): eigenvalues within 1e-10 * ||H|| of the FP64 oracle / the known spectrum;
+Bars: eigenvalues within 1e-10 * ||H|| of the FP64 oracle / the known spectrum;
 orthonormal eigenvectors; ||H y - lambda y|| <= tol * ||H|| recomputed with a fresh product.
 Iteration and matvec counts are never compared between implementations (Sec. 6.2 notes that
 rounding and randomisation change them).
@@ -75,9 +75,9 @@ def test_small_solve_vs_oracle(ctx, optim):
 
 
 def test_config1_cold_start_dos(ctx):
-    c = wl.CONFIGS[1]
+    c = wl.WORKLOADS["uniform_n1000"]
     n, nev, nex = c["n"], c["nev"], c["nex"]
-    lam = wl.spectrum_for(1)
+    lam = wl.spectrum_for("uniform_n1000")
     H = wl.hermitian(n, lam, 1001)
     V0 = wl.start_block(n, nev + nex, 1500)
     starts = wl.start_block(n, 5, 1600)
@@ -94,9 +94,9 @@ def test_config1_cold_start_dos(ctx):
 def test_config1_mixed_precision(ctx):
     from paper_1805_10121_amd import capi
 
-    c = wl.CONFIGS[1]
+    c = wl.WORKLOADS["uniform_n1000"]
     n, nev, nex = c["n"], c["nev"], c["nex"]
-    lam = wl.spectrum_for(1)
+    lam = wl.spectrum_for("uniform_n1000")
     H = wl.hermitian(n, lam, 1001)
     V0 = wl.start_block(n, nev + nex, 1500)
     starts = wl.start_block(n, 5, 1600)
@@ -229,9 +229,9 @@ def test_config2_full_size(ctx):
     import torch
     from paper_1805_10121_amd import capi
 
-    c = wl.CONFIGS[2]
+    c = wl.WORKLOADS["clustered_n10000"]
     n, nev, nex = c["n"], c["nev"], c["nex"]
-    lam = wl.spectrum_for(2)
+    lam = wl.spectrum_for("clustered_n10000")
     print("config2: generating H", flush=True)
     dH = wl.hermitian_torch(n, lam, seed=2001)
     V0 = wl.start_block(n, nev + nex, 2500)

@@ -129,9 +129,9 @@ def test_solve_small_against_eigh(optim):
 
 
 def test_solve_config1_prescribed_spectrum():
-    c = wl.CONFIGS[1]
+    c = wl.WORKLOADS["uniform_n1000"]
     n, nev, nex = c["n"], c["nev"], c["nex"]
-    lam = wl.spectrum_for(1)
+    lam = wl.spectrum_for("uniform_n1000")
     A = wl.hermitian(n, lam, 1001)
     p = chase.ChaseParams(nev=nev, nex=nex, optim=True)
     V0 = wl.start_block(n, nev + nex, 1500)
