@@ -130,3 +130,16 @@ def test_create_without_gpu_fails_cleanly():
     h = ctypes.c_void_p()
     assert capi.lib().chase_create(ctypes.byref(h), 0, None) == capi.CHASE_EDEVICE
     assert not h.value
+
+
+def test_bench_refuses_more_than_one_gpu():
+    # the bench measures one GPU; asking for more exits with status 2 before touching a device
+    import os
+    import subprocess
+    import sys
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU only" in r.stderr and r.stdout == ""
