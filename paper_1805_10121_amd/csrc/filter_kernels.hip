@@ -883,8 +883,15 @@ __global__ __launch_bounds__(kThreads, OCC) void hemm_sk_kernel(
   }
 }
 
-// One workgroup per boundary p (grid = P); it completes the split tile that contains u0(p)
-// when p is the first workgroup whose range starts inside that tile.
+// Element slices of a tile in the fixup: at most 4 elements per thread in each slice.
+template <class C>
+constexpr int fixup_slices() {
+  constexpr int TE = C::BMC * C::BNC;
+  return TE / (4 * kThreads) > 0 ? TE / (4 * kThreads) : 1;
+}
+
+// Grid = P x fixup_slices: workgroup (p, s) completes slice s of the split tile that contains
+// u0(p), when p is the first workgroup whose range starts inside that tile.
 template <typename T, class C>
 __global__ __launch_bounds__(kThreads) void hemm_fixup_kernel(
     const T* __restrict__ X, int64_t ldx, T* __restrict__ OUT, int64_t ldo, int n, int ncols,
@@ -898,12 +905,17 @@ __global__ __launch_bounds__(kThreads) void hemm_fixup_kernel(
   tile_coords(t, (ncols + C::BNC - 1) / C::BNC, &tile_m, &tile_n);
   const int i0 = tile_m * C::BMC, j0 = tile_n * C::BNC;
   constexpr int TE = C::BMC * C::BNC;
-  constexpr int EPT = (TE + kThreads - 1) / kThreads;  // elements per thread
+  constexpr int SL = fixup_slices<C>();
+  constexpr int ES = TE / SL;                          // elements per slice
+  static_assert(ES * SL == TE && ES % kThreads == 0, "slice split");
+  constexpr int EPT = ES / kThreads;                   // elements per thread
+  constexpr int UNR = 4;                               // contributors whose loads are in flight
   constexpr int EW = elem_width<C>();
-  // Contributors outer, elements inner.  The slot offsets of up to kThreads contributors at a
-  // time (integer divisions) are found in parallel, one per thread, into LDS; the sum then runs
-  // over them with several contributors' loads in flight.  Every element still adds its slots
-  // in increasing pp (empty ranges contribute nothing).
+  const int e0 = static_cast<int>(blockIdx.y) * ES;
+  // The slot offsets of up to kThreads contributors at a time (integer divisions) are found in
+  // parallel, one per thread, into LDS.  The loads of UNR contributors are issued before any of
+  // them is added; every element still adds its slots in increasing pp, and an empty range
+  // (offset -1) adds nothing.
   __shared__ int64_t soff[kThreads];
   T hre[EPT], him[EPT];
 #pragma unroll
@@ -917,30 +929,32 @@ __global__ __launch_bounds__(kThreads) void hemm_fixup_kernel(
       soff[threadIdx.x] = a >= b ? int64_t{-1} : EW * (pp * 2 + sk_slot(pp, tr, units, P, nk)) * TE;
     }
     __syncthreads();
-    for (int j = 0; j < cnt; ++j) {
-      const int64_t o = soff[j];
-      if (o < 0) continue;
-      const T* src = partial + o;
-      // all of this contributor's loads first (distinct registers, one wait), then the sums
-      T vre[EPT], vim[EPT];
+    for (int j = 0; j < cnt; j += UNR) {
+      T vre[UNR][EPT], vim[UNR][EPT];
+      int64_t o[UNR];
 #pragma unroll
-      for (int q = 0; q < EPT; ++q) {
-        const int e = threadIdx.x + q * kThreads;
-        const bool in = TE % kThreads == 0 || e < TE;
-        vre[q] = in ? src[EW * e] : T(0);
-        if constexpr (EW == 2) vim[q] = in ? src[EW * e + 1] : T(0);
+      for (int u = 0; u < UNR; ++u) {
+        o[u] = j + u < cnt ? soff[j + u] : int64_t{-1};
+        const T* src = partial + (o[u] < 0 ? 0 : o[u]);
+#pragma unroll
+        for (int q = 0; q < EPT; ++q) {
+          const int e = e0 + static_cast<int>(threadIdx.x) + q * kThreads;
+          vre[u][q] = o[u] < 0 ? T(0) : src[EW * e];
+          if constexpr (EW == 2) vim[u][q] = o[u] < 0 ? T(0) : src[EW * e + 1];
+        }
       }
 #pragma unroll
-      for (int q = 0; q < EPT; ++q) {
-        hre[q] += vre[q];
-        if constexpr (EW == 2) him[q] += vim[q];
-      }
+      for (int u = 0; u < UNR; ++u)
+#pragma unroll
+        for (int q = 0; q < EPT; ++q) {
+          hre[q] = o[u] < 0 ? hre[q] : hre[q] + vre[u][q];
+          if constexpr (EW == 2) him[q] = o[u] < 0 ? him[q] : him[q] + vim[u][q];
+        }
     }
   }
 #pragma unroll
   for (int q = 0; q < EPT; ++q) {
-    const int e = threadIdx.x + q * kThreads;
-    if (TE % kThreads != 0 && e >= TE) continue;
+    const int e = e0 + static_cast<int>(threadIdx.x) + q * kThreads;
     const int r = e % C::BMC, c = e / C::BMC;
     if (i0 + r < n && j0 + c < ncols)
       store_result<T, C>(X, ldx, OUT, ldo, i0 + r, j0 + c, hre[q], him[q], alpha, beta, gamma);
@@ -1009,8 +1023,9 @@ hipError_t launch_sk(const T* H, int64_t ldh, int64_t n, const T* X, int64_t ldx
                      partial);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || units == 0) return e;
-  hipLaunchKernelGGL((hemm_fixup_kernel<T, C>), dim3(static_cast<unsigned>(P)), dim3(kThreads), 0,
-                     stream, X, ldx, OUT, ldo, static_cast<int>(n), static_cast<int>(ncols), alpha,
+  hipLaunchKernelGGL((hemm_fixup_kernel<T, C>),
+                     dim3(static_cast<unsigned>(P), static_cast<unsigned>(fixup_slices<C>())),
+                     dim3(kThreads), 0, stream, X, ldx, OUT, ldo, static_cast<int>(n), static_cast<int>(ncols), alpha,
                      beta, gamma, tiles_m, nk, dp_tiles, units, P, partial);
   return hipGetLastError();
 }
