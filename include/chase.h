@@ -135,7 +135,9 @@ void chase_destroy(chase_ctx* ctx);
 /* Text of the last error on this context ("" if none).  Valid until the next call on ctx. */
 const char* chase_last_error(const chase_ctx* ctx);
 
-/* Device bytes chase_solve will hold for cfg (H itself excluded).  No device work. */
+/* Device bytes chase_solve will hold for cfg: the blocks, Lanczos vectors and small matrices,
+   plus the FP32 copy of H that MIXED solves (4 w n^2 bytes) and single-precision complex solves
+   (planar, 8 n^2 bytes) make; the caller's H itself is not counted.  No device work. */
 size_t chase_workspace_bytes(const chase_config* cfg);
 
 /*
