@@ -337,3 +337,60 @@ def test_hemm_step_3m_single_product(ctx):
     torch.cuda.synchronize()
     got = capi.from_device(o32).astype(np.complex128)
     assert np.max(np.abs(got - ref)) <= 1e-5 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("mode", ["fp64", "fp32", "fp32_3m", "real_fp64", "real_fp32"])
+def test_hemm_step_random_shapes(ctx, mode):
+    """One product OUT <- alpha H X + gamma X + beta OUT on seeded random shapes: orders 1..599,
+    1..199 columns (thin, narrow, slim and wide tiles; data-parallel and stream-K schedules),
+    leading dimensions padded by 0..3 (odd and even), beta = 0 with a NaN-filled OUT that must
+    not be read, and rows past n of OUT that must stay untouched.  Against the oracle's product
+    in FP64; FP32 modes within 5e-5 of max |OUT| (K <= 599 terms of FP32 rounding)."""
+    import torch
+    from paper_1805_10121_amd import capi
+
+    real = mode.startswith("real")
+    prec = {"fp64": capi.CHASE_FP64, "fp32": capi.CHASE_FP32, "fp32_3m": capi.CHASE_FP32_3M,
+            "real_fp64": capi.CHASE_REAL_FP64, "real_fp32": capi.CHASE_REAL_FP32}[mode]
+    single = mode in ("fp32", "fp32_3m", "real_fp32")
+    tol = 5e-5 if single else 1e-13
+    g = wl.rng({"fp64": 1, "fp32": 2, "fp32_3m": 3, "real_fp64": 4, "real_fp32": 5}[mode] + 7000)
+    for case in range(8):
+        n, nb = int(g.integers(1, 600)), int(g.integers(1, 200))
+        ldh, ldx, ldo = (n + int(p) for p in g.integers(0, 4, 3))
+        alpha, beta, gamma = (float(v) for v in g.uniform(-2.0, 2.0, 3))
+        if case % 3 == 0:
+            beta = 0.0
+        print(f"{mode} case {case}: n={n} ncols={nb} ld=({ldh},{ldx},{ldo}) beta={beta:.2f}",
+              flush=True)
+        if real:
+            A = g.standard_normal((n, n))
+            H = 0.5 * (A + A.T)
+            X, Y = g.standard_normal((n, nb)), g.standard_normal((n, nb))
+        else:
+            A = wl.complex_gaussian(g, n, n)
+            H = 0.5 * (A + A.conj().T)
+            X, Y = wl.complex_gaussian(g, n, nb), wl.complex_gaussian(g, n, nb)
+        ref = ch.product(H, X, Y, alpha, beta, gamma)
+        if real:
+            ref = ref.real
+        dt = (np.float32 if real else np.complex64) if single else (np.float64 if real else np.complex128)
+        Hp = np.full((ldh, n), np.nan, dtype=H.dtype)
+        Hp[:n] = H
+        Xp = np.full((ldx, nb), np.nan, dtype=X.dtype)
+        Xp[:n] = X
+        Op = np.full((ldo, nb), 7.0, dtype=Y.dtype)
+        Op[:n] = Y if beta != 0.0 else np.nan
+        if mode == "fp32_3m":
+            dH64 = capi.to_device(Hp)
+            dH = torch.empty(2 * ldh * n, dtype=torch.float32, device="cuda")
+            ctx.chase_convert_c128_to_planar32(dH64, ldh, dH, ldh, n)
+        else:
+            dH = capi.to_device(Hp.astype(dt))
+        dX, dO = capi.to_device(Xp.astype(dt)), capi.to_device(Op.astype(dt))
+        assert ctx.chase_hemm_step(prec, dH, ldh, n, dX, ldx, dO, ldo, nb, alpha, beta, gamma) == 0
+        torch.cuda.synchronize()
+        got = capi.from_device(dO)
+        assert np.all(got[n:] == 7.0)
+        err = np.max(np.abs(got[:n].astype(ref.dtype) - ref)) / np.max(np.abs(ref))
+        assert err <= tol, (mode, case, n, nb, err)
