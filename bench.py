@@ -401,6 +401,10 @@ def main():
                     help="sequence workload: mixed-mode switch thresholds to run")
     ap.add_argument("--deg-max-fp32", type=int, nargs="*", default=[18],
                     help="sequence workload: mixed-mode FP32 degree caps to run")
+    ap.add_argument("--serving-workers", type=int, default=8,
+                    help="serving workload: concurrent solves in the server")
+    ap.add_argument("--serving-rates", type=float, nargs="*", default=[0.5, 0.8, 1.0],
+                    help="serving workload: Poisson rates as fractions of the closed-loop rate")
     ap.add_argument("--order", type=int, default=None,
                     help="sequence workload: order (default: the config's)")
     ap.add_argument("--h-gen", choices=["haar", "structured"], default="haar",
@@ -437,7 +441,8 @@ def main():
         print(json.dumps(out), flush=True)
         return
     if args.workload == "serving":
-        print(json.dumps(run_serving(problems=args.problems or 8)),
+        print(json.dumps(run_serving(problems=args.problems or 8, workers=args.serving_workers,
+                                     rates=tuple(args.serving_rates))),
               flush=True)
         return
 
