@@ -54,7 +54,12 @@ typedef enum {
                        K stages; the blocks are complex64 as for CHASE_FP32 */
   CHASE_REAL_FP64 = 4, /* chase_filter / chase_hemm_step: real symmetric H and real blocks, all
                        float64 (the paper's real "D" instance, Sec. 5.1), FP64 MFMA            */
-  CHASE_REAL_FP32 = 5  /* the same with float32 H and blocks, FP32 MFMA with FP32 accumulation */
+  CHASE_REAL_FP32 = 5, /* the same with float32 H and blocks, FP32 MFMA with FP32 accumulation */
+  CHASE_FP64_3M = 6  /* chase_filter / chase_hemm_step: H is "planar complex128" -- two real
+                       n x n float64 planes, Re H then Im H at an offset of ldh * n doubles --
+                       and the products use three real FP64 MFMA products per complex product
+                       (3M, 6 instead of 8 real flops per complex multiply-add) with FP64
+                       accumulation; the blocks are complex128 as for CHASE_FP64 */
 } chase_precision;
 
 /*
@@ -153,6 +158,7 @@ size_t chase_workspace_bytes(const chase_config* cfg);
  *   precision  CHASE_FP64: H, V, W are complex128.  CHASE_FP32: H, V, W are complex64 (use the
  *              conversion calls below to stage them); the recurrence coefficients are computed
  *              in FP64 and rounded to FP32 per launch.  CHASE_FP32_3M: planar complex64 H.
+ *              CHASE_FP64_3M: planar complex128 H, complex128 V, W.
  *              CHASE_REAL_FP64 / CHASE_REAL_FP32: real symmetric H and real V, W (float64 /
  *              float32); leading dimensions count real elements.
  *   H          device, n x n, column-major, leading dimension ldh >= n, full Hermitian (or
@@ -182,8 +188,11 @@ int chase_hemm_step(chase_ctx* ctx, int precision, const void* H, int64_t ldh, i
 
 /* Precision staging of the mixed filter: dst = (complex64) src / (complex128) src on a
    rows x cols column-major block; planar32 writes the n x n matrix as the two FP32 planes of
-   CHASE_FP32_3M (dst: 2 * ld_dst * n floats).  Device pointers; enqueues only. */
+   CHASE_FP32_3M (dst: 2 * ld_dst * n floats), planar64 as the two float64 planes of
+   CHASE_FP64_3M (dst: 2 * ld_dst * n doubles).  Device pointers; enqueues only. */
 int chase_convert_c128_to_planar32(chase_ctx* ctx, const void* src, int64_t ld_src, void* dst,
+                                   int64_t ld_dst, int64_t n);
+int chase_convert_c128_to_planar64(chase_ctx* ctx, const void* src, int64_t ld_src, void* dst,
                                    int64_t ld_dst, int64_t n);
 int chase_convert_c128_to_c64(chase_ctx* ctx, const void* src, int64_t ld_src, void* dst,
                               int64_t ld_dst, int64_t rows, int64_t cols);

@@ -28,6 +28,7 @@ CHASE_MIXED = 2
 CHASE_FP32_3M = 3
 CHASE_REAL_FP64 = 4
 CHASE_REAL_FP32 = 5
+CHASE_FP64_3M = 6
 
 _i64, _i32, _f64, _u64, _vp = ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_uint64, ctypes.c_void_p
 
@@ -73,6 +74,7 @@ _PROTOTYPES = {
     "chase_convert_c128_to_c64": (ctypes.c_int, [_vp, _vp, _i64, _vp, _i64, _i64, _i64]),
     "chase_convert_c64_to_c128": (ctypes.c_int, [_vp, _vp, _i64, _vp, _i64, _i64, _i64]),
     "chase_convert_c128_to_planar32": (ctypes.c_int, [_vp, _vp, _i64, _vp, _i64, _i64]),
+    "chase_convert_c128_to_planar64": (ctypes.c_int, [_vp, _vp, _i64, _vp, _i64, _i64]),
     "chase_solve": (ctypes.c_int, [_vp, ctypes.POINTER(chase_config), _vp, _i64, _vp, _i64,
                                    ctypes.POINTER(_f64), ctypes.POINTER(_f64),
                                    ctypes.POINTER(chase_stats)]),
@@ -199,6 +201,10 @@ class Context:
     def chase_convert_c128_to_c64(self, src, ld_src, dst, ld_dst, rows, cols):
         return _check(self.handle, lib().chase_convert_c128_to_c64(
             self.handle, _ptr(src), ld_src, _ptr(dst), ld_dst, rows, cols))
+
+    def chase_convert_c128_to_planar64(self, src, ld_src, dst, ld_dst, n):
+        return _check(self.handle, lib().chase_convert_c128_to_planar64(
+            self.handle, _ptr(src), ld_src, _ptr(dst), ld_dst, n))
 
     def chase_convert_c128_to_planar32(self, src, ld_src, dst, ld_dst, n):
         return _check(self.handle, lib().chase_convert_c128_to_planar32(

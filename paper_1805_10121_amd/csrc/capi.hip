@@ -66,10 +66,10 @@ int check_bounds(chase_ctx* ctx, double b_sup, double mu_1, double mu_nevnex) {
 
 int check_product_args(chase_ctx* ctx, int precision, const void* H, int64_t ldh, int64_t n,
                        const void* X, int64_t ldx, const void* OUT, int64_t ldo, int64_t ncols) {
-  if (precision < CHASE_FP64 || precision > CHASE_REAL_FP32 || precision == CHASE_MIXED)
+  if (precision < CHASE_FP64 || precision > CHASE_FP64_3M || precision == CHASE_MIXED)
     return set_error(ctx, CHASE_EINVAL,
-                     "precision must be CHASE_FP64, CHASE_FP32, CHASE_FP32_3M, CHASE_REAL_FP64 or "
-                     "CHASE_REAL_FP32");
+                     "precision must be CHASE_FP64, CHASE_FP32, CHASE_FP32_3M, CHASE_REAL_FP64, "
+                     "CHASE_REAL_FP32 or CHASE_FP64_3M");
   if (n < 0 || ncols < 0) return set_error(ctx, CHASE_EINVAL, "negative size");
   if (n > 0x7fffffffLL || ncols > 0x7fffffffLL)
     return set_error(ctx, CHASE_EINVAL, "n and ncols must fit in int32");
@@ -77,9 +77,13 @@ int check_product_args(chase_ctx* ctx, int precision, const void* H, int64_t ldh
   if (!H || !X || !OUT) return set_error(ctx, CHASE_EINVAL, "NULL buffer");
   if (ldh < n || ldx < n || ldo < n)
     return set_error(ctx, CHASE_EINVAL, "leading dimension smaller than n");
-  const size_t elem = precision == CHASE_FP64 ? 16 : precision == CHASE_REAL_FP32 ? 4 : 8;
-  const size_t hb = precision == CHASE_FP32_3M ? static_cast<size_t>(ldh) * n * 8
-                                               : block_bytes(ldh, n, n, elem);
+  const size_t elem = (precision == CHASE_FP64 || precision == CHASE_FP64_3M) ? 16
+                      : precision == CHASE_REAL_FP32                        ? 4
+                                                                            : 8;
+  // planar H: two ldh x n planes of floats (FP32_3M) or doubles (FP64_3M)
+  const size_t hb = precision == CHASE_FP32_3M   ? static_cast<size_t>(ldh) * n * 8
+                    : precision == CHASE_FP64_3M ? static_cast<size_t>(ldh) * n * 16
+                                                 : block_bytes(ldh, n, n, elem);
   const size_t xb = block_bytes(ldx, n, ncols, elem);
   const size_t ob = block_bytes(ldo, n, ncols, elem);
   if (overlaps(X, xb, OUT, ob)) return set_error(ctx, CHASE_EINVAL, "X and OUT overlap");
@@ -213,10 +217,11 @@ int chase_filter(chase_ctx* ctx, int precision, const void* H, int64_t ldh, int6
   if ((rc = check_bounds(ctx, b_sup, mu_1, mu_nevnex))) return rc;
   CHASE_HIP_TRY(ctx, hipSetDevice(ctx->device));
   hipError_t e;
-  if (precision == CHASE_FP64 || precision == CHASE_REAL_FP64)
+  if (precision == CHASE_FP64 || precision == CHASE_REAL_FP64 || precision == CHASE_FP64_3M)
     e = run_filter<double>(static_cast<const double*>(H), ldh, n, static_cast<double*>(V),
                            static_cast<double*>(W), ld, ncols, degrees, b_sup, mu_1, mu_nevnex,
-                           ctx->prod, ctx->stream, nullptr, precision == CHASE_REAL_FP64 ? 3 : 0);
+                           ctx->prod, ctx->stream, nullptr,
+                           precision == CHASE_REAL_FP64 ? 3 : precision == CHASE_FP64_3M ? 4 : 0);
   else if (precision == CHASE_REAL_FP32)
     e = run_filter<float>(static_cast<const float*>(H), ldh, n, static_cast<float*>(V),
                           static_cast<float*>(W), ld, ncols, degrees, b_sup, mu_1, mu_nevnex,
@@ -257,6 +262,10 @@ int chase_hemm_step(chase_ctx* ctx, int precision, const void* H, int64_t ldh, i
                                      ldo, ncols, static_cast<float>(alpha),
                                      static_cast<float>(beta), static_cast<float>(gamma),
                                      ctx->prod, ctx->stream);
+  else if (precision == CHASE_FP64_3M)
+    e = launch_hemm_step_3m_f64(static_cast<const double*>(H), ldh, n,
+                                static_cast<const double*>(X), ldx, static_cast<double*>(OUT), ldo,
+                                ncols, alpha, beta, gamma, ctx->prod, ctx->stream);
   else if (precision == CHASE_FP32_3M)
     e = launch_hemm_step_3m(static_cast<const float*>(H), ldh, n, static_cast<const float*>(X), ldx,
                             static_cast<float*>(OUT), ldo, ncols, static_cast<float>(alpha),
@@ -310,6 +319,23 @@ int chase_convert_c128_to_planar32(chase_ctx* ctx, const void* src, int64_t ld_s
   CHASE_HIP_TRY(ctx, hipSetDevice(ctx->device));
   CHASE_HIP_TRY(ctx, launch_convert_c128_to_planar32(static_cast<const double*>(src), ld_src,
                                                      static_cast<float*>(dst), ld_dst, n,
+                                                     ctx->stream));
+  return CHASE_OK;
+}
+
+int chase_convert_c128_to_planar64(chase_ctx* ctx, const void* src, int64_t ld_src, void* dst,
+                                   int64_t ld_dst, int64_t n) {
+  if (!ctx) return CHASE_EINVAL;
+  ctx->last_error.clear();
+  if (n < 0) return set_error(ctx, CHASE_EINVAL, "negative size");
+  if (n == 0) return CHASE_OK;
+  if (!src || !dst) return set_error(ctx, CHASE_EINVAL, "NULL buffer");
+  if (ld_src < n || ld_dst < n) return set_error(ctx, CHASE_EINVAL, "leading dimension < n");
+  if (overlaps(src, block_bytes(ld_src, n, n, 16), dst, static_cast<size_t>(ld_dst) * n * 16))
+    return set_error(ctx, CHASE_EINVAL, "src and dst overlap");
+  CHASE_HIP_TRY(ctx, hipSetDevice(ctx->device));
+  CHASE_HIP_TRY(ctx, launch_convert_c128_to_planar64(static_cast<const double*>(src), ld_src,
+                                                     static_cast<double*>(dst), ld_dst, n,
                                                      ctx->stream));
   return CHASE_OK;
 }

@@ -1,5 +1,6 @@
 // Host side of the Chebyshev filter (Algorithm 4 with the scaled recurrence of Eq. (7)), for
-// complex Hermitian H (4M or 3M products) and real symmetric H (kind 3, real products).
+// complex Hermitian H (4M or 3M products, FP32 or FP64) and real symmetric H (kind 3, real
+// products).
 //
 // The coefficients are scalars computed here in FP64 and passed to each launch:
 //   product 1:   W <- (sigma_1/e) (H - cI) V                      (Alg. 4 line 4)
@@ -34,6 +35,9 @@ hipError_t run_filter(const T* H, int64_t ldh, int64_t n, T* V, T* W, int64_t ld
         else
           err = launch_hemm_step<T>(H, ldh, n, X, ld, OUT, ld, p.ncols, static_cast<T>(p.alpha),
                                     static_cast<T>(p.beta), static_cast<T>(p.gamma), ps, stream);
+      } else if (kind == 4) {
+        err = launch_hemm_step_3m_f64(H, ldh, n, X, ld, OUT, ld, p.ncols, p.alpha, p.beta,
+                                      p.gamma, ps, stream);
       } else {
         err = launch_hemm_step<T>(H, ldh, n, X, ld, OUT, ld, p.ncols, static_cast<T>(p.alpha),
                                   static_cast<T>(p.beta), static_cast<T>(p.gamma), ps, stream);

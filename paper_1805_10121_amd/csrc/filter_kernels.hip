@@ -359,14 +359,17 @@ __device__ __forceinline__ void tile_foreach_4m(const typename C::Frag& f, Fn&& 
       }
 }
 
-// 3M complex product on FP32 MFMA (complex64 data, H stored as two real planes: Re H, then
-// Im H at an offset of ldh * n floats).  With T1 = ReH ReX, T2 = ImH ImX and
-// T3 = (ReH + ImH)(ReX + ImX):  Re(HX) = T1 - T2, Im(HX) = T3 - T1 - T2 -- three real products
-// (6 real flops per complex multiply-add) instead of four.  The sums ReH + ImH and ReX + ImX
-// are formed in registers from the LDS planes.  Accumulators are promoted to FP64 every
-// PROMOTE stages (see Tile).  Each wave owns RT x CG MFMA tiles of 16 x 16 complex outputs.
-template <int BMC_, int BNC_, int KT_, int WR_, int WC_, int PAD_ = 4, int PROMOTE_ = 1>
+// 3M complex product (H stored as two real planes: Re H, then Im H at an offset of ldh * n
+// values), on FP32 MFMA for complex64 data or FP64 MFMA for complex128 data.  With
+// T1 = ReH ReX, T2 = ImH ImX and T3 = (ReH + ImH)(ReX + ImX):  Re(HX) = T1 - T2,
+// Im(HX) = T3 - T1 - T2 -- three real products (6 real flops per complex multiply-add) instead
+// of four.  The sums ReH + ImH and ReX + ImX are formed in registers from the LDS planes.  FP32
+// accumulators are promoted to FP64 every PROMOTE stages (see Tile).  Each wave owns RT x CG
+// MFMA tiles of 16 x 16 complex outputs.
+template <int BMC_, int BNC_, int KT_, int WR_, int WC_, int PAD_ = 4, int PROMOTE_ = 1,
+          typename T_ = float>
 struct Tile3M {
+  using T = T_;  // float: complex64 data, FP32 MFMA; double: complex128 data, FP64 MFMA
   static constexpr int KIND = 1;
   static constexpr int BMC = BMC_, BNC = BNC_, KT = KT_, WR = WR_, WC = WC_;
   static constexpr int PROMOTE = PROMOTE_;
@@ -375,14 +378,15 @@ struct Tile3M {
   static constexpr int AR = BMC + PAD_;
   static constexpr int BR = BNC + PAD_;
   static_assert(WR * WC == 4 && RT >= 1 && CG >= 1, "wave grid");
-  static_assert((AR * 4) % 16 == 0, "16-byte LDS rows");
-  using acc_t = f4_t;
-  using v2 = float2;
+  static_assert((AR * sizeof(T)) % 16 == 0, "16-byte LDS rows");
+  static_assert(sizeof(T) == 4 || PROMOTE_ == 0, "promotion applies to FP32 accumulators");
+  using acc_t = typename Acc<T>::type;
+  using v2 = typename Acc<T>::v2;
   struct Smem {
-    float Are[2][KT][AR];
-    float Aim[2][KT][AR];
-    float Bre[2][KT][BR];
-    float Bim[2][KT][BR];
+    T Are[2][KT][AR];
+    T Aim[2][KT][AR];
+    T Bre[2][KT][BR];
+    T Bim[2][KT][BR];
   };
   struct Frag64 {
     acc_t acc[RT][CG][3];
@@ -396,22 +400,28 @@ struct Tile3M {
 
 template <class C, bool V16>
 __device__ __forceinline__ void tile_mainloop_3m(typename C::Smem& sm, typename C::Frag& f,
-                                                 const float* __restrict__ H, int64_t ldh, int n,
-                                                 const float* __restrict__ X, int64_t ldx,
-                                                 int ncols, int i0, int j0, int ka, int kb) {
-  using acc_t = f4_t;
-  constexpr int AV = V16 ? 4 : 1;  // floats per A load (4 consecutive rows of one plane)
-  constexpr int BV = V16 ? 2 : 1;  // complex elements per X load
+                                                 const typename C::T* __restrict__ H, int64_t ldh,
+                                                 int n, const typename C::T* __restrict__ X,
+                                                 int64_t ldx, int ncols, int i0, int j0, int ka,
+                                                 int kb) {
+  using T = typename C::T;
+  using acc_t = typename C::acc_t;
+  using v2 = typename C::v2;
+  // 16-byte global loads when V16: consecutive rows of one plane (4 floats or 2 doubles) and
+  // one or two complex elements of X
+  constexpr int AV = V16 ? 16 / static_cast<int>(sizeof(T)) : 1;
+  constexpr int BV = V16 ? 8 / static_cast<int>(sizeof(T)) : 1;
   constexpr int A_LD = C::BMC * C::KT / (kThreads * AV);
   constexpr int B_LD = C::BNC * C::KT / (kThreads * BV);
   static_assert(A_LD * kThreads * AV == C::BMC * C::KT, "A split");
   static_assert(B_LD * kThreads * BV == C::BNC * C::KT, "B split");
-  // exactly AV floats / BV complex elements: alignment = size, so a copy never touches a
+  // exactly AV values / BV complex elements: alignment = size, so a copy never touches a
   // neighbour
-  struct alignas(4 * AV) AL { float e[AV]; };
-  struct alignas(8 * BV) BL { float2 e[BV]; };
-  static_assert(sizeof(AL) == 4 * AV && sizeof(BL) == 8 * BV, "load unit size");
-  const float* __restrict__ Hi = H + ldh * static_cast<int64_t>(n);
+  struct alignas(sizeof(T) * AV) AL { T e[AV]; };
+  struct alignas(2 * sizeof(T) * BV) BL { v2 e[BV]; };
+  static_assert(sizeof(AL) == sizeof(T) * AV && sizeof(BL) == 2 * sizeof(T) * BV,
+                "load unit size");
+  const T* __restrict__ Hi = H + ldh * static_cast<int64_t>(n);
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, li = lane & 15;
@@ -433,8 +443,8 @@ __device__ __forceinline__ void tile_mainloop_3m(typename C::Smem& sm, typename 
 #pragma unroll
         for (int e = 0; e < AV; ++e) {
           const bool ok = col < n && row + e < n;
-          rar[q].e[e] = ok ? H[off + e] : 0.f;
-          rai[q].e[e] = ok ? Hi[off + e] : 0.f;
+          rar[q].e[e] = ok ? H[off + e] : T(0);
+          rai[q].e[e] = ok ? Hi[off + e] : T(0);
         }
       }
     }
@@ -443,14 +453,14 @@ __device__ __forceinline__ void tile_mainloop_3m(typename C::Smem& sm, typename 
       const int idx = tid + kThreads * q;
       const int jj = idx / (C::KT / BV), kk = (idx % (C::KT / BV)) * BV;
       const int row = k0 + kk, col = j0 + jj;
-      const float* src = X + 2 * (static_cast<int64_t>(row) + static_cast<int64_t>(col) * ldx);
+      const T* src = X + 2 * (static_cast<int64_t>(row) + static_cast<int64_t>(col) * ldx);
       if (col < ncols && row + BV - 1 < n) {
         rb[q] = *reinterpret_cast<const BL*>(src);
       } else {
 #pragma unroll
         for (int e = 0; e < BV; ++e)
-          rb[q].e[e] = (col < ncols && row + e < n) ? reinterpret_cast<const float2*>(src)[e]
-                                                     : float2{0.f, 0.f};
+          rb[q].e[e] = (col < ncols && row + e < n) ? reinterpret_cast<const v2*>(src)[e]
+                                                     : v2{T(0), T(0)};
       }
     }
   };
@@ -498,7 +508,7 @@ __device__ __forceinline__ void tile_mainloop_3m(typename C::Smem& sm, typename 
 #pragma unroll
     for (int s = 0; s < C::KT / 4; ++s) {
       const int k = 4 * s + g;
-      float ar[C::RT], ai[C::RT], as[C::RT], br[C::CG], bi[C::CG], bs[C::CG];
+      T ar[C::RT], ai[C::RT], as[C::RT], br[C::CG], bi[C::CG], bs[C::CG];
 #pragma unroll
       for (int rt = 0; rt < C::RT; ++rt) {
         ar[rt] = sm.Are[cur][k][rbase + rt * 16 + li];
@@ -541,6 +551,7 @@ __device__ __forceinline__ void tile_mainloop_3m(typename C::Smem& sm, typename 
 
 template <class C, typename Fn>
 __device__ __forceinline__ void tile_foreach_3m(const typename C::Frag& f, Fn&& fn) {
+  using T = typename C::T;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, li = lane & 15;
@@ -551,14 +562,15 @@ __device__ __forceinline__ void tile_foreach_3m(const typename C::Frag& f, Fn&& 
     for (int cg = 0; cg < C::CG; ++cg)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = wr * (C::BMC / C::WR) + rt * 16 + 4 * g + r;
+        // accumulator row layout: FP64 MFMA rows g + 4r, FP32 MFMA rows 4g + r
+        const int row = wr * (C::BMC / C::WR) + rt * 16 + (sizeof(T) == 8 ? g + 4 * r : 4 * g + r);
         const int col = wc * (C::BNC / C::WC) + cg * 16 + li;
         if constexpr (C::PROMOTE > 0) {
           const double t1 = f.acc64[rt][cg][0][r], t2 = f.acc64[rt][cg][1][r];
           const double t3 = f.acc64[rt][cg][2][r];
           fn(row, col, static_cast<float>(t1 - t2), static_cast<float>(t3 - t1 - t2));
         } else {
-          const float t1 = f.acc[rt][cg][0][r], t2 = f.acc[rt][cg][1][r], t3 = f.acc[rt][cg][2][r];
+          const T t1 = f.acc[rt][cg][0][r], t2 = f.acc[rt][cg][1][r], t3 = f.acc[rt][cg][2][r];
           fn(row, col, t1 - t2, t3 - t1 - t2);
         }
       }
@@ -1079,6 +1091,12 @@ constexpr double kSlimCost = 1.10;
 // about 9 % faster; the FP32 part of the error grows like sqrt(64) units of FP32 roundoff,
 // well below the 1e-6 residual at which the mixed solver leaves FP32.
 using Wide3M = Tile3M<64, 64, 16, 2, 2, 4, 4>;
+// The same 3M scheme on FP64 MFMA for complex128 data stored as two float64 planes: three
+// real products instead of four per complex product.  No promotion (FP64 accumulators);
+// 8-byte loads (measured faster than 16-byte ones for this tile).
+using Wide3M64 = Tile3M<64, 64, 16, 2, 2, 4, 0, double>;
+using Narrow3M64 = Tile3M<64, 32, 16, 4, 1, 4, 0, double>;
+using Thin3M64 = Tile3M<128, 16, 16, 4, 1, 4, 0, double>;
 
 // Two-element (16-byte) global loads are used for complex64 data when H and X are 16-byte
 // aligned and n and their leading dimensions are even.
@@ -1130,6 +1148,9 @@ size_t product_scratch_bytes(int cus) {
   b = std::max(b, sk_scratch_bytes<double, NarrowTile<double>>(slots));
   b = std::max(b, sk_scratch_bytes<double, SlimTile64>(static_cast<int64_t>(cus) * kOccSlim));
   b = std::max(b, sk_scratch_bytes<double, ThinTile64>(slots));
+  b = std::max(b, sk_scratch_bytes<double, Wide3M64>(slots));
+  b = std::max(b, sk_scratch_bytes<double, Narrow3M64>(slots));
+  b = std::max(b, sk_scratch_bytes<double, Thin3M64>(slots));
   b = std::max(b, sk_scratch_bytes<double, RealTile<double>>(slots));
   b = std::max(b, sk_scratch_bytes<double, RealThinTile<double>>(slots));
   return b;
@@ -1224,6 +1245,21 @@ hipError_t launch_hemm_step_3m(const float* H, int64_t ldh, int64_t n, const flo
                                      stream, ldh % 4 == 0);
 }
 
+hipError_t launch_hemm_step_3m_f64(const double* H, int64_t ldh, int64_t n, const double* X,
+                                   int64_t ldx, double* OUT, int64_t ldo, int64_t ncols,
+                                   double alpha, double beta, double gamma,
+                                   const ProductScratch& ps, hipStream_t stream) {
+  if (n <= 0 || ncols <= 0) return hipSuccess;
+  if (ncols <= 16)
+    return launch_sched<double, Thin3M64>(H, ldh, n, X, ldx, OUT, ldo, ncols, alpha, beta, gamma,
+                                          ps, stream, false);
+  if (ncols <= 32)
+    return launch_sched<double, Narrow3M64>(H, ldh, n, X, ldx, OUT, ldo, ncols, alpha, beta,
+                                            gamma, ps, stream, false);
+  return launch_sched<double, Wide3M64>(H, ldh, n, X, ldx, OUT, ldo, ncols, alpha, beta, gamma,
+                                        ps, stream, false);
+}
+
 hipError_t launch_hemm_group_3m(const GroupDesc<float>* descs, int count, hipStream_t stream) {
   for (int base = 0; base < count; base += kMaxGroup) {
     GroupArgs<float> a{};
@@ -1316,6 +1352,29 @@ __global__ void planar_kernel(const double* __restrict__ src, int64_t lds, float
   }
 }
 }  // namespace
+
+namespace {
+__global__ void planar64_kernel(const double* __restrict__ src, int64_t lds,
+                                double* __restrict__ dst, int64_t ldd, int64_t n) {
+  const int64_t total = n * n;
+  double* im = dst + ldd * n;
+  for (int64_t t = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; t < total;
+       t += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int64_t r = t % n, c = t / n;
+    const double2 v = *reinterpret_cast<const double2*>(src + 2 * (r + c * lds));
+    dst[r + c * ldd] = v.x;
+    im[r + c * ldd] = v.y;
+  }
+}
+}  // namespace
+
+hipError_t launch_convert_c128_to_planar64(const double* src, int64_t lds, double* dst,
+                                           int64_t ldd, int64_t n, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(planar64_kernel, dim3(convert_blocks(n * n)), dim3(256), 0, stream, src,
+                     lds, dst, ldd, n);
+  return hipGetLastError();
+}
 
 hipError_t launch_convert_c128_to_planar32(const double* src, int64_t lds, float* dst, int64_t ldd,
                                            int64_t n, hipStream_t stream) {

@@ -66,6 +66,13 @@ hipError_t launch_hemm_step_3m(const float* H, int64_t ldh, int64_t n, const flo
                                float beta, float gamma, const ProductScratch& ps,
                                hipStream_t stream);
 hipError_t launch_hemm_group_3m(const GroupDesc<float>* descs, int count, hipStream_t stream);
+// 3M products on planar complex128 H (Re plane, then Im plane at H + ldh * n), FP64 MFMA.
+hipError_t launch_hemm_step_3m_f64(const double* H, int64_t ldh, int64_t n, const double* X,
+                                   int64_t ldx, double* OUT, int64_t ldo, int64_t ncols,
+                                   double alpha, double beta, double gamma,
+                                   const ProductScratch& ps, hipStream_t stream);
+hipError_t launch_convert_c128_to_planar64(const double* src, int64_t lds, double* dst,
+                                           int64_t ldd, int64_t n, hipStream_t stream);
 hipError_t launch_convert_c128_to_planar32(const double* src, int64_t lds, float* dst, int64_t ldd,
                                            int64_t n, hipStream_t stream);
 
@@ -111,7 +118,7 @@ hipError_t launch_split_planes_c64(const float* src, int64_t lds, float* dst, in
 // Algorithm 4 on an n x ncols block with sorted even degrees (validated by the caller).  The
 // result ends in V.  scalars: the per-product (alpha, beta, gamma) in FP64.
 // kind: 0 complex128 (4M), 1 complex64 interleaved (4M), 2 complex64 planar H (3M),
-// 3 real data (T = double or float).
+// 3 real data (T = double or float), 4 complex128 planar H (3M, FP64).
 template <typename T>
 hipError_t run_filter(const T* H, int64_t ldh, int64_t n, T* V, T* W, int64_t ld, int64_t ncols,
                       const int32_t* degrees, double b_sup, double mu_1, double mu_nevnex,

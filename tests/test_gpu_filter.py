@@ -339,7 +339,7 @@ def test_hemm_step_3m_single_product(ctx):
     assert np.max(np.abs(got - ref)) <= 1e-5 * np.max(np.abs(ref))
 
 
-@pytest.mark.parametrize("mode", ["fp64", "fp32", "fp32_3m", "real_fp64", "real_fp32"])
+@pytest.mark.parametrize("mode", ["fp64", "fp64_3m", "fp32", "fp32_3m", "real_fp64", "real_fp32"])
 def test_hemm_step_random_shapes(ctx, mode):
     """One product OUT <- alpha H X + gamma X + beta OUT on seeded random shapes: orders 1..599,
     1..199 columns (thin, narrow, slim and wide tiles; data-parallel and stream-K schedules),
@@ -350,11 +350,13 @@ def test_hemm_step_random_shapes(ctx, mode):
     from paper_1805_10121_amd import capi
 
     real = mode.startswith("real")
-    prec = {"fp64": capi.CHASE_FP64, "fp32": capi.CHASE_FP32, "fp32_3m": capi.CHASE_FP32_3M,
-            "real_fp64": capi.CHASE_REAL_FP64, "real_fp32": capi.CHASE_REAL_FP32}[mode]
+    prec = {"fp64": capi.CHASE_FP64, "fp64_3m": capi.CHASE_FP64_3M, "fp32": capi.CHASE_FP32,
+            "fp32_3m": capi.CHASE_FP32_3M, "real_fp64": capi.CHASE_REAL_FP64,
+            "real_fp32": capi.CHASE_REAL_FP32}[mode]
     single = mode in ("fp32", "fp32_3m", "real_fp32")
     tol = 5e-5 if single else 1e-13
-    g = wl.rng({"fp64": 1, "fp32": 2, "fp32_3m": 3, "real_fp64": 4, "real_fp32": 5}[mode] + 7000)
+    g = wl.rng({"fp64": 1, "fp32": 2, "fp32_3m": 3, "real_fp64": 4, "real_fp32": 5,
+                "fp64_3m": 6}[mode] + 7000)
     for case in range(8):
         n, nb = int(g.integers(1, 600)), int(g.integers(1, 200))
         ldh, ldx, ldo = (n + int(p) for p in g.integers(0, 4, 3))
@@ -385,6 +387,10 @@ def test_hemm_step_random_shapes(ctx, mode):
             dH64 = capi.to_device(Hp)
             dH = torch.empty(2 * ldh * n, dtype=torch.float32, device="cuda")
             ctx.chase_convert_c128_to_planar32(dH64, ldh, dH, ldh, n)
+        elif mode == "fp64_3m":
+            dH64 = capi.to_device(Hp)
+            dH = torch.empty(2 * ldh * n, dtype=torch.float64, device="cuda")
+            ctx.chase_convert_c128_to_planar64(dH64, ldh, dH, ldh, n)
         else:
             dH = capi.to_device(Hp.astype(dt))
         dX, dO = capi.to_device(Xp.astype(dt)), capi.to_device(Op.astype(dt))
@@ -394,3 +400,29 @@ def test_hemm_step_random_shapes(ctx, mode):
         assert np.all(got[n:] == 7.0)
         err = np.max(np.abs(got[:n].astype(ref.dtype) - ref)) / np.max(np.abs(ref))
         assert err <= tol, (mode, case, n, nb, err)
+
+
+@pytest.mark.parametrize("n,ld", [(1000, 1000), (333, 335), (130, 130)])
+def test_filter_fp64_3m_parity(ctx, n, ld):
+    """3M products on planar complex128 H (three FP64 MFMA products per complex product) against
+    the oracle at the FP64 filter bar (block-relative 1e-12), with sorted even degrees 2..36 so
+    that the active range shrinks over 36 products (wide, narrow and thin 3M tiles)."""
+    import torch
+    from paper_1805_10121_amd import capi
+
+    nb = 70
+    deg = wl.optimized_degree_profile(nb, 36)
+    lam, H, V = _problem(n, nb, 6000 + n)
+    b_sup, mu_1, mu_b = 2.02, lam[0], lam[min(n - 1, nb)]
+    ref = ch.filter_columns(H, V, deg, b_sup, mu_1, mu_b)
+    Hp = np.zeros((ld, n), dtype=np.complex128)
+    Hp[:n] = H
+    planes = torch.empty(2 * ld * n, dtype=torch.float64, device="cuda")
+    ctx.chase_convert_c128_to_planar64(capi.to_device(Hp), ld, planes, ld, n)
+    dV = capi.to_device(V)
+    dW = torch.empty_like(dV)
+    ctx.chase_filter(capi.CHASE_FP64_3M, planes, ld, n, dV, dW, n, nb, deg, b_sup, mu_1, mu_b)
+    torch.cuda.synchronize()
+    err = _relerr(capi.from_device(dV), ref)
+    print(f"fp64 3M n={n} ld={ld} block-relative error {err:.3e}")
+    assert err <= 1e-12
