@@ -103,6 +103,11 @@ typedef struct chase_config {
   int32_t real_symmetric;/* 1: H is real symmetric and V real, float64 (float32 under CHASE_FP32)
                             (the paper's real instances); leading dimensions count real elements.
                             0: complex Hermitian complex128 (complex64 under CHASE_FP32)    0    */
+  int32_t filter_3m;     /* complex128 data (FP64 and MIXED): 1 = the FP64 filter products and the
+                            Rayleigh-Ritz product H Q use the 3M scheme (CHASE_FP64_3M) on a
+                            planar copy of H made once per solve (16 n^2 bytes of workspace);
+                            0 = the 4M scheme on H itself, no copy.  Solves run by the server
+                            use 4M (their products are grouped across solves).            1     */
 } chase_config;
 
 /* Counters and timings of one solve (Sec. 6 reports iterations, matvecs and filter time). */

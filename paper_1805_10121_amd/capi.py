@@ -43,6 +43,7 @@ class chase_config(ctypes.Structure):
         ("resid_relative", _i32), ("intersperse", _i32), ("dos_sigma", _f64),
         ("seed", _u64), ("lanczos_start", _vp), ("have_mu", _i32),
         ("mu_1", _f64), ("mu_nevnex", _f64), ("verbose", _i32), ("real_symmetric", _i32),
+        ("filter_3m", _i32),
     ]
 
 

@@ -128,6 +128,7 @@ void chase_config_init(chase_config* cfg, int64_t n, int64_t nev, int64_t nex) {
   cfg->mu_nevnex = 0.0;
   cfg->verbose = 0;
   cfg->real_symmetric = 0;
+  cfg->filter_3m = 1;
 }
 
 void chase_config_init_fp32(chase_config* cfg, int64_t n, int64_t nev, int64_t nex) {

@@ -276,6 +276,7 @@ size_t state_bytes_of(const chase_config& c) {
 size_t ws_bytes_of(const chase_config& c, bool warm) {
   chase_config x = c;
   x.approx = warm ? 1 : c.approx;
+  x.filter_3m = 0;  // served solves group their products (4M): no planar copy of H
   return chase_workspace_bytes(&x);
 }
 

@@ -36,13 +36,15 @@ namespace {
 
 struct Layout {
   size_t V, W, AQ, X, G, T, P, lam, res, evE, perm, info, U, Wl, lal, lbe, zero, Z, tau, H32, V32,
-      W32;
+      W32, H64;
   size_t total;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~static_cast<size_t>(255); }
 
-Layout make_layout(int64_t n, int64_t nb, int64_t nv, int64_t k, bool mixed, int w, int esz) {
+// planar64: the planar complex128 copy of H for the FP64 3M products (16 n^2 bytes)
+Layout make_layout(int64_t n, int64_t nb, int64_t nv, int64_t k, bool mixed, int w, int esz,
+                   bool planar64) {
   Layout L{};
   const size_t es = static_cast<size_t>(esz) * w;  // bytes per element (esz: bytes per scalar)
   size_t off = 0;
@@ -78,6 +80,7 @@ Layout make_layout(int64_t n, int64_t nb, int64_t nv, int64_t k, bool mixed, int
     L.V32 = take(static_cast<size_t>(n) * nb * 4 * w);
     L.W32 = take(static_cast<size_t>(n) * nb * 4 * w);
   }
+  if (planar64) L.H64 = take(static_cast<size_t>(n) * n * 16);
   L.total = off;
   return L;
 }
@@ -108,6 +111,7 @@ class Solver {
   int64_t n_ = 0, nb_ = 0;
   int w_ = 2;             // values per element: 2 complex, 1 real
   bool real_ = false;
+  bool planar64_ = false;  // FP64 3M products on the planar copy of H at L_.H64
   hipStream_t s_ = nullptr;
   chase_stats st_{};
   int fallbacks_ = 0;
@@ -232,6 +236,12 @@ class Solver {
     const R a = static_cast<R>(alpha), b = static_cast<R>(beta), g = static_cast<R>(gamma);
     if (real_)
       return launch_hemm_step_real<R>(H, ldh, n_, X, ldx, OUT, ldo, ncols, a, b, g, ctx_->prod, s_);
+    if constexpr (kF64) {
+      // 3M on the planar copy for wide blocks (Rayleigh-Ritz); thin Lanczos blocks stay 4M
+      if (planar64_ && ncols > 16)
+        return launch_hemm_step_3m_f64(at<double>(L_.H64), n_, n_, X, ldx, OUT, ldo, ncols, alpha,
+                                       beta, gamma, ctx_->prod, s_);
+    }
     return launch_hemm_step<R>(H, ldh, n_, X, ldx, OUT, ldo, ncols, a, b, g, ctx_->prod, s_);
   }
   int lanczos(const R* H, int64_t ldh, R* V);
@@ -548,6 +558,11 @@ int Solver<R>::filter_mixed(const R* H, int64_t ldh, int64_t nlock, int64_t nact
       rc = hip(batcher_->run(0, H, ldh, n_, col(L_.V, nlock + n32), col(L_.W, nlock + n32), n_,
                              prods, s_, bev_[0], bev_[1]),
                "batched filter fp64");
+    } else if (planar64_) {  // 3M on the planar copy of H
+      rc = hip(run_filter<double>(at<double>(L_.H64), n_, n_, col(L_.V, nlock + n32),
+                                  col(L_.W, nlock + n32), n_, nact - n32, m.data() + n32, b_sup_,
+                                  mu_1_, mu_b_, ctx_->prod, s_, &mv, 4),
+               "filter fp64 3M");
     } else {
       rc = hip(run_filter<double>(H, ldh, n_, col(L_.V, nlock + n32), col(L_.W, nlock + n32), n_,
                                   nact - n32, m.data() + n32, b_sup_, mu_1_, mu_b_, ctx_->prod, s_,
@@ -568,12 +583,13 @@ int Solver<R>::run(const void* Hv, int64_t ldh, void* Vuser, int64_t ldv, double
   nb_ = cfg_.nev + cfg_.nex;
   real_ = cfg_.real_symmetric != 0;
   w_ = real_ ? 1 : 2;
+  planar64_ = kF64 && !real_ && cfg_.filter_3m != 0 && batcher_ == nullptr;
   s_ = ctx_->stream;
   const bool mixed = cfg_.precision == CHASE_MIXED;
   const bool need_dos = !cfg_.approx && !cfg_.have_mu;
   const int64_t nv = need_dos ? 1 + cfg_.num_lanczos : 1;
   const int64_t k = std::min<int64_t>(cfg_.lanczos_iter, n_);
-  L_ = make_layout(n_, nb_, nv, k, mixed, w_, static_cast<int>(sizeof(R)));
+  L_ = make_layout(n_, nb_, nv, k, mixed, w_, static_cast<int>(sizeof(R)), planar64_);
   int rc = ensure_workspace(ctx_, L_.total);
   if (rc) return rc;
   base_ = static_cast<char*>(ctx_->ws);
@@ -618,6 +634,10 @@ int Solver<R>::run(const void* Hv, int64_t ldh, void* Vuser, int64_t ldv, double
       return rc;
   }
   if constexpr (kF64) {
+    if (planar64_ &&
+        (rc = hip(launch_convert_c128_to_planar64(H, ldh, at<double>(L_.H64), n_, n_, s_),
+                  "planar H")))
+      return rc;
     if (mixed && real_ &&
         (rc = hip(launch_convert_f64_to_f32(H, ldh, at<float>(L_.H32), n_, n_, n_, s_),
                   "convert H")))
@@ -909,6 +929,8 @@ int check_config(chase_ctx* ctx, const chase_config* cfg) {
   if (!(cfg->dos_sigma > 0.0)) return set_error(ctx, CHASE_EINVAL, "dos_sigma must be positive");
   if (cfg->real_symmetric != 0 && cfg->real_symmetric != 1)
     return set_error(ctx, CHASE_EINVAL, "real_symmetric must be 0 or 1");
+  if (cfg->filter_3m != 0 && cfg->filter_3m != 1)
+    return set_error(ctx, CHASE_EINVAL, "filter_3m must be 0 or 1");
   if (cfg->have_mu && !cfg->approx &&
       !(std::isfinite(cfg->mu_1) && std::isfinite(cfg->mu_nevnex) && cfg->mu_1 < cfg->mu_nevnex))
     return set_error(ctx, CHASE_EINVAL, "need finite mu_1 < mu_nevnex");
@@ -975,8 +997,10 @@ size_t chase_workspace_bytes(const chase_config* cfg) {
   const int64_t nb = cfg->nev + cfg->nex;
   const int64_t nv = cfg->approx ? 1 : 1 + std::max<int64_t>(cfg->num_lanczos, 1);
   const int64_t k = std::min<int64_t>(std::max(cfg->lanczos_iter, 1), cfg->n);
+  const bool planar64 =
+      cfg->precision != CHASE_FP32 && !cfg->real_symmetric && cfg->filter_3m != 0;
   return make_layout(cfg->n, nb, nv, k, cfg->precision == CHASE_MIXED, solve_width(*cfg),
-                     solve_scalar_bytes(*cfg)).total;
+                     solve_scalar_bytes(*cfg), planar64).total;
 }
 
 int chase_solve(chase_ctx* ctx, const chase_config* cfg, const void* H, int64_t ldh, void* V,

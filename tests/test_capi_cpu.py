@@ -45,7 +45,7 @@ int main(void) {
   F(chase_config, approx) F(chase_config, tol) F(chase_config, precision)
   F(chase_config, switch_resid) F(chase_config, dos_sigma) F(chase_config, seed)
   F(chase_config, lanczos_start) F(chase_config, have_mu) F(chase_config, mu_nevnex)
-  F(chase_config, verbose) F(chase_config, real_symmetric)
+  F(chase_config, verbose) F(chase_config, real_symmetric) F(chase_config, filter_3m)
   F(chase_stats, matvecs) F(chase_stats, filter_flops) F(chase_stats, norm_est)
   return 0;
 }
@@ -60,7 +60,7 @@ int main(void) {
     assert int(vals["sizeof_config"]) == ctypes.sizeof(capi.chase_config)
     assert int(vals["sizeof_stats"]) == ctypes.sizeof(capi.chase_stats)
     for f in ["approx", "tol", "precision", "switch_resid", "dos_sigma", "seed", "lanczos_start",
-              "have_mu", "mu_nevnex", "verbose", "real_symmetric"]:
+              "have_mu", "mu_nevnex", "verbose", "real_symmetric", "filter_3m"]:
         assert int(vals[f]) == getattr(capi.chase_config, f).offset, f
     for f in ["matvecs", "filter_flops", "norm_est"]:
         assert int(vals[f]) == getattr(capi.chase_stats, f).offset, f
@@ -107,6 +107,20 @@ def test_config_init_fp32_table1_single_precision():
     capi.lib().chase_config_init_fp32(None, 1, 1, 0)  # NULL is ignored
 
 
+def test_workspace_bytes_planar_copy_for_3m():
+    # filter_3m = 1 (default) reserves the planar complex128 copy of H; 0 does not
+    from paper_1805_10121_amd import capi
+
+    n = 3000
+    on = capi.lib().chase_workspace_bytes(ctypes.byref(capi.config(n, 100, 20)))
+    off = capi.lib().chase_workspace_bytes(ctypes.byref(capi.config(n, 100, 20, filter_3m=0)))
+    real = capi.lib().chase_workspace_bytes(ctypes.byref(capi.config(n, 100, 20, real_symmetric=1)))
+    real_off = capi.lib().chase_workspace_bytes(
+        ctypes.byref(capi.config(n, 100, 20, real_symmetric=1, filter_3m=0)))
+    assert 16 * n * n <= on - off <= 16 * n * n + 256
+    assert real == real_off   # real data has no 3M form
+
+
 def test_workspace_bytes_fp32_half_of_fp64():
     from paper_1805_10121_amd import capi
 
@@ -116,9 +130,10 @@ def test_workspace_bytes_fp32_half_of_fp64():
         c32 = capi.config_fp32(n, 200, 40, real_symmetric=real)
         b64 = capi.lib().chase_workspace_bytes(ctypes.byref(c64))
         b32 = capi.lib().chase_workspace_bytes(ctypes.byref(c32))
-        # complex: plus the planar complex64 copy of H (8 n^2 bytes) for the 3M product
-        planar = 0 if real else 8 * n * n
-        assert 0.45 * b64 <= b32 - planar <= 0.55 * b64
+        # complex: each holds a planar copy of H for its 3M filter (16 n^2 bytes for complex128,
+        # 8 n^2 for complex64)
+        p64, p32 = (0, 0) if real else (16 * n * n, 8 * n * n)
+        assert 0.45 * (b64 - p64) <= b32 - p32 <= 0.55 * (b64 - p64)
 
 
 def test_create_without_gpu_fails_cleanly():
