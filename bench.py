@@ -141,6 +141,8 @@ def run_sequence(args):
     ctx = capi.Context(0)
     res = {}
     modes = [("fp64", capi.CHASE_FP64, None, None)] if "fp64" in args.modes else []
+    if "fp64_4m" in args.modes:   # the FP64 filter with 4M products on H itself (no planar copy)
+        modes.append(("fp64_4m", capi.CHASE_FP64, None, None))
     for sw in (args.switch_resid if "mixed" in args.modes else []):
         for dm in args.deg_max_fp32:
             name = "mixed" if (len(args.switch_resid) == 1 and len(args.deg_max_fp32) == 1) \
@@ -149,6 +151,8 @@ def run_sequence(args):
     for mode, prec, sw, dm in modes:
         cfg = capi.config(n, nev, nex, optim=1, precision=prec, seed=3000)
         cfg.verbose = 1
+        if mode == "fp64_4m":
+            cfg.filter_3m = 0
         if sw is not None:
             cfg.switch_resid = sw
             cfg.deg_max_fp32 = dm
@@ -395,7 +399,8 @@ def main():
                     default=["uniform_n1000", "clustered_n10000"],
                     choices=["uniform_n1000", "clustered_n10000", "sequence_n20000"],
                     help="ablation workload: which problems to run (cold start)")
-    ap.add_argument("--modes", nargs="*", default=["fp64", "mixed"], choices=["fp64", "mixed"],
+    ap.add_argument("--modes", nargs="*", default=["fp64", "mixed"],
+                    choices=["fp64", "fp64_4m", "mixed"],
                     help="sequence workload: which filters to run")
     ap.add_argument("--switch-resid", type=float, nargs="*", default=[1e-6],
                     help="sequence workload: mixed-mode switch thresholds to run")
