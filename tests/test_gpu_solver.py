@@ -286,3 +286,25 @@ def test_search_space_is_the_whole_space(ctx, precision):
     assert np.max(np.abs(ritzv[:nev] - lam[:nev])) <= tol * normH
     Y = capi.from_device(dV).astype(np.complex128)
     assert np.linalg.norm(Y[:, :nev].conj().T @ Y[:, :nev] - np.eye(nev)) <= (1e-4 if precision == "fp32" else 1e-12)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_filter_3m_off_and_on(ctx, precision):
+    # filter_3m = 0 (4M products on H itself) and 1 (3M on the planar copy, the default) both
+    # reach the prescribed spectrum; their Ritz values agree far inside the tolerance
+    from paper_1805_10121_amd import capi
+
+    n, nev, nex = 500, 30, 10
+    g = wl.rng(131)
+    lam = wl.spectrum_uniform(n, g)
+    H = wl.hermitian_from(wl.haar_unitary(n, g), lam)
+    V0, S = wl.complex_gaussian(g, n, nev + nex), wl.complex_gaussian(g, n, 5)
+    prec = capi.CHASE_MIXED if precision == "mixed" else capi.CHASE_FP64
+    res = {}
+    for f3m in (0, 1):
+        rc, st, ritzv, resid, Y = _gpu_solve(ctx, H, V0, S, nev=nev, optim=1, precision=prec,
+                                             filter_3m=f3m)
+        assert rc == 0
+        _check(H, lam, ritzv, Y, nev)
+        res[f3m] = ritzv[:nev]
+    assert np.max(np.abs(res[0] - res[1])) <= 1e-12 * np.max(np.abs(lam))
