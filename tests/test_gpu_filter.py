@@ -204,14 +204,29 @@ def test_filter_empty_and_invalid(ctx):
         assert ei.value.code == capi.CHASE_EINVAL
 
 
-def test_filter_full_size_sampled(ctx):
-    """Config-2 shape (n = 10000, nev + nex = 600), the launch configuration the benchmark
-    times; a sample of columns is checked against the oracle column by column."""
+def _filter_operand(ctx, dH, n, mode):
+    """(precision, H operand) for a filter call: the interleaved H itself for the 4M products,
+    or its planar copy (made here, H kept) for the 3M products."""
+    import torch
+    from paper_1805_10121_amd import capi
+
+    if mode == "fp64":
+        return capi.CHASE_FP64, dH
+    planes = torch.empty(2 * n * n, dtype=torch.float64, device="cuda")
+    ctx.chase_convert_c128_to_planar64(dH, n, planes, n, n)
+    return capi.CHASE_FP64_3M, planes
+
+
+@pytest.mark.parametrize("mode", ["fp64", "fp64_3m"])
+def test_filter_full_size_sampled(ctx, mode):
+    """Config-2 shape (n = 10000, nev + nex = 600) in both product schemes; the 3M one on the
+    planar copy of H is the launch configuration the benchmark times.  A sample of columns is
+    checked against the oracle column by column."""
     import torch
     from paper_1805_10121_amd import capi
 
     n, nb = 10000, 600
-    print("full-size filter: generating H on the device", flush=True)
+    print(f"full-size filter ({mode}): generating H on the device", flush=True)
     lam = wl.spectrum_for("clustered_n10000")
     dH = wl.hermitian_torch(n, lam, seed=2001)
     V = wl.start_block(n, nb, 2500)
@@ -219,9 +234,11 @@ def test_filter_full_size_sampled(ctx):
     b_sup, mu_1, mu_b = 2.05, float(lam[0]), float(lam[nb - 1])
     dV = capi.to_device(V)
     dW = torch.empty_like(dV)
+    prec, Hop = _filter_operand(ctx, dH, n, mode)
     print("full-size filter: running", flush=True)
-    ctx.chase_filter(capi.CHASE_FP64, dH, n, n, dV, dW, n, nb, deg, b_sup, mu_1, mu_b)
+    ctx.chase_filter(prec, Hop, n, n, dV, dW, n, nb, deg, b_sup, mu_1, mu_b)
     torch.cuda.synchronize()
+    del Hop
     H = capi.from_device(dH)
     cols = [0, 1, 299, 300, 598, 599]
     sub = capi.from_device(dV[cols])
@@ -231,14 +248,16 @@ def test_filter_full_size_sampled(ctx):
         assert np.linalg.norm(sub[:, k] - ref[:, k]) <= 1e-12 * np.linalg.norm(ref[:, k]) * 10
 
 
+@pytest.mark.parametrize("mode", ["fp64", "fp64_3m"])
 @pytest.mark.parametrize("n,nb,profile_max", [(20000, 1200, 36), (60000, 2400, 4)])
-def test_filter_large_orders_closed_form(ctx, n, nb, profile_max):
+def test_filter_large_orders_closed_form(ctx, n, nb, profile_max, mode):
     """Orders 20000 (1200 columns, degrees 2..36) and 60000 (2400 columns, degrees 2..4) on the
-    structured generator: every column against the closed form Qbar diag(p_m(lam)) Qbar^H v."""
+    structured generator, with 4M products on H and 3M products on its planar copy: every
+    column against the closed form Qbar diag(p_m(lam)) Qbar^H v."""
     import torch
     from paper_1805_10121_amd import capi
 
-    print(f"large-order filter n={n} nb={nb}: generating", flush=True)
+    print(f"large-order filter n={n} nb={nb} {mode}: generating", flush=True)
     lam = wl.spectrum_for("sequence_n60000" if n == 60000 else "sequence_n20000", n=n)
     dH = wl.hermitian_torch_fast(n, lam, seed=7000 + n)
     U, d = wl.structured_unitary(n, 7000 + n)
@@ -247,10 +266,15 @@ def test_filter_large_orders_closed_form(ctx, n, nb, profile_max):
     b_sup, mu_1, mu_b = float(lam[-1]) + 0.05, float(lam[0]), float(lam[nb - 1])
     dV = capi.to_device(V)
     dW = torch.empty_like(dV)
+    prec, Hop = _filter_operand(ctx, dH, n, mode)
+    if mode != "fp64":
+        del dH  # the planar copy is the only operand from here on
+        torch.cuda.empty_cache()
     print("large-order filter: running", flush=True)
-    ctx.chase_filter(capi.CHASE_FP64, dH, n, n, dV, dW, n, nb, deg, b_sup, mu_1, mu_b)
+    ctx.chase_filter(prec, Hop, n, n, dV, dW, n, nb, deg, b_sup, mu_1, mu_b)
     torch.cuda.synchronize()
-    del dH, dW
+    del Hop, dW
+    dH = None
     got = capi.from_device(dV)
     del dV
     torch.cuda.empty_cache()
@@ -261,7 +285,7 @@ def test_filter_large_orders_closed_form(ctx, n, nb, profile_max):
         Wq[:, cols] *= ch.p_closed(lam, int(m), b_sup, mu_1, mu_b)[:, None]
     ref = wl.apply_colmajor_q(U, d, Wq)
     err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
-    print(f"large-order filter n={n}: block-relative error {err:.3e}")
+    print(f"large-order filter n={n} {mode}: block-relative error {err:.3e}")
     assert err <= 1e-12
 
 
