@@ -176,15 +176,32 @@ def test_filter_deterministic(ctx):
     assert np.array_equal(outs[0], outs[1])
 
 
-def test_filter_empty_and_invalid(ctx):
+# per product mode: (precision name, element dtype, H elements per n x n matrix, H dtype)
+_MODES = {
+    "fp64": ("CHASE_FP64", "complex128", 1, "complex128"),
+    "fp64_3m": ("CHASE_FP64_3M", "complex128", 2, "float64"),
+    "fp32": ("CHASE_FP32", "complex64", 1, "complex64"),
+    "fp32_3m": ("CHASE_FP32_3M", "complex64", 2, "float32"),
+    "real_fp64": ("CHASE_REAL_FP64", "float64", 1, "float64"),
+    "real_fp32": ("CHASE_REAL_FP32", "float32", 1, "float32"),
+}
+
+
+@pytest.mark.parametrize("mode", list(_MODES))
+def test_filter_empty_and_invalid(ctx, mode):
+    """Zero columns is a no-op; every malformed call is rejected with CHASE_EINVAL before any
+    launch, in every product mode (for the planar 3M modes H spans both planes, so an output
+    inside the imaginary plane is an overlap)."""
     import torch
     from paper_1805_10121_amd import capi
 
+    pname, vdt, hmul, hdt = _MODES[mode]
+    prec = getattr(capi, pname)
     n = 64
-    dH = torch.zeros((n, n), dtype=torch.complex128, device="cuda")
-    dV = torch.zeros((4, n), dtype=torch.complex128, device="cuda")
+    dH = torch.zeros(hmul * n * n, dtype=getattr(torch, hdt), device="cuda")
+    dV = torch.zeros((4, n), dtype=getattr(torch, vdt), device="cuda")
     dW = torch.zeros_like(dV)
-    assert ctx.chase_filter(capi.CHASE_FP64, dH, n, n, dV, dW, n, 0, [], 2.0, -1.0, 0.0) == 0
+    assert ctx.chase_filter(prec, dH, n, n, dV, dW, n, 0, [], 2.0, -1.0, 0.0) == 0
     bad = [
         dict(deg=[2, 3, 4, 4]),                 # odd
         dict(deg=[4, 2, 4, 4]),                 # unsorted
@@ -193,14 +210,70 @@ def test_filter_empty_and_invalid(ctx):
         dict(bounds=(float("nan"), -1.0, 0.0)),
         dict(W=dV),                             # V and W overlap
         dict(ld=n - 1),
+        dict(ldh=n - 1),
+        dict(W=dH[(hmul * n * n) // 2:]),        # W inside H (its second half)
     ]
     for case in bad:
         deg = case.get("deg", [2, 2, 2, 2])
         bsup, m1, mb = case.get("bounds", (2.0, -1.0, 0.0))
         W = case.get("W", dW)
-        ld = case.get("ld", n)
+        ld, ldh = case.get("ld", n), case.get("ldh", n)
         with pytest.raises(capi.ChaseError) as ei:
-            ctx.chase_filter(capi.CHASE_FP64, dH, n, n, dV, W, ld, 4, deg, bsup, m1, mb)
+            ctx.chase_filter(prec, dH, ldh, n, dV, W, ld, 4, deg, bsup, m1, mb)
+        assert ei.value.code == capi.CHASE_EINVAL, (mode, case)
+
+
+@pytest.mark.parametrize("mode", list(_MODES))
+def test_hemm_step_empty_and_invalid(ctx, mode):
+    """chase_hemm_step: zero columns or order zero is a no-op; bad leading dimensions,
+    overlapping operands, a non-finite coefficient and the solver-only precision
+    CHASE_MIXED are rejected with CHASE_EINVAL before any launch."""
+    import torch
+    from paper_1805_10121_amd import capi
+
+    pname, vdt, hmul, hdt = _MODES[mode]
+    prec = getattr(capi, pname)
+    n = 64
+    dH = torch.zeros(hmul * n * n, dtype=getattr(torch, hdt), device="cuda")
+    dX = torch.zeros((4, n), dtype=getattr(torch, vdt), device="cuda")
+    dO = torch.zeros_like(dX)
+    assert ctx.chase_hemm_step(prec, dH, n, n, dX, n, dO, n, 0, 1.0, 0.0, 0.0) == 0
+    assert ctx.chase_hemm_step(prec, dH, n, 0, dX, n, dO, n, 4, 1.0, 0.0, 0.0) == 0
+    bad = [
+        dict(ldh=n - 1),
+        dict(ldx=n - 1),
+        dict(ldo=n - 1),
+        dict(O=dX),                              # X and OUT are the same block
+        dict(O=dH[(hmul * n * n) // 2:]),         # OUT inside H
+        dict(X=dH[(hmul * n * n) // 2:]),         # X inside H
+        dict(coef=(float("inf"), 0.0, 0.0)),
+        dict(coef=(1.0, float("nan"), 0.0)),
+        dict(prec=capi.CHASE_MIXED),
+        dict(ncols=-1),
+    ]
+    for case in bad:
+        a, b, g = case.get("coef", (1.0, 0.0, 0.0))
+        with pytest.raises(capi.ChaseError) as ei:
+            ctx.chase_hemm_step(case.get("prec", prec), dH, case.get("ldh", n), n,
+                                case.get("X", dX), case.get("ldx", n), case.get("O", dO),
+                                case.get("ldo", n), case.get("ncols", 4), a, b, g)
+        assert ei.value.code == capi.CHASE_EINVAL, (mode, case)
+
+
+def test_convert_planar64_invalid(ctx):
+    """chase_convert_c128_to_planar64: order zero is a no-op; short leading dimensions and
+    overlapping source and destination are rejected."""
+    import torch
+    from paper_1805_10121_amd import capi
+
+    n = 32
+    src = torch.zeros((n, n), dtype=torch.complex128, device="cuda")
+    dst = torch.zeros(2 * n * n, dtype=torch.float64, device="cuda")
+    assert ctx.chase_convert_c128_to_planar64(src, n, dst, n, 0) == 0
+    for args in [(src, n - 1, dst, n), (src, n, dst, n - 1),
+                 (src, n, torch.view_as_real(src).reshape(-1), n)]:
+        with pytest.raises(capi.ChaseError) as ei:
+            ctx.chase_convert_c128_to_planar64(*args, n)
         assert ei.value.code == capi.CHASE_EINVAL
 
 
