@@ -107,7 +107,7 @@ typedef struct chase_config {
                             Rayleigh-Ritz product H Q use the 3M scheme (CHASE_FP64_3M) on a
                             planar copy of H made once per solve (16 n^2 bytes of workspace);
                             0 = the 4M scheme on H itself, no copy.  Solves run by the server
-                            use 4M (their products are grouped across solves).            1     */
+                            follow the same setting in their grouped products.            1     */
 } chase_config;
 
 /* Counters and timings of one solve (Sec. 6 reports iterations, matvecs and filter time). */

@@ -1287,6 +1287,29 @@ hipError_t launch_hemm_group_3m(const GroupDesc<float>* descs, int count, hipStr
   return hipSuccess;
 }
 
+hipError_t launch_hemm_group_3m_f64(const GroupDesc<double>* descs, int count,
+                                    hipStream_t stream) {
+  using C = Wide3M64;
+  for (int base = 0; base < count; base += kMaxGroup) {
+    GroupArgs<double> a{};
+    a.count = std::min(kMaxGroup, count - base);
+    int64_t tiles = 0;
+    for (int q = 0; q < a.count; ++q) {
+      a.d[q] = descs[base + q];
+      a.d[q].tile_begin = static_cast<int>(tiles);
+      tiles += ((a.d[q].n + C::BMC - 1) / C::BMC) *
+               static_cast<int64_t>((a.d[q].ncols + C::BNC - 1) / C::BNC);
+    }
+    if (tiles == 0) continue;
+    if (tiles > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((hemm_group_kernel<double, C, kOcc, false>),
+                       dim3(static_cast<unsigned>(tiles)), dim3(kThreads), 0, stream, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 template hipError_t launch_hemm_step<double>(const double*, int64_t, int64_t, const double*,
                                              int64_t, double*, int64_t, int64_t, double, double,
                                              double, const ProductScratch&, hipStream_t);

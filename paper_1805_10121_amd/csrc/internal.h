@@ -71,6 +71,8 @@ hipError_t launch_hemm_step_3m_f64(const double* H, int64_t ldh, int64_t n, cons
                                    int64_t ldx, double* OUT, int64_t ldo, int64_t ncols,
                                    double alpha, double beta, double gamma,
                                    const ProductScratch& ps, hipStream_t stream);
+hipError_t launch_hemm_group_3m_f64(const GroupDesc<double>* descs, int count,
+                                    hipStream_t stream);
 hipError_t launch_convert_c128_to_planar64(const double* src, int64_t lds, double* dst,
                                            int64_t ldd, int64_t n, hipStream_t stream);
 hipError_t launch_convert_c128_to_planar32(const double* src, int64_t lds, float* dst, int64_t ldd,

@@ -30,7 +30,8 @@
 namespace chase {
 
 struct Batcher::Job {
-  int kind;  // 0 complex128, 1 complex64 interleaved H, 2 complex64 planar H (3M)
+  int kind;  // 0 complex128, 1 complex64 interleaved H, 2 complex64 planar H (3M),
+            // 3 complex128 planar H (3M)
   const void* H;
   int64_t ldh, n, ld;
   void* V;
@@ -132,11 +133,11 @@ hipError_t Batcher::Impl::tick_once() {
     hipError_t e = hipEventSynchronize(tick_ev[slot]);
     if (e != hipSuccess) return e;
   }
-  std::vector<GroupDesc<double>> d64;
+  std::vector<GroupDesc<double>> d64, d3m64;
   std::vector<GroupDesc<float>> d32, d3m;
   for (Job* j : active) {
     const FilterProduct& p = (*j->prods)[j->next];
-    if (j->kind == 0) {
+    if (j->kind == 0 || j->kind == 3) {
       const double* V = static_cast<const double*>(j->V);
       const double* W = static_cast<const double*>(j->W);
       GroupDesc<double> d{};
@@ -150,7 +151,7 @@ hipError_t Batcher::Impl::tick_once() {
       d.alpha = p.alpha;
       d.beta = p.beta;
       d.gamma = p.gamma;
-      d64.push_back(d);
+      (j->kind == 3 ? d3m64 : d64).push_back(d);
     } else {
       const float* V = static_cast<const float*>(j->V);
       const float* W = static_cast<const float*>(j->W);
@@ -175,14 +176,16 @@ hipError_t Batcher::Impl::tick_once() {
     e = launch_hemm_group<float>(d32.data(), static_cast<int>(d32.size()), stream);
   if (e == hipSuccess && !d3m.empty())
     e = launch_hemm_group_3m(d3m.data(), static_cast<int>(d3m.size()), stream);
+  if (e == hipSuccess && !d3m64.empty())
+    e = launch_hemm_group_3m_f64(d3m64.data(), static_cast<int>(d3m64.size()), stream);
   if (e == hipSuccess) e = hipEventRecord(tick_ev[slot], stream);
   tick_recorded[slot] = true;
   ++tick;
   {
     std::lock_guard<std::mutex> lk(mu);
     auto nl = [](size_t c) { return static_cast<int64_t>((c + kMaxGroup - 1) / kMaxGroup); };
-    launches += nl(d64.size()) + nl(d32.size()) + nl(d3m.size());
-    products += static_cast<int64_t>(d64.size() + d32.size() + d3m.size());
+    launches += nl(d64.size()) + nl(d32.size()) + nl(d3m.size()) + nl(d3m64.size());
+    products += static_cast<int64_t>(d64.size() + d32.size() + d3m.size() + d3m64.size());
   }
   return e;
 }
@@ -276,7 +279,6 @@ size_t state_bytes_of(const chase_config& c) {
 size_t ws_bytes_of(const chase_config& c, bool warm) {
   chase_config x = c;
   x.approx = warm ? 1 : c.approx;
-  x.filter_3m = 0;  // served solves group their products (4M): no planar copy of H
   return chase_workspace_bytes(&x);
 }
 

@@ -555,9 +555,13 @@ int Solver<R>::filter_mixed(const R* H, int64_t ldh, int64_t nlock, int64_t nact
       const auto prods = filter_schedule(nact - n32, m.data() + n32, b_sup_, mu_1_, mu_b_);
       mv = 0;
       for (const auto& p : prods) mv += p.ncols;
-      rc = hip(batcher_->run(0, H, ldh, n_, col(L_.V, nlock + n32), col(L_.W, nlock + n32), n_,
-                             prods, s_, bev_[0], bev_[1]),
-               "batched filter fp64");
+      rc = planar64_
+               ? hip(batcher_->run(3, at<double>(L_.H64), n_, n_, col(L_.V, nlock + n32),
+                                   col(L_.W, nlock + n32), n_, prods, s_, bev_[0], bev_[1]),
+                     "batched filter fp64 3M")
+               : hip(batcher_->run(0, H, ldh, n_, col(L_.V, nlock + n32), col(L_.W, nlock + n32),
+                                   n_, prods, s_, bev_[0], bev_[1]),
+                     "batched filter fp64");
     } else if (planar64_) {  // 3M on the planar copy of H
       rc = hip(run_filter<double>(at<double>(L_.H64), n_, n_, col(L_.V, nlock + n32),
                                   col(L_.W, nlock + n32), n_, nact - n32, m.data() + n32, b_sup_,
@@ -583,7 +587,7 @@ int Solver<R>::run(const void* Hv, int64_t ldh, void* Vuser, int64_t ldv, double
   nb_ = cfg_.nev + cfg_.nex;
   real_ = cfg_.real_symmetric != 0;
   w_ = real_ ? 1 : 2;
-  planar64_ = kF64 && !real_ && cfg_.filter_3m != 0 && batcher_ == nullptr;
+  planar64_ = kF64 && !real_ && cfg_.filter_3m != 0;
   s_ = ctx_->stream;
   const bool mixed = cfg_.precision == CHASE_MIXED;
   const bool need_dos = !cfg_.approx && !cfg_.have_mu;

@@ -23,7 +23,7 @@ def _sequences():
     return out
 
 
-def _run(seqs, order, precision):
+def _run(seqs, order, precision, filter_3m=1):
     import torch
     from paper_1805_10121_amd import capi
 
@@ -33,7 +33,8 @@ def _run(seqs, order, precision):
     tickets = []
     for sid, k in order:
         n, nev, nex, _ = seqs[sid]
-        cfg = capi.config(n, nev, nex, optim=1, seed=77 + sid, precision=precision)
+        cfg = capi.config(n, nev, nex, optim=1, seed=77 + sid, precision=precision,
+                          filter_3m=filter_3m)
         tickets.append((sid, k, srv.chase_server_submit(sid, cfg, dev[sid][k], n)))
     res = {}
     for sid, k, t in tickets:
@@ -49,16 +50,18 @@ def _run(seqs, order, precision):
     return res, vecs, info
 
 
-@pytest.mark.parametrize("precision_name", ["fp64", "mixed"])
-def test_alone_equals_mix(precision_name):
+@pytest.mark.parametrize("precision_name,filter_3m", [("fp64", 1), ("fp64", 0), ("mixed", 1)])
+def test_alone_equals_mix(precision_name, filter_3m):
+    """Grouped FP64 products in both schemes (3M on each solve's planar copy of H, the default,
+    and 4M on H itself) and the mixed solver's grouped FP32 3M and FP64 3M products."""
     from paper_1805_10121_amd import capi
 
     precision = capi.CHASE_FP64 if precision_name == "fp64" else capi.CHASE_MIXED
     seqs = _sequences()
     alone_order = [(12, 0), (12, 1), (12, 2)]
     mix_order = [(11, 0), (12, 0), (13, 0), (11, 1), (12, 1), (13, 1), (13, 2), (11, 2), (12, 2)]
-    a_res, a_vec, _ = _run(seqs, alone_order, precision)
-    m_res, m_vec, info = _run(seqs, mix_order, precision)
+    a_res, a_vec, _ = _run(seqs, alone_order, precision, filter_3m)
+    m_res, m_vec, info = _run(seqs, mix_order, precision, filter_3m)
     assert info["grouped_products"] > info["grouped_launches"] > 0
     for k in range(3):
         ra, rm = a_res[(12, k)], m_res[(12, k)]
