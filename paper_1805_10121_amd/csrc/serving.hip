@@ -3,8 +3,9 @@
 //
 //   Batcher  -- every solve that reaches its FILTER phase hands the products of its filter
 //               call (Alg. 4) to the batcher; each tick takes the next product of every
-//               submitted filter and runs them all in one grouped launch per precision.  New
-//               filter calls join at the next tick.  At most two ticks are in flight, so a
+//               submitted filter and runs them all in one grouped launch per product kind
+//               (FP64 or FP32, 4M on H or 3M on a planar copy).  New filter calls join at the
+//               next tick.  At most two ticks are in flight, so a
 //               newly arrived solve waits at most about two product times.
 //   Server   -- worker threads, each with its own context (HIP stream, rocBLAS handle,
 //               workspace), take requests first-come first-served subject to (a) problems of
