@@ -78,7 +78,7 @@ typedef struct chase_config {
   int32_t optim;         /* per-vector degrees (Alg. 5) instead of constant deg      0           */
   int32_t deg_extra;     /* DEGEXTRA of Alg. 5                                        2           */
   int32_t deg_max;       /* DEGMAX of Alg. 5                                          36          */
-  int32_t deg;           /* initial / constant degree (Alg. 1 line 1), rounded up to even 20     */
+  int32_t deg;           /* initial / constant degree (Alg. 1), rounded up to even    20          */
   int32_t lanczos_iter;  /* k of Alg. 6                                               25          */
   int32_t num_lanczos;   /* n_vec of Alg. 6                                           4           */
 
@@ -90,7 +90,7 @@ typedef struct chase_config {
                             largest |Ritz value| of the b_sup Lanczos run (a lower bound of
                             ||H||_2); 0: absolute Res <= tol as in the paper's experiments  1   */
   int32_t intersperse;   /* cold start: put Lanczos Ritz vectors below mu_{nev+nex} into the
-                            leading columns of the start block (Alg. 6 line 13)      1           */
+                            leading columns of the start block (Alg. 6)               1           */
   double dos_sigma;      /* Gaussian width of the DoS (Sec. 4.2), on the [-1, 1] scale 0.25      */
   uint64_t seed;         /* seed of the counter-based generator for Lanczos start vectors   0    */
   const void* lanczos_start; /* optional device n x (1 + num_lanczos) block (ld = n) of Lanczos
@@ -156,7 +156,7 @@ size_t chase_workspace_bytes(const chase_config* cfg);
  * For every column a of the n x ncols block V, replaces V[:, a] by p_{m_a}(H) V[:, a], where p_m
  * is the degree-m Chebyshev polynomial of Eq. (5) for the interval [mu_nevnex, b_sup] scaled so
  * that p_m(mu_1) = 1.  Product i of the recurrence (i = 1 .. max m) is one kernel launch
- * over the columns with m_a >= i (Alg. 4 lines 7-14); the two buffers swap after every
+ * over the columns with m_a >= i (Alg. 4, its recurrence loop); the two buffers swap after every
  * product.  Because all m_a are even, every column's last product lands in the buffer that
  * held the input, so the result is returned in V and W is scratch (Sec. 4.1.3).
  *
@@ -170,9 +170,9 @@ size_t chase_workspace_bytes(const chase_config* cfg);
  *              symmetric) storage (both triangles are read).  Read only.
  *   V          device, n x ncols, leading dimension ld >= n.  In: the block.  Out: the result.
  *   W          device, n x ncols, leading dimension ld, must not overlap V or H.  Scratch.
- *   degrees    host, ncols int32, sorted ascending, even, 2 <= m_a <= 64 (Alg. 1 line 15 and
- *              Alg. 5 line 6 establish these properties).
- *   b_sup, mu_1, mu_nevnex   the spectral bounds of Alg. 4 line 1; need mu_1 < mu_nevnex < b_sup.
+ *   degrees    host, ncols int32, sorted ascending, even, 2 <= m_a <= 64 (the sort of Alg. 1
+ *              and the even rounding of Alg. 5 establish these properties).
+ *   b_sup, mu_1, mu_nevnex   the spectral bounds Alg. 4 takes as input; need mu_1 < mu_nevnex < b_sup.
  * ncols == 0 is a no-op.  Enqueues only.
  */
 int chase_filter(chase_ctx* ctx, int precision, const void* H, int64_t ldh, int64_t n, void* V,
@@ -183,7 +183,7 @@ int chase_filter(chase_ctx* ctx, int precision, const void* H, int64_t ldh, int6
  * One fused product of the filter (the kernel behind every launch of chase_filter):
  *     OUT[:, j] <- alpha * H X[:, j] + gamma * X[:, j] + beta * OUT[:, j],   j < ncols
  * With beta == 0 the old OUT is not read (it may hold NaN).  Also serves the other products of
- * the outer loop: H Q for Rayleigh-Ritz (Alg. 2 line 2) and the Lanczos block (Alg. 6).
+ * the outer loop: H Q for Rayleigh-Ritz (Alg. 2) and the Lanczos block (Alg. 6).
  * X and OUT: device, n x ncols, leading dimensions ldx, ldo >= n; must not overlap each other
  * or H.  Types as in chase_filter.  Enqueues only.
  */

@@ -2,19 +2,19 @@
 
 Algorithm 1 of the paper, step by step, with
   * FILTER          -- ``chebyshev.filter_columns`` (Alg. 4 / Eq. (7), per column);
-  * ORTHOGONALIZE   -- Householder QR of [Y V] (``numpy.linalg.qr``; Alg. 1 lines 5-6);
+  * ORTHOGONALIZE   -- Householder QR of [Y V] (``numpy.linalg.qr``; Alg. 1);
   * RAYLEIGH-RITZ   -- Alg. 2 with TSOLVE = ``numpy.linalg.eigh``;
-  * residuals       -- Alg. 1 line 8, Res_a = ||A v_a - lambda_a v_a||_2;
+  * residuals       -- Alg. 1, Res_a = ||A v_a - lambda_a v_a||_2;
   * DEFLATION & LOCKING -- Alg. 3;
-  * interval update -- Alg. 1 lines 10-11;
+  * interval update -- Alg. 1 (new mu_1 and mu_{nev+nex}, then c and e);
   * DEGREES         -- Alg. 5 / Eq. (8);
-  * sort by degree  -- Alg. 1 line 15;
+  * sort by degree  -- Alg. 1 (last step of an iteration);
   * LANCZOS         -- Alg. 6 (``lanczos.lanczos_estimates``);
 and the sequence driver of Sec. 3.3 / Sec. 6.1 (solution of problem l-1 is the start of l).
 
 Readings (the paper is silent, ambiguous or garbled):
-  * Alg. 1 line 7 passes Q-hat to RAYLEIGH-RITZ; the active block Q-tilde is meant.
-  * Alg. 1 line 13 passes lambda_a; the Ritz value of the active vector is meant (Alg. 5 input).
+  * Alg. 1 passes Q-hat to RAYLEIGH-RITZ; the active block Q-tilde is meant.
+  * Alg. 1's call of DEGREES passes lambda_a; the Ritz value of the active vector is meant (Alg. 5 input).
   * The Rayleigh quotient G is symmetrised, (G + G^H)/2, before TSOLVE.
   * Residual test: relative by default, Res_a <= tol * ||A||_est with ||A||_est the largest
     |Ritz value| of the b_sup Lanczos run, fixed after LANCZOS.  Ritz values lie in
@@ -105,7 +105,7 @@ def rayleigh_ritz(A, Qt):
 
 
 def orthogonalize(Y, Vf):
-    """Alg. 1 lines 5-6: Householder QR of [Y V], keep the columns after Y."""
+    """ORTHOGONALIZE of Alg. 1: Householder QR of [Y V], keep the columns after Y."""
     Qh, _ = np.linalg.qr(np.hstack([Y, Vf]), mode="reduced")
     return Qh[:, Y.shape[1]:]
 
@@ -125,7 +125,7 @@ def solve(A, p: ChaseParams, V0, lanczos_starts, approx: bool = False, ritzv0=No
     nb = p.nev + p.nex
     V = np.array(V0, dtype=np.complex128, copy=True)
     deg0 = p.deg + (p.deg % 2)
-    m = np.full(nb, deg0, dtype=np.int64)                     # Alg. 1 line 1
+    m = np.full(nb, deg0, dtype=np.int64)                     # Alg. 1: initial degrees
 
     est = lanczos.lanczos_estimates(A, np.asarray(lanczos_starts), p.nev, p.nex,
                                     p.lanczos_iter, approx or mu is not None, p.dos_sigma)
@@ -151,29 +151,29 @@ def solve(A, p: ChaseParams, V0, lanczos_starts, approx: bool = False, ritzv0=No
     res = np.zeros(nb)
     it = 0
     filter_mv = 0
-    while Y.shape[1] < p.nev and it < p.max_iter:             # Alg. 1 line 3
+    while Y.shape[1] < p.nev and it < p.max_iter:             # Alg. 1: outer loop
         it += 1
         nact = V.shape[1]
-        Vf = chebyshev.filter_columns(A, V, m, b_sup, mu_1, mu_b)       # line 4
+        Vf = chebyshev.filter_columns(A, V, m, b_sup, mu_1, mu_b)       # FILTER
         filter_mv += int(m.sum())
-        Qt = orthogonalize(Y, Vf)                                         # lines 5-6
-        ritz, V, AV = rayleigh_ritz(A, Qt)                                # line 7
+        Qt = orthogonalize(Y, Vf)                                         # ORTHOGONALIZE
+        ritz, V, AV = rayleigh_ritz(A, Qt)                                # RAYLEIGH-RITZ
         matvecs += nact                                                   # H Q (A V = (H Q) W)
-        res = np.linalg.norm(AV - V * ritz[None, :], axis=0)             # line 8
-        n_new, order = lock(ritz, res, V, tol_eff)                       # line 9
+        res = np.linalg.norm(AV - V * ritz[None, :], axis=0)             # residuals
+        n_new, order = lock(ritz, res, V, tol_eff)                       # DEFLATION & LOCKING
         ritz, res, V = ritz[order], res[order], V[:, order]
         Y = np.hstack([Y, V[:, :n_new]])
         Lam = np.concatenate([Lam, ritz[:n_new]])
         Ylam_res = np.concatenate([Ylam_res, res[:n_new]])
         ritz, res, V = ritz[n_new:], res[n_new:], V[:, n_new:]
         allv = np.concatenate([Lam, ritz])
-        mu_1, mu_b = float(allv.min()), float(allv.max())                 # line 10
-        c, e = chebyshev.filter_interval(b_sup, mu_b)                     # line 11
-        if p.optim:                                                       # lines 12-14
+        mu_1, mu_b = float(allv.min()), float(allv.max())                 # interval
+        c, e = chebyshev.filter_interval(b_sup, mu_b)                     # c, e
+        if p.optim:                                                       # DEGREES
             m = degrees(tol_eff, res, ritz, c, e, p.deg_extra, p.deg_max)
         else:
             m = np.full(V.shape[1], deg0, dtype=np.int64)
-        srt = np.argsort(m, kind="stable")                                # line 15
+        srt = np.argsort(m, kind="stable")                                # sort by degree
         m, ritz, res, V = m[srt], ritz[srt], res[srt], V[:, srt]
     matvecs += filter_mv
 

@@ -35,7 +35,7 @@ def cheb_closed(m: int, t):
 
 
 def filter_interval(b_sup: float, mu_nevnex: float):
-    """Centre c and half-width e of [mu_{nev+nex}, b_sup] (Alg. 1 line 11, Alg. 4 line 2)."""
+    """Centre c and half-width e of [mu_{nev+nex}, b_sup] (Alg. 1's interval update, Alg. 4)."""
     c = 0.5 * (b_sup + mu_nevnex)
     e = 0.5 * (b_sup - mu_nevnex)
     return c, e
@@ -63,8 +63,8 @@ def filter_scalars(m_max: int, b_sup: float, mu_1: float, mu_nevnex: float):
     """Per-product coefficients of the filter, one row per product i = 1..m_max.
 
     Product i computes  OUT <- a_i * A @ X + g_i * X + b_i * Y  with
-      i = 1 : a_1 = sigma_1/e,            b_1 = 0,                    g_1 = -a_1*c   (Alg. 4 line 4)
-      i >= 2: tau = 1/(2/sigma_1 - sigma), a_i = 2*tau/e, b_i = -tau*sigma, g_i = -a_i*c (line 8-9)
+      i = 1 : a_1 = sigma_1/e,            b_1 = 0,                    g_1 = -a_1*c   (Alg. 4, first step)
+      i >= 2: tau = 1/(2/sigma_1 - sigma), a_i = 2*tau/e, b_i = -tau*sigma, g_i = -a_i*c (Alg. 4, recurrence)
     Returned as an (m_max, 3) array of (a_i, b_i, g_i).
     """
     c, e = filter_interval(b_sup, mu_nevnex)
@@ -109,8 +109,8 @@ def filter_columns(A, V, degrees, b_sup: float, mu_1: float, mu_nevnex: float):
 def filter_alg4(A, V, degrees, b_sup: float, mu_1: float, mu_nevnex: float):
     """Algorithm 4 as printed: two buffers swapped after every product, active columns s:end.
 
-    ``degrees`` must be sorted ascending and even (Alg. 5 line 6 guarantees evenness; Alg. 1
-    line 15 the sorting).  Returns the buffer the algorithm returns (W after the last swap).
+    ``degrees`` must be sorted ascending and even (Alg. 5 guarantees evenness, the sort
+    closing each iteration of Alg. 1 the order).  Returns the buffer the algorithm returns (W after the last swap).
     """
     Vb = np.array(V, dtype=np.complex128, copy=True)
     m = np.asarray(degrees, dtype=np.int64)
@@ -137,7 +137,7 @@ def filter_alg4(A, V, degrees, b_sup: float, mu_1: float, mu_nevnex: float):
 
 def product(A, X, Y, alpha: float, beta: float, gamma: float):
     """One product of the recurrence written out: alpha*A@X + gamma*X + beta*Y (Eq. (7) with the
-    shift (A - cI) expanded, as in Alg. 4 lines 4 and 9).  ``Y`` is ignored when beta == 0."""
+    shift (A - cI) expanded, as in the steps of Alg. 4).  ``Y`` is ignored when beta == 0."""
     out = alpha * (np.asarray(A) @ np.asarray(X)) + gamma * np.asarray(X)
     if beta != 0.0:
         out = out + beta * np.asarray(Y)

@@ -69,7 +69,7 @@ def tridiagonal(alpha, beta):
 
 
 def upper_bound(alpha, beta):
-    """b_sup = ||f_k||_2 + max(Ritz values of T_k) (Alg. 6 line 3)."""
+    """b_sup = ||f_k||_2 + max(Ritz values of T_k) (Alg. 6, the upper bound)."""
     ritz = np.linalg.eigvalsh(tridiagonal(alpha, beta))
     return float(beta[-1] + ritz.max())
 
@@ -79,7 +79,7 @@ def _phi_cdf(x):
 
 
 def dos_estimates(runs, b_sup: float, nev: int, nex: int, n: int, sigma: float = 0.25):
-    """mu_1 and mu_{nev+nex} from the averaged spectral density of Eq. (10) (Alg. 6 lines 10-12).
+    """mu_1 and mu_{nev+nex} from the averaged spectral density of Eq. (10) (Alg. 6, the DoS estimate).
 
     ``runs`` is a list of (alpha, beta) pairs, one per DoS Lanczos run.  The integral of the
     Gaussian-smoothed density is a sum of normal CDFs; t with integral (nev+nex)/n is found by
@@ -113,7 +113,7 @@ def dos_estimates(runs, b_sup: float, nev: int, nex: int, n: int, sigma: float =
 
 
 def ritz_vectors_below(alpha, beta, U, bound: float):
-    """Ritz vectors U z_i of one run whose Ritz values lie below ``bound`` (Alg. 6 line 13)."""
+    """Ritz vectors U z_i of one run whose Ritz values lie below ``bound`` (Alg. 6, the vectors it returns)."""
     lam, S = np.linalg.eigh(tridiagonal(alpha, beta))
     sel = lam < bound
     return U[:, : S.shape[0]] @ S[:, sel]

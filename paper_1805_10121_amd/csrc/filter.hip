@@ -3,10 +3,10 @@
 // products).
 //
 // The coefficients are scalars computed here in FP64 and passed to each launch:
-//   product 1:   W <- (sigma_1/e) (H - cI) V                      (Alg. 4 line 4)
-//   product i>1: V[:, s:] <- (2 tau/e)(H - cI) W[:, s:] - tau sigma V[:, s:], swap V, W   (lines 8-10)
+//   product 1:   W <- (sigma_1/e) (H - cI) V                      (Alg. 4, first step)
+//   product i>1: V[:, s:] <- (2 tau/e)(H - cI) W[:, s:] - tau sigma V[:, s:], swap V, W   (recurrence)
 // with sigma_1 = e/(mu_1 - c), tau = 1/(2/sigma_1 - sigma) and sigma <- tau.  The active range
-// starts at s, the first column whose degree exceeds the products done so far (lines 12-14);
+// starts at s, the first column whose degree exceeds the products done so far (Alg. 4's active range);
 // degrees are sorted, so the range is a contiguous suffix and one launch covers it.
 
 #include "internal.h"

@@ -1,6 +1,6 @@
 // Chebyshev-filter product kernels for gfx950 (CDNA4).
 //
-// One launch computes, for the active columns of the block (Alg. 4 lines 4 and 9, Eq. (7)),
+// One launch computes, for the active columns of the block (the steps of Alg. 4, Eq. (7)),
 //     OUT <- alpha * H X + gamma * X + beta * OUT
 // with H complex Hermitian n x n, X and OUT complex n x ncols, all column-major.  The shift
 // (A - cI) of Eq. (7) is the gamma = -alpha*c term, so H is never modified.

@@ -1,6 +1,6 @@
 // Small kernels of the outer loop (Algorithm 1): Lanczos vector updates (Alg. 6), column
-// normalisation, residual norms (Alg. 1 line 8), column gathers for locking and sorting
-// (Alg. 1 line 15, Alg. 3), Hermitian symmetrisation of the Rayleigh quotient (Alg. 2) and a
+// normalisation, residual norms (Alg. 1), column gathers for locking and sorting
+// (Alg. 1, Alg. 3), Hermitian symmetrisation of the Rayleigh quotient (Alg. 2) and a
 // counter-based Gaussian generator for Lanczos start vectors.
 //
 // Every reduction runs in one workgroup per column with a fixed-order tree, so results are

@@ -2,15 +2,15 @@
 //
 // Per iteration, all block data stay in device memory:
 //   FILTER            Alg. 4 on the active columns, FP64 or (mixed mode) FP32 per column group
-//   ORTHOGONALIZE     Alg. 1 lines 5-6: block Gram-Schmidt against the locked vectors, column
+//   ORTHOGONALIZE     Alg. 1: block Gram-Schmidt against the locked vectors, column
 //                     scaling, shifted Cholesky QR + two Cholesky QR passes; Householder QR of
 //                     [Y V] (rocSOLVER) if a Cholesky factorisation breaks down
 //   RAYLEIGH-RITZ     Alg. 2: H Q with the filter's product kernel, G = Q^H (H Q) (rocBLAS, K
 //                     split into slices so that the tall-skinny product fills the GPU),
 //                     TSOLVE = rocSOLVER zheevd, V = Q Z, H V = (H Q) Z
-//   residuals         Alg. 1 line 8, one fused kernel, then Ritz values and residual norms go to
+//   residuals         Alg. 1, one fused kernel, then Ritz values and residual norms go to
 //                     the host (the only per-iteration device-to-host transfer of results)
-//   host              Alg. 3 (locking), Alg. 1 lines 10-11 (interval), Alg. 5 (degrees), line 15
+//   host              Alg. 3 (locking), Alg. 1 (interval), Alg. 5 (degrees), Alg. 1
 //                     (sort); the new column order is applied on the device by one gather.
 // LANCZOS (Alg. 6) runs first: the b_sup run and the n_vec DoS runs are independent, so they
 // advance together as one block product per step.
@@ -300,7 +300,7 @@ int Solver<R>::lanczos(const R* H, int64_t ldh, R* V) {
     if (!std::isfinite(x)) return set_error(ctx_, CHASE_ENUMERIC, "Lanczos produced NaN/Inf");
 
   LanczosRun r0 = tridiag_eig(al, be, static_cast<int>(nv), 0, k);
-  b_sup_ = r0.beta_last + r0.ritz.back();                      // Alg. 6 line 3
+  b_sup_ = r0.beta_last + r0.ritz.back();                      // Alg. 6 upper bound
   norm_est_ = std::max(std::fabs(r0.ritz.front()), std::fabs(r0.ritz.back()));
   if (!need_dos) return CHASE_OK;
 
@@ -310,10 +310,10 @@ int Solver<R>::lanczos(const R* H, int64_t ldh, R* V) {
     runs.push_back(tridiag_eig(al, be, static_cast<int>(nv), c, k));
     lo = std::min(lo, runs.back().ritz.front());
   }
-  mu_1_ = lo;                                                   // Alg. 6 line 12
+  mu_1_ = lo;                                                   // Alg. 6 DoS estimate
   mu_b_ = dos_mu(runs, lo, b_sup_, cfg_.dos_sigma,
                  static_cast<double>(nb_) / static_cast<double>(n_));
-  if (cfg_.intersperse) {                                       // Alg. 6 line 13
+  if (cfg_.intersperse) {                                       // Alg. 6 returned vectors
     const LanczosRun& r1 = runs.front();
     std::vector<int> sel;
     for (int i = 0; i < r1.k; ++i)
@@ -652,7 +652,7 @@ int Solver<R>::run(const void* Hv, int64_t ldh, void* Vuser, int64_t ldv, double
       return rc;
   }
 
-  // ---------------------------------------------------------------- LANCZOS (Alg. 1 line 2)
+  // ---------------------------------------------------------------- LANCZOS (Alg. 1, Alg. 6)
   (void)hipEventRecord(ev[0], s_);
   if ((rc = lanczos(H, ldh, at<R>(L_.V)))) return rc;
   (void)hipEventRecord(ev[1], s_);
@@ -680,7 +680,7 @@ int Solver<R>::run(const void* Hv, int64_t ldh, void* Vuser, int64_t ldv, double
   const int deg0 = cfg_.deg + (cfg_.deg & 1);
   const int deg32max = cfg_.deg_max_fp32 + (cfg_.deg_max_fp32 & 1);
 
-  // ---------------------------------------------------------------- main loop (Alg. 1 line 3)
+  // ---------------------------------------------------------------- main loop (Alg. 1)
   const auto t_start = std::chrono::steady_clock::now();
   int64_t nlock = 0;
   std::vector<int> m(nb_, mixed ? std::min(deg0, deg32max) : deg0);
@@ -701,11 +701,11 @@ int Solver<R>::run(const void* Hv, int64_t ldh, void* Vuser, int64_t ldv, double
     for (int64_t a = 0; a < nact; ++a) any32 |= prec[a] == 1;
     if (any32) ++st_.fp32_iterations;
     (void)hipEventRecord(ev[0], s_);
-    if ((rc = filter(H, ldh, nlock, nact, m, prec))) return rc;             // line 4
+    if ((rc = filter(H, ldh, nlock, nact, m, prec))) return rc;             // FILTER
     (void)hipEventRecord(ev[1], s_);
-    if ((rc = orthogonalize(nlock, nact))) return rc;                       // lines 5-6
+    if ((rc = orthogonalize(nlock, nact))) return rc;                       // ORTHOGONALIZE
     (void)hipEventRecord(ev[2], s_);
-    // RAYLEIGH-RITZ (line 7, Alg. 2)
+    // RAYLEIGH-RITZ (Alg. 2)
     R* Q = col(L_.V, nlock);
     R* AQ = at<R>(L_.AQ);
     R* G = at<R>(L_.G);
@@ -743,7 +743,7 @@ int Solver<R>::run(const void* Hv, int64_t ldh, void* Vuser, int64_t ldv, double
                     nb_, 0.0, Xb, n_)))
       return rc;
     (void)hipEventRecord(ev[3], s_);
-    // residuals (line 8)
+    // residuals
     if ((rc = hip(launch_resid(Xb, Wb, at<R>(L_.lam), n_, n_, nact, at<double>(L_.res), s_,
                                w_),
                   "resid")))
@@ -774,7 +774,7 @@ int Solver<R>::run(const void* Hv, int64_t ldh, void* Vuser, int64_t ldv, double
       if (!std::isfinite(lam_act[a]) || !std::isfinite(res_act[a]))
         return set_error(ctx_, CHASE_ENUMERIC, "NaN/Inf in Ritz values or residuals");
 
-    // DEFLATION & LOCKING (line 9, Alg. 3): Ritz values arrive ascending from zheevd.
+    // DEFLATION & LOCKING (Alg. 3): Ritz values arrive ascending from zheevd.
     std::vector<int> order(nact);
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(),
@@ -785,7 +785,7 @@ int Solver<R>::run(const void* Hv, int64_t ldh, void* Vuser, int64_t ldv, double
       lam_lock.push_back(lam_act[order[q]]);
       res_lock.push_back(res_act[order[q]]);
     }
-    // interval update (lines 10-11)
+    // interval update
     double lo = INFINITY, hi = -INFINITY;
     for (double x : lam_lock) lo = std::min(lo, x), hi = std::max(hi, x);
     for (int64_t a = 0; a < nact; ++a) lo = std::min(lo, lam_act[a]), hi = std::max(hi, lam_act[a]);
@@ -793,7 +793,7 @@ int Solver<R>::run(const void* Hv, int64_t ldh, void* Vuser, int64_t ldv, double
     mu_b_ = hi;
     if (!(mu_b_ < b_sup_)) mu_b_ = b_sup_ - 1e-12 * std::fabs(b_sup_) - 1e-300;
     const double c = 0.5 * (b_sup_ + mu_b_), e = 0.5 * (b_sup_ - mu_b_);
-    // degrees (lines 12-14, Alg. 5) and precision groups
+    // degrees (Alg. 5) and precision groups
     const int64_t rem = nact - n_new;
     std::vector<int> mnew(rem), pnew(rem), idx(rem);
     std::vector<double> nres(rem);
@@ -821,7 +821,7 @@ int Solver<R>::run(const void* Hv, int64_t ldh, void* Vuser, int64_t ldv, double
       hist_fp32[q] = nfp32[q];
       lock64[q] = nl64[q];
     }
-    // sort (line 15): key (precision group: FP32 first, degree)
+    // sort: key (precision group: FP32 first, degree)
     std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) {
       if (pnew[x] != pnew[y]) return pnew[x] > pnew[y];
       return mnew[x] < mnew[y];

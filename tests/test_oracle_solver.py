@@ -31,7 +31,7 @@ GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
         (1.0, -1.1, 36, 36),
         # |t| < 1: |rho| = 1, the division by log 1 = 0 gives DEGMAX
         (1e-3, 0.3, 36, 36),
-        # odd DEGMAX: min(.., 35) = 35, made even -> 36 (literal reading of line 6)
+        # odd DEGMAX: min(.., 35) = 35, made even -> 36 (literal reading of Alg. 5's even rounding)
         (1.0, -1.1, 35, 36),
         # Res < tol: |log(1e-2)|/1.7627 = 2.61 -> 3; +2 = 5 -> even 6
         (1e-12, -3.0, 36, 6),
