@@ -410,6 +410,8 @@ def main():
                     help="serving workload: concurrent solves in the server")
     ap.add_argument("--serving-rates", type=float, nargs="*", default=[0.5, 0.8, 1.0],
                     help="serving workload: Poisson rates as fractions of the closed-loop rate")
+    ap.add_argument("--serving-precision", choices=["mixed", "fp64"], default="mixed",
+                    help="serving workload: filter precision of the served solves")
     ap.add_argument("--order", type=int, default=None,
                     help="sequence workload: order (default: the config's)")
     ap.add_argument("--h-gen", choices=["haar", "structured"], default="haar",
@@ -447,7 +449,8 @@ def main():
         return
     if args.workload == "serving":
         print(json.dumps(run_serving(problems=args.problems or 8, workers=args.serving_workers,
-                                     rates=tuple(args.serving_rates))),
+                                     rates=tuple(args.serving_rates),
+                                     precision_name=args.serving_precision)),
               flush=True)
         return
 
