@@ -9,7 +9,10 @@ Pins (tests/test_oracle_chebyshev.py):
     Eq. (5) evaluated at the eigenvalues;
   * ``sigma`` values against C_{m-1}(s)/C_m(s) with s = 1/sigma_1;
   * p_m(mu_1) = 1 (the normalisation of Eq. (5));
-  * ``filter_alg4`` (double-buffer transcription) against ``filter_columns`` (per-column).
+  * ``filter_alg4`` (double-buffer transcription) against ``filter_columns`` (per-column);
+  * ``product`` against a hand-computed 3 x 3 complex case (beta and gamma nonzero; a transposed
+    or conjugated matrix or swapped beta/gamma fails it), and composed with the rows of
+    ``filter_scalars`` and Alg. 4's buffer swap against ``filter_columns`` and Eq. (5).
 
 Readings where the paper is silent: (A - cI)X is formed as A@X - c*X (the matrix is never shifted
 in place); in Alg. 4 the loop over s stops at the end of the degree array; a column with m_a = i
@@ -137,7 +140,9 @@ def filter_alg4(A, V, degrees, b_sup: float, mu_1: float, mu_nevnex: float):
 
 def product(A, X, Y, alpha: float, beta: float, gamma: float):
     """One product of the recurrence written out: alpha*A@X + gamma*X + beta*Y (Eq. (7) with the
-    shift (A - cI) expanded, as in the steps of Alg. 4).  ``Y`` is ignored when beta == 0."""
+    shift (A - cI) expanded, as in the steps of Alg. 4).  ``Y`` is ignored when beta == 0.
+
+    Pinned by the hand-computed case and the composition test in tests/test_oracle_chebyshev.py."""
     out = alpha * (np.asarray(A) @ np.asarray(X)) + gamma * np.asarray(X)
     if beta != 0.0:
         out = out + beta * np.asarray(Y)

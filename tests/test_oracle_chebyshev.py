@@ -162,3 +162,80 @@ def test_filter_on_real_symmetric_matrix():
     for a in range(nb):
         ref = Q @ (p_lib(lam, int(deg[a]), 1.05, lam[0], lam[12]) * (Q.T @ V[:, a]))
         assert np.linalg.norm(out[:, a].real - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
+# ----------------------------------------------------------------------------------------------
+# oracle.chebyshev.product: one fused step  alpha*A@X + gamma*X + beta*Y  (Eq. (7) with the shift
+# expanded; the steps of Alg. 4).  It is the reference of every single-product GPU test, so it is
+# pinned on its own: a hand-computed case, and its composition into the whole filter.
+
+# Hand-computed 3 x 3 case with integer entries: A Hermitian and not real (so A^T = conj(A) != A),
+# beta != gamma, both nonzero.  A @ X, worked out by hand:
+#   column 0: (4+2j, 5-1j, 3j);  column 1: (2j, 1-1j, 1)
+# and with alpha = 2, beta = -3, gamma = 0.5:  2*A@X + 0.5*X - 3*Y  is _OUT below.
+_A3 = np.array([[2, 1 + 1j, 0], [1 - 1j, 3, -2j], [0, 2j, 1]], dtype=np.complex128)
+_X3 = np.array([[1, 1j], [2, 0], [-1j, 1]], dtype=np.complex128)
+_Y3 = np.array([[1, 0], [0, 1], [1j, -1]], dtype=np.complex128)
+_OUT = np.array([[5.5 + 4j, 4.5j], [11 - 2j, -1 - 2j], [2.5j, 5.5]], dtype=np.complex128)
+
+
+def test_product_hand_computed():
+    got = ch.product(_A3, _X3, _Y3, 2.0, -3.0, 0.5)
+    assert np.array_equal(got, _OUT)
+    # beta == 0: Y is not read (NaN there must not reach the result)
+    nan_y = np.full_like(_Y3, np.nan)
+    got0 = ch.product(_A3, _X3, nan_y, 2.0, 0.0, 0.5)
+    assert np.array_equal(got0, _OUT + 3.0 * _Y3)
+
+
+def test_product_fixture_rejects_plausible_mistakes():
+    # The hand-computed case must tell apart a transposed or conjugated A and swapped beta/gamma.
+    wrong = [
+        ch.product(_A3.T, _X3, _Y3, 2.0, -3.0, 0.5),
+        ch.product(_A3.conj(), _X3, _Y3, 2.0, -3.0, 0.5),
+        ch.product(_A3, _X3, _Y3, 2.0, 0.5, -3.0),
+        ch.product(_A3, _Y3, _X3, 2.0, -3.0, 0.5),
+    ]
+    for w in wrong:
+        assert np.max(np.abs(w - _OUT)) >= 1.0
+
+
+def _filter_by_products(A, V, degrees, b_sup, mu_1, mu_b):
+    """Alg. 4 written with oracle.chebyshev.product and the rows of filter_scalars: product 1 into
+    W, then V[:, s:] <- product(A, W[:, s:], V[:, s:], row i) and a swap of the two buffers."""
+    m = np.asarray(degrees)
+    rows = ch.filter_scalars(int(m[-1]), b_sup, mu_1, mu_b)
+    Vb = np.array(V, dtype=np.complex128, copy=True)
+    a, b, g = rows[0]
+    Wb = ch.product(A, Vb, None, a, b, g)
+    s = 0
+    for i in range(2, int(m[-1]) + 1):
+        a, b, g = rows[i - 1]
+        Vb[:, s:] = ch.product(A, Wb[:, s:], Vb[:, s:], a, b, g)
+        Vb, Wb = Wb, Vb
+        while s < m.size and m[s] <= i:
+            s += 1
+    return Wb
+
+
+@pytest.mark.parametrize("kind", ["diagonal", "unitary"])
+def test_products_compose_to_the_filter(kind):
+    g = wl.rng(31)
+    n, nb = 70, 11
+    lam = np.sort(g.uniform(-1.0, 2.0, n))
+    b_sup, mu_1, mu_b = 2.04, float(lam[0]), float(lam[12])
+    if kind == "diagonal":
+        Q = np.eye(n, dtype=np.complex128)
+        A = np.diag(lam).astype(np.complex128)
+    else:
+        Q = wl.haar_unitary(n, g)
+        A = wl.hermitian_from(Q, lam)
+    V = wl.complex_gaussian(g, n, nb)
+    deg = np.sort(2 * g.integers(1, 19, nb))
+    got = _filter_by_products(A, V, deg, b_sup, mu_1, mu_b)
+    per_col = ch.filter_columns(A, V, deg, b_sup, mu_1, mu_b)
+    closed = np.empty_like(V)
+    for a in range(nb):
+        closed[:, a] = Q @ (p_lib(lam, int(deg[a]), b_sup, mu_1, mu_b) * (Q.conj().T @ V[:, a]))
+    assert np.linalg.norm(got - per_col) <= 1e-13 * np.linalg.norm(per_col)
+    assert np.linalg.norm(got - closed) <= 1e-13 * np.linalg.norm(closed)
