@@ -92,6 +92,24 @@ int check_product_args(chase_ctx* ctx, int precision, const void* H, int64_t ldh
   return CHASE_OK;
 }
 
+hipError_t run_filter_precision(int precision, const void* H, int64_t ldh, int64_t n, void* V,
+                                void* W, int64_t ld, int64_t ncols, const int32_t* degrees,
+                                double b_sup, double mu_1, double mu_nevnex,
+                                const ProductScratch& ps, hipStream_t stream) {
+  if (precision == CHASE_FP64 || precision == CHASE_REAL_FP64 || precision == CHASE_FP64_3M)
+    return run_filter<double>(static_cast<const double*>(H), ldh, n, static_cast<double*>(V),
+                              static_cast<double*>(W), ld, ncols, degrees, b_sup, mu_1, mu_nevnex,
+                              ps, stream, nullptr,
+                              precision == CHASE_REAL_FP64 ? 3 : precision == CHASE_FP64_3M ? 4 : 0);
+  if (precision == CHASE_REAL_FP32)
+    return run_filter<float>(static_cast<const float*>(H), ldh, n, static_cast<float*>(V),
+                             static_cast<float*>(W), ld, ncols, degrees, b_sup, mu_1, mu_nevnex,
+                             ps, stream, nullptr, 3);
+  return run_filter<float>(static_cast<const float*>(H), ldh, n, static_cast<float*>(V),
+                           static_cast<float*>(W), ld, ncols, degrees, b_sup, mu_1, mu_nevnex, ps,
+                           stream, nullptr, precision == CHASE_FP32_3M ? 2 : 1);
+}
+
 }  // namespace chase
 
 using namespace chase;
@@ -217,20 +235,8 @@ int chase_filter(chase_ctx* ctx, int precision, const void* H, int64_t ldh, int6
   if ((rc = check_degrees(ctx, degrees, ncols))) return rc;
   if ((rc = check_bounds(ctx, b_sup, mu_1, mu_nevnex))) return rc;
   CHASE_HIP_TRY(ctx, hipSetDevice(ctx->device));
-  hipError_t e;
-  if (precision == CHASE_FP64 || precision == CHASE_REAL_FP64 || precision == CHASE_FP64_3M)
-    e = run_filter<double>(static_cast<const double*>(H), ldh, n, static_cast<double*>(V),
-                           static_cast<double*>(W), ld, ncols, degrees, b_sup, mu_1, mu_nevnex,
-                           ctx->prod, ctx->stream, nullptr,
-                           precision == CHASE_REAL_FP64 ? 3 : precision == CHASE_FP64_3M ? 4 : 0);
-  else if (precision == CHASE_REAL_FP32)
-    e = run_filter<float>(static_cast<const float*>(H), ldh, n, static_cast<float*>(V),
-                          static_cast<float*>(W), ld, ncols, degrees, b_sup, mu_1, mu_nevnex,
-                          ctx->prod, ctx->stream, nullptr, 3);
-  else
-    e = run_filter<float>(static_cast<const float*>(H), ldh, n, static_cast<float*>(V),
-                          static_cast<float*>(W), ld, ncols, degrees, b_sup, mu_1, mu_nevnex,
-                          ctx->prod, ctx->stream, nullptr, precision == CHASE_FP32_3M ? 2 : 1);
+  const hipError_t e = run_filter_precision(precision, H, ldh, n, V, W, ld, ncols, degrees, b_sup,
+                                            mu_1, mu_nevnex, ctx->prod, ctx->stream);
   if (e != hipSuccess)
     return set_error(ctx, CHASE_EDEVICE, std::string("filter launch: ") + hipGetErrorString(e));
   return CHASE_OK;

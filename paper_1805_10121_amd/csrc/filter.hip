@@ -20,8 +20,10 @@ hipError_t run_filter(const T* H, int64_t ldh, int64_t n, T* V, T* W, int64_t ld
                       int kind) {
   int64_t matvecs = 0;
   const int ew = kind == 3 ? 1 : 2;  // values per element
+  hipError_t status = hipSuccess;
   if (ncols > 0 && n > 0) {
-    for (const FilterProduct& p : filter_schedule(ncols, degrees, b_sup, mu_1, mu_nevnex)) {
+    for_each_filter_product(ncols, degrees, b_sup, mu_1, mu_nevnex, [&](const FilterProduct& p) {
+      if (status != hipSuccess) return;
       const T* X = (p.from_v ? V : W) + ew * p.col0 * ld;
       T* OUT = (p.from_v ? W : V) + ew * p.col0 * ld;
       hipError_t err;
@@ -42,10 +44,14 @@ hipError_t run_filter(const T* H, int64_t ldh, int64_t n, T* V, T* W, int64_t ld
         err = launch_hemm_step<T>(H, ldh, n, X, ld, OUT, ld, p.ncols, static_cast<T>(p.alpha),
                                   static_cast<T>(p.beta), static_cast<T>(p.gamma), ps, stream);
       }
-      if (err != hipSuccess) return err;
+      if (err != hipSuccess) {
+        status = err;
+        return;
+      }
       matvecs += p.ncols;
-    }
+    });
   }
+  if (status != hipSuccess) return status;
   if (matvecs_out) *matvecs_out = matvecs;
   return hipSuccess;
 }

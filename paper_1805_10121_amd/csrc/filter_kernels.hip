@@ -1126,6 +1126,10 @@ hipError_t launch_sched(const T* H, int64_t ldh, int64_t n, const T* X, int64_t 
   const int64_t slots = static_cast<int64_t>(ps.cus) * OCC;
   const int64_t rounds = (tiles + slots - 1) / slots;
   const double eff = static_cast<double>(tiles) / static_cast<double>(rounds * slots);
+  if (ps.sk_need) {
+    if (eff < 0.92) *ps.sk_need = std::max(*ps.sk_need, sk_scratch_bytes<T, C>(slots));
+    return hipSuccess;
+  }
   const bool v16 = v16_ok && wide_loads<T, C>(H, ldh, X, ldx, n);
   if (eff >= 0.92 || !ps.ptr || sk_scratch_bytes<T, C>(slots) > ps.bytes) {
     if (v16)

@@ -90,18 +90,19 @@ struct FilterProduct {
   double alpha, beta, gamma;
 };
 
-// The products of one filter call on sorted even degrees (the recurrence scalars of Eq. (7)).
-inline std::vector<FilterProduct> filter_schedule(int64_t ncols, const int32_t* degrees, double b_sup,
-                                           double mu_1, double mu_nevnex) {
-  std::vector<FilterProduct> out;
-  if (ncols <= 0) return out;
+// The products of one filter call on sorted even degrees (the recurrence scalars of Eq. (7)),
+// handed one by one to fn(const FilterProduct&) without building a list (no allocation).
+template <class Fn>
+inline void for_each_filter_product(int64_t ncols, const int32_t* degrees, double b_sup,
+                                    double mu_1, double mu_nevnex, Fn&& fn) {
+  if (ncols <= 0) return;
   const double c = 0.5 * (b_sup + mu_nevnex);
   const double e = 0.5 * (b_sup - mu_nevnex);
   const double sigma1 = e / (mu_1 - c);
   const int32_t m_max = degrees[ncols - 1];
   // product 1, every column: W <- a1 H V + g1 V
   double alpha = sigma1 / e;
-  out.push_back({/*from_v=*/true, 0, ncols, alpha, 0.0, -alpha * c});
+  fn(FilterProduct{/*from_v=*/true, 0, ncols, alpha, 0.0, -alpha * c});
   bool in_is_w = true;  // p_{i-1} lives in W, p_{i-2} in V
   double sigma = sigma1;
   int64_t s = 0;
@@ -109,12 +110,20 @@ inline std::vector<FilterProduct> filter_schedule(int64_t ncols, const int32_t* 
   for (int32_t i = 2; i <= m_max; ++i) {
     const double tau = 1.0 / (2.0 / sigma1 - sigma);
     alpha = 2.0 * tau / e;
-    out.push_back({/*from_v=*/!in_is_w, s, ncols - s, alpha, -tau * sigma, -alpha * c});
+    fn(FilterProduct{/*from_v=*/!in_is_w, s, ncols - s, alpha, -tau * sigma, -alpha * c});
     in_is_w = !in_is_w;
     sigma = tau;
     while (s < ncols && degrees[s] <= i) ++s;
   }
   // m_max is even, so the last product wrote V.
+}
+
+// The same products as a list.
+inline std::vector<FilterProduct> filter_schedule(int64_t ncols, const int32_t* degrees, double b_sup,
+                                                  double mu_1, double mu_nevnex) {
+  std::vector<FilterProduct> out;
+  for_each_filter_product(ncols, degrees, b_sup, mu_1, mu_nevnex,
+                          [&](const FilterProduct& p) { out.push_back(p); });
   return out;
 }
 

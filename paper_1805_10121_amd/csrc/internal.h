@@ -18,6 +18,10 @@ struct ProductScratch {
   void* ptr = nullptr;
   size_t bytes = 0;
   int cus = 0;  // compute units of the device
+  // Dry run: when set, the product launchers enqueue nothing and raise *sk_need to the
+  // partial-sum bytes the stream-K schedule they would choose needs (0 for a data-parallel
+  // grid), so a caller with a fixed scratch can check a whole filter call before launching it.
+  size_t* sk_need = nullptr;
 };
 size_t product_scratch_bytes(int cus);
 
@@ -175,6 +179,16 @@ class Batcher;
 int solve_with(chase_ctx* ctx, const chase_config* cfg, const void* H, int64_t ldh, void* V,
                int64_t ldv, double* ritzv, double* resid, chase_stats* stats, Batcher* batcher);
 int check_config(chase_ctx* ctx, const chase_config* cfg);
+// Argument checks of chase_filter / chase_hemm_step (messages go to ctx->last_error).
+int check_product_args(chase_ctx* ctx, int precision, const void* H, int64_t ldh, int64_t n,
+                       const void* X, int64_t ldx, const void* OUT, int64_t ldo, int64_t ncols);
+int check_degrees(chase_ctx* ctx, const int32_t* degrees, int64_t ncols);
+int check_bounds(chase_ctx* ctx, double b_sup, double mu_1, double mu_nevnex);
+// Algorithm 4 in the given chase_precision (checked beforehand), products on `ps`.
+hipError_t run_filter_precision(int precision, const void* H, int64_t ldh, int64_t n, void* V,
+                                void* W, int64_t ld, int64_t ncols, const int32_t* degrees,
+                                double b_sup, double mu_1, double mu_nevnex,
+                                const ProductScratch& ps, hipStream_t stream);
 // Layout of a solve's H and V elements: bytes per real scalar (8, or 4 for CHASE_FP32) and
 // values per element (2 complex, 1 real symmetric).
 inline int solve_scalar_bytes(const chase_config& c) { return c.precision == CHASE_FP32 ? 4 : 8; }
