@@ -180,6 +180,29 @@ int chase_filter(chase_ctx* ctx, int precision, const void* H, int64_t ldh, int6
                  double mu_1, double mu_nevnex);
 
 /*
+ * chase_filter for callers that cannot allocate device memory: code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc.  Same operation, arguments and result
+ * as chase_filter (bitwise the same products), but it needs no context and allocates nothing:
+ * no hipMalloc, hipFree or allocating library call.
+ *
+ *   device, hip_stream  the HIP device (made current by the call) and a hipStream_t on it to
+ *              enqueue on (NULL: the device's null stream).
+ *   precision .. mu_nevnex   as in chase_filter.
+ *   err        host buffer of err_len bytes for an error message (may be NULL); "" on success.
+ * The stream-K partial sums of the products live in a fixed 64 MiB device array that the library
+ * holds on every GPU it runs on until the process ends.  The first call on a device (an empty
+ * call, ncols = 0, is enough; make it before any graph capture) looks the array's address up.
+ * A call whose products would need more than 64 MiB of partial sums -- on a 256-CU device only
+ * CHASE_REAL_FP64 on more than 16 columns can -- returns CHASE_EINVAL with nothing enqueued.
+ * Calls that overlap on one GPU share the array and race: order them on one stream.
+ * Returns CHASE_OK, CHASE_EINVAL (argument errors, nothing enqueued) or CHASE_EDEVICE.
+ */
+int chase_filter_noalloc(int device, void* hip_stream, int precision, const void* H,
+                         int64_t ldh, int64_t n, void* V, void* W, int64_t ld, int64_t ncols,
+                         const int32_t* degrees, double b_sup, double mu_1, double mu_nevnex,
+                         char* err, size_t err_len);
+
+/*
  * One fused product of the filter (the kernel behind every launch of chase_filter):
  *     OUT[:, j] <- alpha * H X[:, j] + gamma * X[:, j] + beta * OUT[:, j],   j < ncols
  * With beta == 0 the old OUT is not read (it may hold NaN).  Also serves the other products of

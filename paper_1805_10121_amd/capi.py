@@ -70,6 +70,9 @@ _PROTOTYPES = {
     "chase_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(chase_config)]),
     "chase_filter": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _i64, _i64, _vp, _vp, _i64, _i64,
                                     ctypes.POINTER(_i32), _f64, _f64, _f64]),
+    "chase_filter_noalloc": (ctypes.c_int, [ctypes.c_int, _vp, ctypes.c_int, _vp, _i64, _i64, _vp,
+                                            _vp, _i64, _i64, ctypes.POINTER(_i32), _f64, _f64,
+                                            _f64, ctypes.c_char_p, ctypes.c_size_t]),
     "chase_hemm_step": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _i64, _i64, _vp, _i64, _vp, _i64,
                                        _i64, _f64, _f64, _f64]),
     "chase_convert_c128_to_c64": (ctypes.c_int, [_vp, _vp, _i64, _vp, _i64, _i64, _i64]),
@@ -330,6 +333,21 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def chase_filter_noalloc(device, stream, precision, H, ldh, n, V, W, ld, ncols, degrees, b_sup,
+                         mu_1, mu_nevnex):
+    """chase_filter without a context and without device allocation; ``stream`` is a torch
+    CUDA stream on ``device`` (None: the null stream)."""
+    deg = (_i32 * max(int(ncols), 1))(*[int(x) for x in degrees])
+    err = ctypes.create_string_buffer(512)
+    rc = lib().chase_filter_noalloc(
+        int(device), ctypes.c_void_p(stream.cuda_stream if stream is not None else 0), precision,
+        _ptr(H), ldh, n, _ptr(V), _ptr(W), ld, ncols, deg, float(b_sup), float(mu_1),
+        float(mu_nevnex), err, len(err))
+    if rc < 0:
+        raise ChaseError(rc, err.value.decode())
+    return rc
 
 
 # ----------------------------------------------------------------------------- layout helpers

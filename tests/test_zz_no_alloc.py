@@ -1,0 +1,94 @@
+"""chase_filter_noalloc (the filter for callers that cannot allocate device memory) against
+chase_filter, through the C ABI.
+
+Both entry points run the same products with the same stream-K schedule; only the partial-sum
+scratch differs (the context's allocation against the library's static device array), so the
+results must be bitwise equal.  The oracle (Alg. 4, Eq. (7)) is checked on sampled columns at the
+FP64 filter bar, 1e-12 block-relative.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import chebyshev as ch
+from paper_1805_10121_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def _problem(n, nb, seed):
+    g = wl.rng(seed)
+    lam = np.sort(g.uniform(-1.0, 2.0, n))
+    H = wl.hermitian_from(wl.haar_unitary(n, g), lam)
+    V = wl.complex_gaussian(g, n, nb)
+    deg = wl.optimized_degree_profile(nb, 36)
+    return lam, H, V, deg
+
+
+def _run_pair(capi, ctx, precision, n, nb, seed, planar):
+    import torch
+
+    lam, H, V, deg = _problem(n, nb, seed)
+    b_sup, mu_1, mu_b = 2.02, float(lam[0]), float(lam[nb - 1])
+    dH = capi.to_device(H)
+    if planar:
+        Hd = torch.empty(2 * n * n, dtype=torch.float64, device="cuda")
+        ctx.chase_convert_c128_to_planar64(dH, n, Hd, n, n)
+    else:
+        Hd = dH
+    dV1, dV2 = capi.to_device(V), capi.to_device(V)
+    dW1, dW2 = torch.empty_like(dV1), torch.full_like(dV2, float("nan"))
+    ctx.chase_filter(precision, Hd, n, n, dV1, dW1, n, nb, deg, b_sup, mu_1, mu_b)
+    capi.chase_filter_noalloc(0, torch.cuda.current_stream(), precision, Hd, n, n, dV2, dW2, n,
+                              nb, deg, b_sup, mu_1, mu_b)
+    torch.cuda.synchronize()
+    ref_lib, got = capi.from_device(dV1), capi.from_device(dV2)
+    cols = np.unique(np.linspace(0, nb - 1, 6).astype(int))
+    ref = ch.filter_columns(H, V[:, cols], deg[cols], b_sup, mu_1, mu_b)
+    return got, ref_lib, ref, cols
+
+
+def test_noalloc_matches_chase_filter_twice():
+    from paper_1805_10121_amd import capi
+
+    ctx = capi.Context(0)
+    # first call: order 2000, 600 columns (stream-K products on the wide tile); second call a
+    # smaller one (order 1000, 200 columns: the slim tile), which reuses the same static array
+    for n, nb, seed in ((2000, 600, 71), (1000, 200, 72)):
+        print(f"noalloc fp64 n={n} nb={nb}", flush=True)
+        got, ref_lib, ref, cols = _run_pair(capi, ctx, capi.CHASE_FP64, n, nb, seed, False)
+        assert np.array_equal(got, ref_lib)
+        err = np.linalg.norm(got[:, cols] - ref) / np.linalg.norm(ref)
+        assert err <= 1e-12, err
+    ctx.close()
+
+
+def test_noalloc_3m_and_rejection():
+    import torch
+    from paper_1805_10121_amd import capi
+
+    ctx = capi.Context(0)
+    print("noalloc fp64 3m n=1500 nb=300", flush=True)
+    got, ref_lib, ref, cols = _run_pair(capi, ctx, capi.CHASE_FP64_3M, 1500, 300, 73, True)
+    assert np.array_equal(got, ref_lib)
+    assert np.linalg.norm(got[:, cols] - ref) / np.linalg.norm(ref) <= 1e-12
+    # a call whose stream-K partial sums would exceed the static array: the real FP64 wide tile
+    # (128 x 128 values per slot) on a 256-CU device; refused before anything is enqueued
+    n, nb = 2000, 600
+    H = torch.eye(n, dtype=torch.float64, device="cuda")
+    V = torch.ones((nb, n), dtype=torch.float64, device="cuda")
+    W = torch.empty_like(V)
+    deg = np.full(nb, 2, dtype=np.int32)
+    props = torch.cuda.get_device_properties(0)
+    if props.multi_processor_count * 2 * 2 * 128 * 128 * 8 <= 64 << 20:
+        pytest.skip("this device's stream-K scratch for real FP64 fits the static array")
+    with pytest.raises(capi.ChaseError) as e:
+        capi.chase_filter_noalloc(0, torch.cuda.current_stream(), capi.CHASE_REAL_FP64, H, n, n,
+                                  V, W, n, nb, deg, 2.0, -1.0, 0.5)
+    assert e.value.code == capi.CHASE_EINVAL and "static buffer" in str(e.value)
+    torch.cuda.synchronize()
+    assert bool(torch.all(V == 1.0))
+    # an empty call is accepted and enqueues nothing
+    assert capi.chase_filter_noalloc(0, None, capi.CHASE_FP64, None, 1, 0, None, None, 1, 0, [],
+                                     2.0, -1.0, 0.5) == capi.CHASE_OK
+    ctx.close()
