@@ -27,7 +27,7 @@ def _run(seqs, order, precision, filter_3m=1):
     import torch
     from paper_1805_10121_amd import capi
 
-    srv = capi.Server(0, mem_budget_bytes=8 << 30, workers=4)
+    srv = capi.Server(0, mem_budget_bytes=16 << 30, workers=4)
     dev = {sid: [capi.to_device(H) for H in seqs[sid][3]] for sid in seqs}
     torch.cuda.synchronize()
     tickets = []
@@ -209,3 +209,39 @@ def test_fp32_sequence_in_server_matches_direct():
     srv.close()
     for k in range(3):
         assert np.array_equal(served[k], direct[k])
+
+
+def test_config4_sizes_alone_equals_mix():
+    """Serving-size solves (orders 2000 and 4000, nev = 5 % of n, nex = 20 % of nev, clustered
+    spectrum, eps = 1e-3, mixed filter) beside a small sequence: the order-4000 sequence gives
+    bitwise the same Ritz values, residuals and vectors alone and in the mix, and every served
+    result meets the 1e-10 * ||H|| bar against a dense eigensolver."""
+    from paper_1805_10121_amd import capi
+
+    seqs = {}
+    for sid, n in ((21, 2000), (22, 4000)):
+        nev = round(0.05 * n)
+        nex = round(0.2 * nev)
+        lam = wl.spectrum_clustered(n, wl.rng(600 + sid), 600)
+        print(f"serving sizes: generating order {n}", flush=True)
+        seqs[sid] = (n, nev, nex, wl.sequence(n, lam, 3, 1e-3, 700 + sid))
+    seqs[11] = _sequences()[11]
+    alone_order = [(22, 0), (22, 1), (22, 2)]
+    mix_order = [(21, 0), (22, 0), (11, 0), (22, 1), (21, 1), (11, 1), (21, 2), (22, 2), (11, 2)]
+    print("serving sizes: alone", flush=True)
+    a_res, a_vec, _ = _run(seqs, alone_order, capi.CHASE_MIXED)
+    print("serving sizes: mix", flush=True)
+    m_res, m_vec, info = _run(seqs, mix_order, capi.CHASE_MIXED)
+    assert info["grouped_products"] > info["grouped_launches"] > 0
+    for k in range(3):
+        ra, rm = a_res[(22, k)], m_res[(22, k)]
+        assert ra[0] == 0 and rm[0] == 0
+        assert np.array_equal(ra[1], rm[1]), "Ritz values differ alone vs mix"
+        assert np.array_equal(ra[2], rm[2])
+    assert np.array_equal(a_vec[22], m_vec[22]), "vectors differ alone vs mix"
+    for (sid, k), (rc, ritzv, resid, it) in sorted(m_res.items()):
+        n, nev, nex, Hs = seqs[sid]
+        ev = np.linalg.eigvalsh(Hs[k])
+        err = np.max(np.abs(ritzv[:nev] - ev[:nev])) / np.max(np.abs(ev))
+        print(f"served order {n} problem {k + 1}: {it} iterations, error {err:.2e} x ||H||")
+        assert rc == 0 and err <= 1e-10
