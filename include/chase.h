@@ -189,10 +189,10 @@ int chase_filter(chase_ctx* ctx, int precision, const void* H, int64_t ldh, int6
  *              enqueue on (NULL: the device's null stream).
  *   precision .. mu_nevnex   as in chase_filter.
  *   err        host buffer of err_len bytes for an error message (may be NULL); "" on success.
- * The stream-K partial sums of the products live in a fixed 64 MiB device array that the library
+ * The stream-K partial sums of the products live in a fixed 96 MiB device array that the library
  * holds on every GPU it runs on until the process ends.  The first call on a device (an empty
  * call, ncols = 0, is enough; make it before any graph capture) looks the array's address up.
- * A call whose products would need more than 64 MiB of partial sums -- on a 256-CU device only
+ * A call whose products would need more than 96 MiB of partial sums -- on a 256-CU device only
  * CHASE_REAL_FP64 on more than 16 columns can -- returns CHASE_EINVAL with nothing enqueued.
  * Calls that overlap on one GPU share the array and race: order them on one stream.
  * Returns CHASE_OK, CHASE_EINVAL (argument errors, nothing enqueued) or CHASE_EDEVICE.
@@ -276,10 +276,14 @@ void chase_seq_destroy(chase_seq* seq);
  * n x (nev+nex) vectors of the solve's element type and the Ritz values).  A request is started
  * when its sequence is idle and the device memory it needs -- the sequence state if new, plus
  * the growth of a worker's workspace (chase_workspace_bytes) -- fits in mem_budget_bytes beside
- * what is already held.  Up to `workers` requests run at once, each on its own stream; the
- * filter products of all complex FP64 and MIXED requests in flight are grouped into shared
- * launches (real and FP32 requests run theirs on their worker's stream).  A request's results
- * are bitwise the same whatever else runs beside it.
+ * what is already held.  What is held includes the server's fixed allocations, charged at
+ * creation: the batchers' partial-sum scratch and, per worker, the product scratch of its
+ * context plus a 64 MiB allowance for its rocBLAS/rocSOLVER handle.  Up to `workers` requests
+ * run at once, each on its own stream; the filter products of complex FP64 and MIXED requests
+ * in flight are grouped into shared launches, one batcher (thread and stream) per size class
+ * of n (below 3000, 6000, 12000, and the rest), so a small solve's products never wait behind
+ * a much larger one's (real and FP32 requests run theirs on their worker's stream).  A request's
+ * results are bitwise the same whatever else runs beside it.
  *
  * H: device, the solve's element type, n x n, ldh >= n, owned by the caller and kept valid and
  * unchanged until the request's ticket reports done.  n, nev and nex must stay the same within a
@@ -287,10 +291,12 @@ void chase_seq_destroy(chase_seq* seq);
  * Sequence states are held until chase_server_end_sequence or chase_server_destroy.
  */
 typedef struct chase_server chase_server;
-/* workers in [1, 64]; mem_budget_bytes > 0.  Creates a batching thread and the workers. */
+/* workers in [1, 64]; mem_budget_bytes above the fixed allocations (else CHASE_EINVAL).  Creates
+   the batching threads and the workers. */
 int chase_server_create(chase_server** out, int device, size_t mem_budget_bytes, int workers);
 /* Queue one problem.  CHASE_EINVAL on a bad configuration or a size change inside a sequence;
-   CHASE_EBUSY if the request alone needs more than the budget.  *ticket identifies it. */
+   CHASE_EBUSY if the request alone needs more than the budget left beside the fixed
+   allocations.  *ticket identifies it. */
 int chase_server_submit(chase_server* s, uint64_t seq_id, const chase_config* cfg, const void* H,
                         int64_t ldh, uint64_t* ticket);
 /* Poll (wait = 0) or wait (wait != 0) for a ticket.  When *done is set, ritzv / resid (host,
@@ -302,7 +308,8 @@ int chase_server_poll(chase_server* s, uint64_t ticket, int wait, int* done, dou
 int chase_server_vectors(chase_server* s, uint64_t seq_id, void** V, int64_t* ldv);
 /* Release an idle sequence's state.  CHASE_EBUSY while it runs or has queued requests. */
 int chase_server_end_sequence(chase_server* s, uint64_t seq_id);
-/* Counters: grouped launches and products issued by the batcher, bytes admitted. */
+/* Counters: grouped launches and products issued by the batchers, bytes held (fixed allocations,
+   sequence states and worker workspaces). */
 int chase_server_info(chase_server* s, int64_t* grouped_launches, int64_t* grouped_products,
                       size_t* bytes_in_use);
 const char* chase_server_last_error(chase_server* s);

@@ -78,6 +78,7 @@ template <typename T, int BMC_, int BNC_, int KT_, int WR_, int WC_, int PAD_ = 
           bool BKT_ = false, int PADB_ = -1, int SCHED_ = 0>
 struct Tile {
   static constexpr int KIND = 0;  // 4M real embedding of interleaved complex H
+  static constexpr int OCC = 2;   // workgroups per CU the tile is built for
   static constexpr int BMC = BMC_, BNC = BNC_, KT = KT_, WR = WR_, WC = WC_;
   static constexpr int PROMOTE = PROMOTE_;
   static constexpr int SCHED = SCHED_;
@@ -363,14 +364,19 @@ __device__ __forceinline__ void tile_foreach_4m(const typename C::Frag& f, Fn&& 
 // values), on FP32 MFMA for complex64 data or FP64 MFMA for complex128 data.  With
 // T1 = ReH ReX, T2 = ImH ImX and T3 = (ReH + ImH)(ReX + ImX):  Re(HX) = T1 - T2,
 // Im(HX) = T3 - T1 - T2 -- three real products (6 real flops per complex multiply-add) instead
-// of four.  The sums ReH + ImH and ReX + ImX are formed in registers from the LDS planes.  FP32
-// accumulators are promoted to FP64 every PROMOTE stages (see Tile).  Each wave owns RT x CG
-// MFMA tiles of 16 x 16 complex outputs.
+// of four.  The sums ReH + ImH and ReX + ImX are formed in registers from the LDS planes.  Each
+// wave owns RT x CG MFMA tiles of 16 x 16 complex outputs.
+// PROMOTE_ > 0 (FP32): every PROMOTE_ K stages the three FP32 partial products are combined in
+// FP32 into the real and imaginary parts of that stretch, T1 - T2 and T3 - T1 - T2, which are
+// added into two FP64 sums and the FP32 accumulators cleared.  Keeping two FP64 sums instead of
+// three saves 32 registers per lane, enough for three workgroups per CU.
+// OCC_: workgroups per CU the tile is built for (launch bounds and the stream-K grid).
 template <int BMC_, int BNC_, int KT_, int WR_, int WC_, int PAD_ = 4, int PROMOTE_ = 1,
-          typename T_ = float>
+          typename T_ = float, int OCC_ = 2>
 struct Tile3M {
   using T = T_;  // float: complex64 data, FP32 MFMA; double: complex128 data, FP64 MFMA
   static constexpr int KIND = 1;
+  static constexpr int OCC = OCC_;
   static constexpr int BMC = BMC_, BNC = BNC_, KT = KT_, WR = WR_, WC = WC_;
   static constexpr int PROMOTE = PROMOTE_;
   static constexpr int RT = BMC / WR / 16;
@@ -390,7 +396,7 @@ struct Tile3M {
   };
   struct Frag64 {
     acc_t acc[RT][CG][3];
-    double acc64[RT][CG][3][4];
+    double acc64[RT][CG][2][4];  // FP64 sums of the real and imaginary parts
   };
   struct Frag32 {
     acc_t acc[RT][CG][3];
@@ -492,8 +498,10 @@ __device__ __forceinline__ void tile_mainloop_3m(typename C::Smem& sm, typename 
       for (int c = 0; c < 3; ++c) {
         f.acc[a][b][c] = acc_t{0};
         if constexpr (C::PROMOTE > 0) {
+          if (c < 2) {
 #pragma unroll
-          for (int e = 0; e < 4; ++e) f.acc64[a][b][c][e] = 0.0;
+            for (int e = 0; e < 4; ++e) f.acc64[a][b][c][e] = 0.0;
+          }
         }
       }
 
@@ -535,13 +543,16 @@ __device__ __forceinline__ void tile_mainloop_3m(typename C::Smem& sm, typename 
 #pragma unroll
         for (int a = 0; a < C::RT; ++a)
 #pragma unroll
-          for (int b = 0; b < C::CG; ++b)
+          for (int b = 0; b < C::CG; ++b) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-#pragma unroll
-              for (int e = 0; e < 4; ++e) f.acc64[a][b][c][e] += static_cast<double>(f.acc[a][b][c][e]);
-              f.acc[a][b][c] = acc_t{0};
+            for (int e = 0; e < 4; ++e) {
+              const T t1 = f.acc[a][b][0][e], t2 = f.acc[a][b][1][e], t3 = f.acc[a][b][2][e];
+              f.acc64[a][b][0][e] += static_cast<double>(t1 - t2);
+              f.acc64[a][b][1][e] += static_cast<double>(t3 - t1 - t2);
             }
+#pragma unroll
+            for (int c = 0; c < 3; ++c) f.acc[a][b][c] = acc_t{0};
+          }
       }
     }
     if (kt + 1 < kb) store_tiles(cur ^ 1);
@@ -566,9 +577,8 @@ __device__ __forceinline__ void tile_foreach_3m(const typename C::Frag& f, Fn&& 
         const int row = wr * (C::BMC / C::WR) + rt * 16 + (sizeof(T) == 8 ? g + 4 * r : 4 * g + r);
         const int col = wc * (C::BNC / C::WC) + cg * 16 + li;
         if constexpr (C::PROMOTE > 0) {
-          const double t1 = f.acc64[rt][cg][0][r], t2 = f.acc64[rt][cg][1][r];
-          const double t3 = f.acc64[rt][cg][2][r];
-          fn(row, col, static_cast<float>(t1 - t2), static_cast<float>(t3 - t1 - t2));
+          fn(row, col, static_cast<float>(f.acc64[rt][cg][0][r]),
+             static_cast<float>(f.acc64[rt][cg][1][r]));
         } else {
           const T t1 = f.acc[rt][cg][0][r], t2 = f.acc[rt][cg][1][r], t3 = f.acc[rt][cg][2][r];
           fn(row, col, t1 - t2, t3 - t1 - t2);
@@ -583,6 +593,7 @@ __device__ __forceinline__ void tile_foreach_3m(const typename C::Frag& f, Fn&& 
 template <typename T, int BM_, int BN_, int KT_, int WR_, int WC_, int PAD_ = 2>
 struct TileR {
   static constexpr int KIND = 2;
+  static constexpr int OCC = 2;
   static constexpr int BMC = BM_, BNC = BN_, KT = KT_, WR = WR_, WC = WC_;  // real rows / columns
   static constexpr int PROMOTE = 0;
   static constexpr int RT = BM_ / WR_ / 16;
@@ -973,10 +984,13 @@ __global__ __launch_bounds__(kThreads) void hemm_fixup_kernel(
   }
 }
 
-// Grouped data-parallel schedule: one launch runs one product for each of up to kMaxGroup
-// independent problems (continuous batching of small solves).  The tiles of all problems are
-// concatenated; every tile is computed exactly as hemm_dp_kernel computes it (same K order),
-// so a problem's result does not depend on what it was grouped with.
+// Grouped schedule: one launch runs one product for each of up to kMaxGroup independent
+// problems (continuous batching of small solves).  The tiles of all problems are concatenated.
+// A product with ksplit > 1 has each output tile computed as ksplit K slices (workgroup
+// tile + tiles * slice covers the K stages [slice * nk / ksplit, (slice + 1) * nk / ksplit)),
+// whose partial sums go to the scratch; hemm_group_fixup_kernel adds them in slice order.  The
+// split of a product depends only on its own n and ncols, so a problem's result does not
+// depend on what it was grouped with.
 template <typename T, class C, int OCC, bool V16>
 __global__ __launch_bounds__(kThreads, OCC) void hemm_group_kernel(GroupArgs<T> args) {
   __shared__ typename C::Smem sm;
@@ -987,17 +1001,76 @@ __global__ __launch_bounds__(kThreads, OCC) void hemm_group_kernel(GroupArgs<T> 
   const GroupDesc<T> d = args.d[g];
   const int local = b - d.tile_begin;
   const int tiles_m = (d.n + C::BMC - 1) / C::BMC;
-  const int tile_m = local % tiles_m, tile_n = local / tiles_m;
+  const int tiles = tiles_m * ((d.ncols + C::BNC - 1) / C::BNC);
+  const int S = d.ksplit > 1 ? d.ksplit : 1;
+  const int tile = local % tiles, slice = local / tiles;
+  const int tile_m = tile % tiles_m, tile_n = tile / tiles_m;
   const int i0 = tile_m * C::BMC, j0 = tile_n * C::BNC;
   const int nk = (d.n + C::KT - 1) / C::KT;
-  tile_mainloop<T, C, V16>(sm, f, d.H, d.ldh, d.n, d.X, d.ldx, d.ncols, i0, j0, 0, nk);
-  tile_foreach<T, C>(f, [&](int r, int c, T hre, T him) {
-    if (i0 + r < d.n && j0 + c < d.ncols)
-      store_result<T, C>(d.X, d.ldx, d.OUT, d.ldo, i0 + r, j0 + c, hre, him, d.alpha, d.beta,
-                        d.gamma);
-  });
+  const int ka = static_cast<int>(static_cast<int64_t>(slice) * nk / S);
+  const int kb = static_cast<int>(static_cast<int64_t>(slice + 1) * nk / S);
+  tile_mainloop<T, C, V16>(sm, f, d.H, d.ldh, d.n, d.X, d.ldx, d.ncols, i0, j0, ka, kb);
+  if (S == 1) {
+    tile_foreach<T, C>(f, [&](int r, int c, T hre, T him) {
+      if (i0 + r < d.n && j0 + c < d.ncols)
+        store_result<T, C>(d.X, d.ldx, d.OUT, d.ldo, i0 + r, j0 + c, hre, him, d.alpha, d.beta,
+                          d.gamma);
+    });
+  } else {
+    constexpr int EW = elem_width<C>();
+    constexpr int TE = C::BMC * C::BNC;
+    T* dst = args.partial + d.part_off + static_cast<int64_t>(slice * tiles + tile) * EW * TE;
+    tile_foreach<T, C>(f, [&](int r, int c, T hre, T him) {
+      dst[EW * (r + c * C::BMC)] = hre;
+      if constexpr (EW == 2) dst[EW * (r + c * C::BMC) + 1] = him;
+    });
+  }
 }
 
+// Completes the K-sliced tiles of a grouped launch: workgroup fix_begin + fixup_slices * tile +
+// e of a product adds the ksplit partial sums of element slice e of that tile, in slice order,
+// and applies the epilogue.
+template <typename T, class C>
+__global__ __launch_bounds__(kThreads) void hemm_group_fixup_kernel(GroupArgs<T> args) {
+  const int b = static_cast<int>(blockIdx.x);
+  int g = -1;
+  for (int q = 0; q < args.count; ++q)
+    if (args.d[q].ksplit > 1 && b >= args.d[q].fix_begin) g = q;
+  if (g < 0) return;
+  const GroupDesc<T> d = args.d[g];
+  constexpr int TE = C::BMC * C::BNC;
+  constexpr int SL = fixup_slices<C>();
+  constexpr int ES = TE / SL;
+  static_assert(ES * SL == TE && ES % kThreads == 0, "slice split");
+  constexpr int EPT = ES / kThreads;
+  constexpr int EW = elem_width<C>();
+  const int tiles_m = (d.n + C::BMC - 1) / C::BMC;
+  const int tiles = tiles_m * ((d.ncols + C::BNC - 1) / C::BNC);
+  const int local = b - d.fix_begin;
+  const int tile = local / SL, es = local % SL;
+  if (tile >= tiles) return;
+  const int i0 = (tile % tiles_m) * C::BMC, j0 = (tile / tiles_m) * C::BNC;
+  T hre[EPT], him[EPT];
+#pragma unroll
+  for (int q = 0; q < EPT; ++q) hre[q] = T(0), him[q] = T(0);
+  for (int sl = 0; sl < d.ksplit; ++sl) {
+    const T* src = args.partial + d.part_off + static_cast<int64_t>(sl * tiles + tile) * EW * TE;
+#pragma unroll
+    for (int q = 0; q < EPT; ++q) {
+      const int e = es * ES + static_cast<int>(threadIdx.x) + q * kThreads;
+      hre[q] += src[EW * e];
+      if constexpr (EW == 2) him[q] += src[EW * e + 1];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < EPT; ++q) {
+    const int e = es * ES + static_cast<int>(threadIdx.x) + q * kThreads;
+    const int r = e % C::BMC, c = e / C::BMC;
+    if (i0 + r < d.n && j0 + c < d.ncols)
+      store_result<T, C>(d.X, d.ldx, d.OUT, d.ldo, i0 + r, j0 + c, hre[q], him[q], d.alpha,
+                        d.beta, d.gamma);
+  }
+}
 
 template <typename T, class C, int OCC, bool V16 = false>
 hipError_t launch_dp(const T* H, int64_t ldh, int64_t n, const T* X, int64_t ldx, T* OUT,
@@ -1086,15 +1159,17 @@ template <typename T> using RealTile = TileR<T, 128, 128, 16, 2, 2, sizeof(T) ==
 template <typename T> using RealThinTile = TileR<T, 256, 16, 16, 4, 1, sizeof(T) == 4 ? 4 : 2>;
 constexpr double kSlimCost = 1.10;
 
-// 3M tile for the planar FP32 products: FP64 promotion every four stages (64 K terms).  Each
-// promotion waits for the MFMA pipeline to drain, so promoting every 4 stages instead of 2 runs
-// about 9 % faster; the FP32 part of the error grows like sqrt(64) units of FP32 roundoff,
-// well below the 1e-6 residual at which the mixed solver leaves FP32.
-using Wide3M = Tile3M<64, 64, 16, 2, 2, 4, 4>;
+// 3M tile for the planar FP32 products: FP64 promotion every four stages (64 K terms), three
+// workgroups per CU (the combined promotion keeps it at 163 VGPRs).  Each promotion waits for
+// the MFMA pipeline to drain, so promoting every 4 stages instead of 2 runs about 9 % faster;
+// the FP32 part of the error grows like sqrt(64) units of FP32 roundoff, well below the 1e-6
+// residual at which the mixed solver leaves FP32.
+using Wide3M = Tile3M<64, 64, 16, 2, 2, 4, 4, float, 3>;
 // The same 3M scheme on FP64 MFMA for complex128 data stored as two float64 planes: three
 // real products instead of four per complex product.  No promotion (FP64 accumulators);
-// 8-byte loads (measured faster than 16-byte ones for this tile).
-using Wide3M64 = Tile3M<64, 64, 16, 2, 2, 4, 0, double>;
+// 8-byte loads (measured faster than 16-byte ones for this tile); K stages of 8 with three
+// workgroups per CU (35 KB of LDS, at most 168 VGPRs), 4-6 % faster than stages of 16 with two.
+using Wide3M64 = Tile3M<64, 64, 8, 2, 2, 4, 0, double, 3>;
 using Narrow3M64 = Tile3M<64, 32, 16, 4, 1, 4, 0, double>;
 using Thin3M64 = Tile3M<128, 16, 16, 4, 1, 4, 0, double>;
 
@@ -1118,7 +1193,7 @@ bool wide_loads(const T* H, int64_t ldh, const T* X, int64_t ldx, int64_t n) {
     return use_v16(H, ldh, X, ldx, n);
 }
 
-template <typename T, class C, int OCC = kOcc>
+template <typename T, class C, int OCC = C::OCC>
 hipError_t launch_sched(const T* H, int64_t ldh, int64_t n, const T* X, int64_t ldx, T* OUT,
                         int64_t ldo, int64_t ncols, T alpha, T beta, T gamma,
                         const ProductScratch& ps, hipStream_t stream, bool v16_ok = true) {
@@ -1145,18 +1220,24 @@ hipError_t launch_sched(const T* H, int64_t ldh, int64_t n, const T* X, int64_t 
 }
 }  // namespace
 
+// Stream-K partial sums of a tile on a device with `cus` compute units.
+template <typename T, class C>
+size_t tile_scratch(int cus, int occ = C::OCC) {
+  return sk_scratch_bytes<T, C>(static_cast<int64_t>(cus) * occ);
+}
+
 size_t product_scratch_bytes(int cus) {
-  const int64_t slots = static_cast<int64_t>(cus) * kOcc;
-  size_t b = sk_scratch_bytes<double, WideTile<double>>(slots);
-  b = std::max(b, sk_scratch_bytes<float, WideTile<float>>(slots));
-  b = std::max(b, sk_scratch_bytes<double, NarrowTile<double>>(slots));
-  b = std::max(b, sk_scratch_bytes<double, SlimTile64>(static_cast<int64_t>(cus) * kOccSlim));
-  b = std::max(b, sk_scratch_bytes<double, ThinTile64>(slots));
-  b = std::max(b, sk_scratch_bytes<double, Wide3M64>(slots));
-  b = std::max(b, sk_scratch_bytes<double, Narrow3M64>(slots));
-  b = std::max(b, sk_scratch_bytes<double, Thin3M64>(slots));
-  b = std::max(b, sk_scratch_bytes<double, RealTile<double>>(slots));
-  b = std::max(b, sk_scratch_bytes<double, RealThinTile<double>>(slots));
+  size_t b = tile_scratch<double, WideTile<double>>(cus);
+  b = std::max(b, tile_scratch<float, WideTile<float>>(cus));
+  b = std::max(b, tile_scratch<double, NarrowTile<double>>(cus));
+  b = std::max(b, tile_scratch<double, SlimTile64>(cus, kOccSlim));
+  b = std::max(b, tile_scratch<double, ThinTile64>(cus));
+  b = std::max(b, tile_scratch<float, Wide3M>(cus));
+  b = std::max(b, tile_scratch<double, Wide3M64>(cus));
+  b = std::max(b, tile_scratch<double, Narrow3M64>(cus));
+  b = std::max(b, tile_scratch<double, Thin3M64>(cus));
+  b = std::max(b, tile_scratch<double, RealTile<double>>(cus));
+  b = std::max(b, tile_scratch<double, RealThinTile<double>>(cus));
   return b;
 }
 
@@ -1208,36 +1289,89 @@ hipError_t launch_hemm_step(const T* H, int64_t ldh, int64_t n, const T* X, int6
                                       stream);
 }
 
-template <typename T>
-hipError_t launch_hemm_group(const GroupDesc<T>* descs, int count, hipStream_t stream) {
-  for (int base = 0; base < count; base += kMaxGroup) {
+// Grouped launches.  Workgroup slots of the whole device that a lone product's K split aims
+// to fill, and the most K slices per tile (each slice keeps at least 8 K stages).
+constexpr int kGroupSlots = 512;
+constexpr int kGroupMaxSplit = 8;
+
+// K slices of a product in a grouped launch: a function of n and ncols only.
+template <class C>
+int group_ksplit(int64_t n, int64_t ncols) {
+  const int64_t tiles = ((n + C::BMC - 1) / C::BMC) * ((ncols + C::BNC - 1) / C::BNC);
+  const int64_t nk = (n + C::KT - 1) / C::KT;
+  int64_t s = tiles > 0 ? kGroupSlots / tiles : 1;
+  s = std::min<int64_t>(s, kGroupMaxSplit);
+  s = std::min<int64_t>(s, nk / 8);
+  return static_cast<int>(std::max<int64_t>(s, 1));
+}
+
+// Partial-sum values of one product (all its slices).
+template <typename T, class C>
+int64_t group_partial_values(int64_t n, int64_t ncols) {
+  const int s = group_ksplit<C>(n, ncols);
+  if (s <= 1) return 0;
+  const int64_t tiles = ((n + C::BMC - 1) / C::BMC) * ((ncols + C::BNC - 1) / C::BNC);
+  return s * tiles * C::BMC * C::BNC * elem_width<C>();
+}
+
+// Runs the products in launches of at most kMaxGroup products whose partial sums fit the
+// scratch; each launch is the main kernel and, when a product is split, the fixup kernel.
+template <typename T, class C, bool V16>
+hipError_t launch_group(const GroupDesc<T>* descs, int count, const GroupScratch& gs,
+                        hipStream_t stream) {
+  const int64_t cap = static_cast<int64_t>(gs.bytes / sizeof(T));
+  int q0 = 0;
+  while (q0 < count) {
     GroupArgs<T> a{};
-    a.count = std::min(kMaxGroup, count - base);
-    int64_t tiles = 0;
-    for (int q = 0; q < a.count; ++q) {
-      a.d[q] = descs[base + q];
-      a.d[q].tile_begin = static_cast<int>(tiles);
-      using C = WideTile<T>;
-      tiles += ((a.d[q].n + C::BMC - 1) / C::BMC) *
-               static_cast<int64_t>((a.d[q].ncols + C::BNC - 1) / C::BNC);
+    a.partial = static_cast<T*>(gs.ptr);
+    int64_t tiles = 0, fix = 0, part = 0;
+    int q = q0;
+    for (; q < count && a.count < kMaxGroup; ++q) {
+      const GroupDesc<T>& src = descs[q];
+      const int64_t pv = group_partial_values<T, C>(src.n, src.ncols);
+      if (pv > 0 && (!gs.ptr || pv > cap)) return hipErrorInvalidValue;   // scratch too small
+      if (part + pv > cap) break;                                        // next launch
+      GroupDesc<T> d = src;
+      const int64_t t = ((d.n + C::BMC - 1) / C::BMC) *
+                        static_cast<int64_t>((d.ncols + C::BNC - 1) / C::BNC);
+      d.ksplit = group_ksplit<C>(d.n, d.ncols);
+      d.tile_begin = static_cast<int>(tiles);
+      d.fix_begin = static_cast<int>(fix);
+      d.part_off = part;
+      tiles += t * d.ksplit;
+      if (d.ksplit > 1) fix += t * fixup_slices<C>();
+      part += pv;
+      a.d[a.count++] = d;
     }
+    q0 = q;
     if (tiles == 0) continue;
-    if (tiles > 0x7fffffff) return hipErrorInvalidValue;
-    bool v16 = true;
-    for (int q = 0; q < a.count; ++q) v16 = v16 && use_v16(a.d[q].H, a.d[q].ldh, a.d[q].X, a.d[q].ldx, a.d[q].n);
-    if (v16)
-      hipLaunchKernelGGL((hemm_group_kernel<T, WideTile<T>, kOcc, true>),
-                         dim3(static_cast<unsigned>(tiles)), dim3(kThreads), 0, stream, a);
-    else
-      hipLaunchKernelGGL((hemm_group_kernel<T, WideTile<T>, kOcc, false>),
-                         dim3(static_cast<unsigned>(tiles)), dim3(kThreads), 0, stream, a);
+    if (tiles > 0x7fffffff || fix > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((hemm_group_kernel<T, C, C::OCC, V16>), dim3(static_cast<unsigned>(tiles)),
+                       dim3(kThreads), 0, stream, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    if (fix > 0) {
+      hipLaunchKernelGGL((hemm_group_fixup_kernel<T, C>), dim3(static_cast<unsigned>(fix)),
+                         dim3(kThreads), 0, stream, a);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
   }
   return hipSuccess;
 }
-template hipError_t launch_hemm_group<double>(const GroupDesc<double>*, int, hipStream_t);
-template hipError_t launch_hemm_group<float>(const GroupDesc<float>*, int, hipStream_t);
+
+template <typename T>
+hipError_t launch_hemm_group(const GroupDesc<T>* descs, int count, const GroupScratch& gs,
+                             hipStream_t stream) {
+  bool v16 = true;
+  for (int q = 0; q < count; ++q)
+    v16 = v16 && use_v16(descs[q].H, descs[q].ldh, descs[q].X, descs[q].ldx, descs[q].n);
+  if (v16) return launch_group<T, WideTile<T>, true>(descs, count, gs, stream);
+  return launch_group<T, WideTile<T>, false>(descs, count, gs, stream);
+}
+template hipError_t launch_hemm_group<double>(const GroupDesc<double>*, int, const GroupScratch&,
+                                              hipStream_t);
+template hipError_t launch_hemm_group<float>(const GroupDesc<float>*, int, const GroupScratch&,
+                                             hipStream_t);
 
 hipError_t launch_hemm_step_3m(const float* H, int64_t ldh, int64_t n, const float* X,
                                int64_t ldx, float* OUT, int64_t ldo, int64_t ncols, float alpha,
@@ -1264,54 +1398,31 @@ hipError_t launch_hemm_step_3m_f64(const double* H, int64_t ldh, int64_t n, cons
                                         ps, stream, false);
 }
 
-hipError_t launch_hemm_group_3m(const GroupDesc<float>* descs, int count, hipStream_t stream) {
-  for (int base = 0; base < count; base += kMaxGroup) {
-    GroupArgs<float> a{};
-    a.count = std::min(kMaxGroup, count - base);
-    int64_t tiles = 0;
-    bool v16 = true;
-    for (int q = 0; q < a.count; ++q) {
-      a.d[q] = descs[base + q];
-      a.d[q].tile_begin = static_cast<int>(tiles);
-      tiles += ((a.d[q].n + Wide3M::BMC - 1) / Wide3M::BMC) *
-               static_cast<int64_t>((a.d[q].ncols + Wide3M::BNC - 1) / Wide3M::BNC);
-      v16 = v16 && a.d[q].ldh % 4 == 0 && use_v16(a.d[q].H, a.d[q].ldh, a.d[q].X, a.d[q].ldx, a.d[q].n);
-    }
-    if (tiles == 0) continue;
-    if (tiles > 0x7fffffff) return hipErrorInvalidValue;
-    if (v16)
-      hipLaunchKernelGGL((hemm_group_kernel<float, Wide3M, kOcc, true>),
-                         dim3(static_cast<unsigned>(tiles)), dim3(kThreads), 0, stream, a);
-    else
-      hipLaunchKernelGGL((hemm_group_kernel<float, Wide3M, kOcc, false>),
-                         dim3(static_cast<unsigned>(tiles)), dim3(kThreads), 0, stream, a);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
-  return hipSuccess;
+hipError_t launch_hemm_group_3m(const GroupDesc<float>* descs, int count, const GroupScratch& gs,
+                                hipStream_t stream) {
+  // vector loads of four rows per plane need ldh % 4 == 0 on top of the usual conditions
+  bool v16 = true;
+  for (int q = 0; q < count; ++q)
+    v16 = v16 && descs[q].ldh % 4 == 0 &&
+          use_v16(descs[q].H, descs[q].ldh, descs[q].X, descs[q].ldx, descs[q].n);
+  if (v16) return launch_group<float, Wide3M, true>(descs, count, gs, stream);
+  return launch_group<float, Wide3M, false>(descs, count, gs, stream);
 }
 
 hipError_t launch_hemm_group_3m_f64(const GroupDesc<double>* descs, int count,
-                                    hipStream_t stream) {
-  using C = Wide3M64;
-  for (int base = 0; base < count; base += kMaxGroup) {
-    GroupArgs<double> a{};
-    a.count = std::min(kMaxGroup, count - base);
-    int64_t tiles = 0;
-    for (int q = 0; q < a.count; ++q) {
-      a.d[q] = descs[base + q];
-      a.d[q].tile_begin = static_cast<int>(tiles);
-      tiles += ((a.d[q].n + C::BMC - 1) / C::BMC) *
-               static_cast<int64_t>((a.d[q].ncols + C::BNC - 1) / C::BNC);
-    }
-    if (tiles == 0) continue;
-    if (tiles > 0x7fffffff) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((hemm_group_kernel<double, C, kOcc, false>),
-                       dim3(static_cast<unsigned>(tiles)), dim3(kThreads), 0, stream, a);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
-  return hipSuccess;
+                                    const GroupScratch& gs, hipStream_t stream) {
+  return launch_group<double, Wide3M64, false>(descs, count, gs, stream);
+}
+
+size_t group_scratch_min_bytes() {
+  // a split product has fewer than kGroupSlots tiles and at most kGroupSlots / tiles slices, so
+  // its partial sums hold at most kGroupSlots tiles' worth of values
+  size_t b = 0;
+  b = std::max(b, kGroupSlots * sizeof(double) * 2 * WideTile<double>::BMC * WideTile<double>::BNC);
+  b = std::max(b, kGroupSlots * sizeof(float) * 2 * WideTile<float>::BMC * WideTile<float>::BNC);
+  b = std::max(b, kGroupSlots * sizeof(float) * 2 * Wide3M::BMC * Wide3M::BNC);
+  b = std::max(b, kGroupSlots * sizeof(double) * 2 * Wide3M64::BMC * Wide3M64::BNC);
+  return b;
 }
 
 template hipError_t launch_hemm_step<double>(const double*, int64_t, int64_t, const double*,

@@ -41,8 +41,8 @@ hipError_t launch_hemm_step_real(const T* H, int64_t ldh, int64_t n, const T* X,
                                  T* OUT, int64_t ldo, int64_t ncols, T alpha, T beta, T gamma,
                                  const ProductScratch& ps, hipStream_t stream);
 
-// One product of one problem inside a grouped launch (fields as in launch_hemm_step;
-// tile_begin is filled by the launcher).  Zero-column products are allowed and skipped.
+// One product of one problem inside a grouped launch (fields as in launch_hemm_step; the
+// last four are filled by the launcher).  Zero-column products are allowed and skipped.
 template <typename T>
 struct GroupDesc {
   const T* H;
@@ -51,32 +51,48 @@ struct GroupDesc {
   int64_t ldh, ldx, ldo;
   int n, ncols;
   T alpha, beta, gamma;
-  int tile_begin;
+  int tile_begin;    // first workgroup of this product in the main launch
+  int ksplit;        // K slices per output tile (1: each tile is finished in place)
+  int fix_begin;     // first workgroup of this product in the fixup launch (ksplit > 1)
+  int64_t part_off;  // offset (values) of this product's partial sums in the scratch
 };
 constexpr int kMaxGroup = 16;
 template <typename T>
 struct GroupArgs {
   int count;
+  T* partial;
   GroupDesc<T> d[kMaxGroup];
 };
-// Grouped products; every product is computed exactly as the data-parallel schedule computes
-// it alone, so results do not depend on the grouping.
+// Partial-sum scratch of K-sliced grouped products (owned by the batcher, fixed size).
+struct GroupScratch {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+};
+// Bytes the largest single K-sliced product can need; a scratch of at least this size lets the
+// launchers run any group (in several launches when one does not fit).
+size_t group_scratch_min_bytes();
+// Grouped products.  Each product is computed exactly as it would be computed alone in a
+// grouped launch: its K split (ksplit) is a function of its own order and width only, its tiles
+// keep a fixed K order, and the slices of a split tile are added in slice order by a second
+// (fixup) launch.  Results therefore do not depend on the grouping.  A product with few tiles
+// is split along K so that a lone small product still occupies the whole device.
 template <typename T>
-hipError_t launch_hemm_group(const GroupDesc<T>* descs, int count, hipStream_t stream);
-
+hipError_t launch_hemm_group(const GroupDesc<T>* descs, int count, const GroupScratch& gs,
+                             hipStream_t stream);
 // 3M products on planar complex64 H (Re plane, then Im plane at H + ldh * n).
 hipError_t launch_hemm_step_3m(const float* H, int64_t ldh, int64_t n, const float* X,
                                int64_t ldx, float* OUT, int64_t ldo, int64_t ncols, float alpha,
                                float beta, float gamma, const ProductScratch& ps,
                                hipStream_t stream);
-hipError_t launch_hemm_group_3m(const GroupDesc<float>* descs, int count, hipStream_t stream);
+hipError_t launch_hemm_group_3m(const GroupDesc<float>* descs, int count, const GroupScratch& gs,
+                                hipStream_t stream);
 // 3M products on planar complex128 H (Re plane, then Im plane at H + ldh * n), FP64 MFMA.
 hipError_t launch_hemm_step_3m_f64(const double* H, int64_t ldh, int64_t n, const double* X,
                                    int64_t ldx, double* OUT, int64_t ldo, int64_t ncols,
                                    double alpha, double beta, double gamma,
                                    const ProductScratch& ps, hipStream_t stream);
 hipError_t launch_hemm_group_3m_f64(const GroupDesc<double>* descs, int count,
-                                    hipStream_t stream);
+                                    const GroupScratch& gs, hipStream_t stream);
 hipError_t launch_convert_c128_to_planar64(const double* src, int64_t lds, double* dst,
                                            int64_t ldd, int64_t n, hipStream_t stream);
 hipError_t launch_convert_c128_to_planar32(const double* src, int64_t lds, float* dst, int64_t ldd,
@@ -148,6 +164,8 @@ class Batcher {
                  const std::vector<FilterProduct>& prods, hipStream_t caller, hipEvent_t ready,
                  hipEvent_t done);
   void counters(int64_t* launches, int64_t* products) const;
+  // Device memory each batcher holds for its lifetime (the K-slice partial sums).
+  static size_t scratch_bytes();
 
  private:
   struct Job;

@@ -16,7 +16,10 @@
 
 namespace {
 
-constexpr size_t kStaticScratchBytes = size_t{64} << 20;  // 64 MiB
+// 96 MiB: the stream-K partial sums of every complex tile on a 256-CU device (the largest, the
+// FP64 3M tile at three workgroups per CU, needs exactly this); the real FP64 128 x 128 tile
+// (128 MiB there) is refused.
+constexpr size_t kStaticScratchBytes = size_t{96} << 20;
 constexpr int kMaxDevices = 64;
 
 static __device__ __align__(256) double scratch[kStaticScratchBytes / sizeof(double)];

@@ -2,11 +2,16 @@
 // uneven order, Sec. 2 and Sec. 6.1) on one device.
 //
 //   Batcher  -- every solve that reaches its FILTER phase hands the products of its filter
-//               call (Alg. 4) to the batcher; each tick takes the next product of every
-//               submitted filter and runs them all in one grouped launch per product kind
-//               (FP64 or FP32, 4M on H or 3M on a planar copy).  New filter calls join at the
-//               next tick.  At most two ticks are in flight, so a
-//               newly arrived solve waits at most about two product times.
+//               call (Alg. 4) to the batcher of its size class; each tick takes the next
+//               product of every submitted filter and runs them all in one grouped launch per
+//               product kind (FP64 or FP32, 4M on H or 3M on a planar copy).  New filter calls
+//               join at the next tick.  At most two ticks are in flight, so a newly arrived
+//               solve waits at most about two product times.  Solves of different orders go to
+//               different batchers (own thread and stream), so the products of a small solve
+//               never wait for a tick that holds the product of a much larger one; the classes'
+//               launches share the device concurrently.  A product with few tiles is split
+//               along K inside its grouped launch (a deterministic split that depends only on
+//               its order and width), so a lone small product still fills the device.
 //   Server   -- worker threads, each with its own context (HIP stream, rocBLAS handle,
 //               workspace), take requests first-come first-served subject to (a) problems of
 //               one sequence run in submission order, each warm-started from the previous
@@ -47,6 +52,7 @@ struct Batcher::Job {
 struct Batcher::Impl {
   int device = 0;
   hipStream_t stream = nullptr;
+  GroupScratch gs;  // partial sums of K-sliced grouped products (reused launch after launch)
   hipEvent_t tick_ev[2] = {nullptr, nullptr};
   bool tick_recorded[2] = {false, false};
   int tick = 0;
@@ -62,12 +68,17 @@ struct Batcher::Impl {
   hipError_t tick_once();
 };
 
+size_t Batcher::scratch_bytes() { return 4 * group_scratch_min_bytes(); }
+
 Batcher::Batcher(int device) {
   impl_ = new Impl();
   impl_->device = device;
+  impl_->gs.bytes = scratch_bytes();
   if (hipSetDevice(device) != hipSuccess || hipStreamCreate(&impl_->stream) != hipSuccess ||
       hipEventCreateWithFlags(&impl_->tick_ev[0], hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&impl_->tick_ev[1], hipEventDisableTiming) != hipSuccess) {
+      hipEventCreateWithFlags(&impl_->tick_ev[1], hipEventDisableTiming) != hipSuccess ||
+      hipMalloc(&impl_->gs.ptr, impl_->gs.bytes) != hipSuccess) {
+    impl_->gs.ptr = nullptr;
     (void)hipGetLastError();
     return;
   }
@@ -89,6 +100,7 @@ Batcher::~Batcher() {
   for (auto& e : impl_->tick_ev)
     if (e) (void)hipEventDestroy(e);
   if (impl_->stream) (void)hipStreamDestroy(impl_->stream);
+  if (impl_->gs.ptr) (void)hipFree(impl_->gs.ptr);
   delete impl_;
 }
 
@@ -172,13 +184,14 @@ hipError_t Batcher::Impl::tick_once() {
     ++j->next;
   }
   hipError_t e = hipSuccess;
-  if (!d64.empty()) e = launch_hemm_group<double>(d64.data(), static_cast<int>(d64.size()), stream);
+  if (!d64.empty())
+    e = launch_hemm_group<double>(d64.data(), static_cast<int>(d64.size()), gs, stream);
   if (e == hipSuccess && !d32.empty())
-    e = launch_hemm_group<float>(d32.data(), static_cast<int>(d32.size()), stream);
+    e = launch_hemm_group<float>(d32.data(), static_cast<int>(d32.size()), gs, stream);
   if (e == hipSuccess && !d3m.empty())
-    e = launch_hemm_group_3m(d3m.data(), static_cast<int>(d3m.size()), stream);
+    e = launch_hemm_group_3m(d3m.data(), static_cast<int>(d3m.size()), gs, stream);
   if (e == hipSuccess && !d3m64.empty())
-    e = launch_hemm_group_3m_f64(d3m64.data(), static_cast<int>(d3m64.size()), stream);
+    e = launch_hemm_group_3m_f64(d3m64.data(), static_cast<int>(d3m64.size()), gs, stream);
   if (e == hipSuccess) e = hipEventRecord(tick_ev[slot], stream);
   tick_recorded[slot] = true;
   ++tick;
@@ -232,15 +245,25 @@ void Batcher::Impl::loop() {
 struct chase_server {
   int device = 0;
   size_t budget = 0;
-  std::unique_ptr<chase::Batcher> batcher;
+  // one batcher per size class: orders below 3000, 6000, 12000, and the rest
+  static constexpr int kClasses = 4;
+  std::unique_ptr<chase::Batcher> batchers[kClasses];
   std::vector<std::thread> workers;
   std::vector<size_t> worker_ws;  // workspace bytes each worker's context holds
   std::mutex mu;
   std::condition_variable cv, done_cv;
   bool stop = false;
   uint64_t next_ticket = 1;
-  size_t used = 0;  // sequence states + worker workspaces
+  // fixed allocations (batcher scratch, each worker's product scratch and a handle allowance)
+  // + sequence states + worker workspaces
+  size_t used = 0;
+  size_t fixed = 0;  // the fixed part of used
   std::string last_error;
+
+  chase::Batcher* batcher_for(int64_t n) {
+    const int c = n < 3000 ? 0 : n < 6000 ? 1 : n < 12000 ? 2 : 3;
+    return batchers[c].get();
+  }
 
   struct Req {
     uint64_t seq = 0;
@@ -365,7 +388,7 @@ void chase_server::worker(int w) {
         rv = seq->ritzv;
       }
       rc = chase::solve_with(ctx, &cfg, req->H, req->ldh, seq->V, cfg.n, rv.data(), rs.data(), &st,
-                             batcher.get());
+                             batcher_for(cfg.n));
       if (rc < 0) err = chase_last_error(ctx);
     }
     {
@@ -381,6 +404,13 @@ void chase_server::worker(int w) {
       if (rc >= 0) {
         seq->ritzv = rv;
         ++seq->solved;
+      }
+      // charge what the workspace really holds (a failed growth frees the old one)
+      used = used - worker_ws[w] + ctx->ws_bytes;
+      worker_ws[w] = ctx->ws_bytes;
+      if (!seq->V) {  // the sequence state could not be allocated: forget the sequence
+        used -= seq->state_bytes;
+        seqs.erase(req->seq);
       }
       (void)ticket;
     }
@@ -402,13 +432,28 @@ int chase_server_create(chase_server** out, int device, size_t mem_budget_bytes,
     (void)hipGetLastError();
     return CHASE_EDEVICE;
   }
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) {
+    (void)hipGetLastError();
+    return CHASE_EDEVICE;
+  }
+  // fixed device memory: the batchers' scratch, and per worker context its product scratch
+  // plus an allowance for the rocBLAS/rocSOLVER handle workspace
+  constexpr size_t kHandleAllowance = size_t{64} << 20;
+  const size_t fixed = chase_server::kClasses * Batcher::scratch_bytes() +
+                       static_cast<size_t>(workers) * (product_scratch_bytes(cus) + kHandleAllowance);
+  if (fixed >= mem_budget_bytes) return CHASE_EINVAL;
   auto* s = new chase_server();
   s->device = device;
   s->budget = mem_budget_bytes;
-  s->batcher.reset(new Batcher(device));
-  if (!s->batcher->ok()) {
-    delete s;
-    return CHASE_EDEVICE;
+  s->used = fixed;
+  s->fixed = fixed;
+  for (auto& b : s->batchers) {
+    b.reset(new Batcher(device));
+    if (!b->ok()) {
+      delete s;
+      return CHASE_EDEVICE;
+    }
   }
   s->worker_ws.assign(workers, 0);
   for (int w = 0; w < workers; ++w) s->workers.emplace_back([s, w] { s->worker(w); });
@@ -451,8 +496,9 @@ int chase_server_submit(chase_server* s, uint64_t seq_id, const chase_config* cf
     }
   }
   const size_t need = ws_bytes_of(*cfg, false) + state_bytes_of(*cfg);
-  if (need > s->budget) {
-    s->last_error = "request needs " + std::to_string(need) + " bytes, above the budget";
+  if (need > s->budget - s->fixed) {
+    s->last_error = "request needs " + std::to_string(need) +
+                    " bytes, above the budget left beside the server's fixed allocations";
     return CHASE_EBUSY;
   }
   chase_server::Req r;
@@ -506,7 +552,15 @@ int chase_server_vectors(chase_server* s, uint64_t seq_id, void** V, int64_t* ld
 int chase_server_info(chase_server* s, int64_t* grouped_launches, int64_t* grouped_products,
                       size_t* bytes_in_use) {
   if (!s) return CHASE_EINVAL;
-  s->batcher->counters(grouped_launches, grouped_products);
+  int64_t launches = 0, products = 0;
+  for (auto& b : s->batchers) {
+    int64_t l = 0, p = 0;
+    b->counters(&l, &p);
+    launches += l;
+    products += p;
+  }
+  if (grouped_launches) *grouped_launches = launches;
+  if (grouped_products) *grouped_products = products;
   std::lock_guard<std::mutex> lk(s->mu);
   if (bytes_in_use) *bytes_in_use = s->used;
   return CHASE_OK;
@@ -542,7 +596,7 @@ void chase_server_destroy(chase_server* s) {
   }
   s->cv.notify_all();
   for (auto& t : s->workers) t.join();
-  s->batcher.reset();
+  for (auto& b : s->batchers) b.reset();
   (void)hipSetDevice(s->device);
   for (auto& kv : s->seqs)
     if (kv.second.V) (void)hipFree(kv.second.V);

@@ -86,7 +86,15 @@ def test_budget_and_sequence_rules():
     H = capi.to_device(wl.hermitian_from(wl.haar_unitary(n, g), lam))
     cfg = capi.config(n, nev, nex, optim=1)
     need = capi.lib().chase_workspace_bytes(__import__("ctypes").byref(cfg)) + n * (nev + nex) * 16
-    srv = capi.Server(0, mem_budget_bytes=need + (1 << 20), workers=2)
+    # the server's fixed allocations (batcher scratch, per-worker product scratch and handle
+    # allowance) are charged at creation and reported as bytes in use
+    probe = capi.Server(0, mem_budget_bytes=64 << 30, workers=2)
+    fixed = probe.chase_server_info()["bytes_in_use"]
+    probe.close()
+    assert fixed > 0
+    with pytest.raises(capi.ChaseError):                            # budget below the fixed part
+        capi.Server(0, mem_budget_bytes=fixed, workers=2)
+    srv = capi.Server(0, mem_budget_bytes=fixed + need + (1 << 20), workers=2)
     with pytest.raises(capi.ChaseError) as ei:                      # alone above the budget
         big = capi.config(4 * n, 4 * nev, nex, optim=1)
         srv.chase_server_submit(9, big, H, 4 * n)
