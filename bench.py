@@ -1,9 +1,15 @@
 """Benchmark of the Chebyshev filter hot path on one MI355X.
 
 One step = one call of chase_filter (Algorithm 4: every product of the recurrence, the
-active-range schedule and the fused epilogue) on the order-10000 isolated problem with
-nev + nex = 600 search vectors (clustered spectrum, complex128), with a sorted even degree
-array spread over 2..36.  The metric is the algorithmic filter rate 8 n^2 sum(m_a) / time.
+active-range schedule and the fused epilogue) on the order-20000 problem with nev + nex = 1200
+search vectors (complex128 Hermitian H with the order-20000 sequence's clustered spectrum), with
+a sorted even degree array spread over 2..36, in the FP64 3M scheme that solves use.  The metric
+is the algorithmic filter rate 8 n^2 sum(m_a) / time.
+
+The same run adds the metric's other half and its context: time-to-solution of the warm-started
+order-20000 sequence (plain FP64 against the mixed FP32/FP64 filter), continuous-batching
+serving of 16 sequences x 8 problems (closed loop and Poisson arrivals: solves/s, p50/p99
+latency), the order-10000 isolated problem (filter and solve), and the oracle on the host cores.
 
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
@@ -45,11 +51,34 @@ def load_traffic(name: str):
     return d.get("hbm_bytes_per_launch")
 
 
+def host_record():
+    """The host the CPU baseline ran on: CPU model, physical and logical cores, the BLAS library
+    NumPy calls and its thread count."""
+    import psutil
+    from threadpoolctl import threadpool_info
+
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    blas = [i for i in threadpool_info() if i.get("user_api") == "blas"]
+    b = blas[0] if blas else {}
+    return {"cpu_model": model, "physical_cores": psutil.cpu_count(logical=False),
+            "logical_cpus": psutil.cpu_count(logical=True),
+            "affinity_cpus": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None,
+            "blas": f"{b.get('internal_api', '?')} {b.get('version', '?')} "
+                    f"({b.get('threading_layer', '?')}, {b.get('architecture', '?')})",
+            "blas_threads": int(b.get("num_threads", 1))}
+
+
 def cpu_baseline(H_host, V_host, deg, b_sup, mu_1, mu_b, budget_s=15.0):
     """Time the oracle's per-column filter on a bounded sample of columns (stops after the
     column that crosses ``budget_s`` seconds)."""
     import numpy as np
-    from threadpoolctl import threadpool_info
 
     from oracle import chebyshev as ch
 
@@ -64,16 +93,59 @@ def cpu_baseline(H_host, V_host, deg, b_sup, mu_1, mu_b, budget_s=15.0):
         used.append(int(c))
         if t_total > budget_s:
             break
-    threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    host = host_record()
     return {
         "value": done_flops / t_total / 1e12,
         "unit": "TFLOP/s",
-        "cores": int(threads),
+        "cores": host["blas_threads"],
         "kind": "oracle",
         "sample": f"oracle.chebyshev.filter_columns on {len(used)} of {V_host.shape[1]} columns "
                   f"(sum of degrees {sum(int(deg[c]) for c in used)}) of the same n={n} problem, "
                   f"{t_total:.1f} s",
+        "host": host,
     }
+
+
+def oracle_solve_baseline(ctx):
+    """Time-to-solution of the order-1000 isolated problem (nev 50, nex 20, uniform spectrum,
+    cold start, optim): the oracle's Alg. 1 on the host cores beside chase_solve on the device,
+    same H, start block and Lanczos start vectors."""
+    import numpy as np
+    import torch
+
+    from oracle import chase as och
+    from paper_1805_10121_amd import capi
+    from paper_1805_10121_amd import workloads as wl
+
+    c = wl.WORKLOADS["uniform_n1000"]
+    n, nev, nex = c["n"], c["nev"], c["nex"]
+    lam = wl.spectrum_for("uniform_n1000")
+    H = wl.hermitian(n, lam, 1001)
+    V0 = wl.start_block(n, nev + nex, 1500)
+    starts = wl.start_block(n, 5, 1600)
+    t0 = time.perf_counter()
+    ref = och.solve(H, och.ChaseParams(nev=nev, nex=nex, optim=True), V0, starts)
+    t_oracle = time.perf_counter() - t0
+    dH, dS = capi.to_device(H), capi.to_device(starts)
+    gpu = []
+    for _ in range(2):   # the first solve in a process pays rocBLAS/rocSOLVER kernel loading
+        cfg = capi.config(n, nev, nex, optim=1)
+        cfg.lanczos_start = dS.data_ptr()
+        dV = capi.to_device(V0)
+        ritzv, resid = np.zeros(nev + nex), np.zeros(nev + nex)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, st = ctx.chase_solve(cfg, dH, n, dV, n, ritzv, resid)
+        gpu.append(time.perf_counter() - t0)
+    host = host_record()
+    return {"workload": "isolated problem n=1000, nev=50, nex=20, uniform spectrum on [-1, 1], "
+                        "cold start, optim, tol 1e-10",
+            "oracle_s": round(t_oracle, 3), "oracle_iterations": ref["iterations"],
+            "oracle_cores": host["blas_threads"],
+            "gpu_s": round(gpu[1], 4), "gpu_first_in_process_s": round(gpu[0], 4),
+            "gpu_status": rc, "gpu_iterations": st.iterations,
+            "max_eig_diff_gpu_vs_oracle": float(np.max(np.abs(ritzv[:nev] - ref["ritzv"][:nev]))),
+            "speedup": round(t_oracle / gpu[1], 1)}
 
 
 def make_sequence_problem(n, lam, k, eps, seed, prev=None, norm=None):
@@ -120,7 +192,8 @@ def make_sequence_problem(n, lam, k, eps, seed, prev=None, norm=None):
 SEQUENCES = {"n20000": "sequence_n20000", "n60000": "sequence_n60000"}
 
 
-def run_sequence(args):
+def run_sequence(sequence="n20000", order=None, problems=None, modes=("fp64", "mixed"),
+                 switch_resid=(1e-6,), deg_max_fp32=(18,), verbose=True):
     """Warm-started sequence (order 20000, nev 1000, nex 200, eps 1e-3 by default): total
     time-to-solution with the plain FP64 filter and with the mixed FP32/FP64 filter."""
     import numpy as np
@@ -129,28 +202,28 @@ def run_sequence(args):
     from paper_1805_10121_amd import capi
     from paper_1805_10121_amd import workloads as wl
 
-    name = SEQUENCES[args.sequence]
+    name = SEQUENCES[sequence]
     c = wl.WORKLOADS[name]
-    n = args.order or c["n"]
+    n = order or c["n"]
     nev = max(1, round(c["nev"] * n / c["n"]))
     nex = max(1, round(c["nex"] * n / c["n"]))
     eps = c["eps"]
-    problems = args.problems or c["problems"]
+    problems = problems or c["problems"]
     lam = wl.spectrum_for(name, n=n)
     norm = float(np.max(np.abs(lam)))
     ctx = capi.Context(0)
     res = {}
-    modes = [("fp64", capi.CHASE_FP64, None, None)] if "fp64" in args.modes else []
-    if "fp64_4m" in args.modes:   # the FP64 filter with 4M products on H itself (no planar copy)
-        modes.append(("fp64_4m", capi.CHASE_FP64, None, None))
-    for sw in (args.switch_resid if "mixed" in args.modes else []):
-        for dm in args.deg_max_fp32:
-            name = "mixed" if (len(args.switch_resid) == 1 and len(args.deg_max_fp32) == 1) \
+    runs = [("fp64", capi.CHASE_FP64, None, None)] if "fp64" in modes else []
+    if "fp64_4m" in modes:   # the FP64 filter with 4M products on H itself (no planar copy)
+        runs.append(("fp64_4m", capi.CHASE_FP64, None, None))
+    for sw in (switch_resid if "mixed" in modes else []):
+        for dm in deg_max_fp32:
+            label = "mixed" if (len(switch_resid) == 1 and len(deg_max_fp32) == 1) \
                 else f"mixed sw={sw:g} dm={dm}"
-            modes.append((name, capi.CHASE_MIXED, sw, dm))
-    for mode, prec, sw, dm in modes:
+            runs.append((label, capi.CHASE_MIXED, sw, dm))
+    for mode, prec, sw, dm in runs:
         cfg = capi.config(n, nev, nex, optim=1, precision=prec, seed=3000)
-        cfg.verbose = 1
+        cfg.verbose = 1 if verbose else 0
         if mode == "fp64_4m":
             cfg.filter_3m = 0
         if sw is not None:
@@ -228,12 +301,16 @@ class _SeqSource:
         return H
 
 
-def run_serving(n_seq=16, problems=8, rates=(0.5, 0.8, 1.0), sizes=(2000, 4000, 8000, 16000),
+def run_serving(n_seq=16, problems=8, rates=(0.8,), sizes=(2000, 4000, 8000, 16000),
                 workers=8, precision_name="mixed", seed=4000):
     """Continuous-batching serving of n_seq sequences: a closed-loop run (each sequence submits
     its next problem when the previous finishes) measures the saturated throughput X; then
-    Poisson arrivals (each sequence its own process of rate r/n_seq) at r = f * X for f in
-    rates.  Latency = completion - arrival."""
+    Poisson arrivals at r = f * X for f in rates.  The arrivals form one Poisson process of rate
+    r (exponential gaps of mean 1/r); arrival j is the next problem of sequence j mod n_seq, so
+    every sequence receives its problems in order and the last one arrives after about
+    n_seq * problems / r seconds.  A problem that arrives while its sequence's previous one is
+    still running waits in the server (it is warm-started from that solution).
+    Latency = completion - arrival; p50/p99 are reported over all solves and per order n."""
     import numpy as np
     import torch
 
@@ -249,15 +326,17 @@ def run_serving(n_seq=16, problems=8, rates=(0.5, 0.8, 1.0), sizes=(2000, 4000, 
         cfgs = [capi.config(src.n, src.nev, src.nex, optim=1, precision=prec, seed=seed + s)
                 for s, src in enumerate(srcs)]
         g = wl.rng(seed + 999)
-        t0 = time.perf_counter()
+        total = n_seq * problems
         if rate is None:
             arrivals = [[0.0] + [None] * (problems - 1) for _ in range(n_seq)]
         else:
-            arrivals = [list(np.cumsum(g.exponential(n_seq / rate, problems))) for _ in range(n_seq)]
+            times = np.cumsum(g.exponential(1.0 / rate, total))
+            arrivals = [[float(times[k * n_seq + s]) for k in range(problems)] for s in range(n_seq)]
+        t0 = time.perf_counter()
         nxt = [0] * n_seq
         live = {}          # ticket -> (sid, k, arrival_time, H)
-        lat, errs, iters = [], [], []
-        done_count, total = 0, n_seq * problems
+        lat, lat_n, errs, iters = [], [], [], []
+        done_count = 0
         busy = [False] * n_seq
         first_arr = None
         while done_count < total:
@@ -287,6 +366,7 @@ def run_serving(n_seq=16, problems=8, rates=(0.5, 0.8, 1.0), sizes=(2000, 4000, 
                 s, k, ta, H = live.pop(t)
                 t_end = time.perf_counter() - t0
                 lat.append(t_end - ta)
+                lat_n.append(ns[s])
                 iters.append(st.iterations)
                 src = srcs[s]
                 if rc != 0:
@@ -299,7 +379,7 @@ def run_serving(n_seq=16, problems=8, rates=(0.5, 0.8, 1.0), sizes=(2000, 4000, 
                 busy[s] = any(v[0] == s for v in live.values())
                 done_count += 1
                 last_end = t_end
-                if done_count % 8 == 0 or done_count == total:
+                if done_count % 16 == 0 or done_count == total:
                     log(f"serving ({'closed loop' if rate is None else f'rate {rate:.3f}/s'}): "
                         f"{done_count}/{total} solves done at {t_end:.1f} s")
             time.sleep(0.0005)
@@ -308,11 +388,16 @@ def run_serving(n_seq=16, problems=8, rates=(0.5, 0.8, 1.0), sizes=(2000, 4000, 
         del srcs
         torch.cuda.empty_cache()
         span = last_end - (first_arr or 0.0)
-        lat = np.array(lat)
+        lat, lat_n = np.array(lat), np.array(lat_n)
+        by_n = {str(int(m)): {"solves": int(np.sum(lat_n == m)),
+                              "p50_latency_s": round(float(np.percentile(lat[lat_n == m], 50)), 4),
+                              "p99_latency_s": round(float(np.percentile(lat[lat_n == m], 99)), 4)}
+                for m in sorted(set(lat_n.tolist()))}
         return {"solves": total, "span_s": round(span, 3), "solves_per_s": round(total / span, 3),
                 "p50_latency_s": round(float(np.percentile(lat, 50)), 4),
                 "p99_latency_s": round(float(np.percentile(lat, 99)), 4),
-                "max_error_over_normH": max(errs), "mean_iterations": float(np.mean(iters)),
+                "by_order": by_n,
+                "max_error_over_normH": max(errs), "mean_iterations": round(float(np.mean(iters)), 3),
                 "grouped_products_per_launch": round(info["grouped_products"] /
                                                      max(1, info["grouped_launches"]), 2)}
 
@@ -376,20 +461,40 @@ def run_ablation(name="uniform_n1000", degrees=(8, 12, 16, 20, 24, 28, 32, 36)):
             "rows": rows}
 
 
+def _timed(stream, reps, fn):
+    """Run fn reps times between two HIP events on ``stream`` (the library's stream); returns
+    (wall seconds, event milliseconds)."""
+    import torch
+
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(reps):
+        fn()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, ev0.elapsed_time(ev1)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only the timed order-20000 filter (for profiler and counter runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
-    ap.add_argument("--no-solve", action="store_true")
-    ap.add_argument("--no-n20000", action="store_true",
-                    help="skip the filter measurement at the order-20000 shape")
+    ap.add_argument("--no-n10000", action="store_true",
+                    help="skip the order-10000 isolated problem (filter and solves)")
+    ap.add_argument("--no-sequence", action="store_true",
+                    help="skip the order-20000 sequence leg (FP64 against mixed time-to-solution)")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
     ap.add_argument("--workload", choices=["filter", "sequence", "serving", "ablation"],
                     default="filter",
-                    help="filter: the hot-path benchmark (default); sequence: time-to-solution of "
-                         "a warm-started sequence, plain FP64 against the mixed FP32/FP64 filter")
+                    help="filter: the hot-path benchmark with its sequence and serving legs "
+                         "(default); sequence, serving, ablation: one of the other workloads alone")
     ap.add_argument("--problems", type=int, default=None,
                     help="sequence: problems (default: the config's); serving: per sequence (8)")
     ap.add_argument("--sequence", choices=sorted(SEQUENCES), default="n20000",
@@ -407,16 +512,13 @@ def main():
     ap.add_argument("--deg-max-fp32", type=int, nargs="*", default=[18],
                     help="sequence workload: mixed-mode FP32 degree caps to run")
     ap.add_argument("--serving-workers", type=int, default=8,
-                    help="serving workload: concurrent solves in the server")
-    ap.add_argument("--serving-rates", type=float, nargs="*", default=[0.5, 0.8, 1.0],
-                    help="serving workload: Poisson rates as fractions of the closed-loop rate")
+                    help="serving: concurrent solves in the server")
+    ap.add_argument("--serving-rates", type=float, nargs="*", default=[0.8],
+                    help="serving: Poisson rates as fractions of the closed-loop rate")
     ap.add_argument("--serving-precision", choices=["mixed", "fp64"], default="mixed",
-                    help="serving workload: filter precision of the served solves")
+                    help="serving: filter precision of the served solves")
     ap.add_argument("--order", type=int, default=None,
                     help="sequence workload: order (default: the config's)")
-    ap.add_argument("--h-gen", choices=["haar", "structured"], default="haar",
-                    help="H for the filter workload: Haar Q (QR of a Gaussian) or the structured "
-                         "reflector unitary (no QR; used for counter-collection runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy three times (counter calibration)")
     args = ap.parse_args()
@@ -441,7 +543,9 @@ def main():
     from paper_1805_10121_amd import workloads as wl
 
     if args.workload == "sequence":
-        print(json.dumps(run_sequence(args)), flush=True)
+        print(json.dumps(run_sequence(args.sequence, args.order, args.problems, tuple(args.modes),
+                                      tuple(args.switch_resid), tuple(args.deg_max_fp32))),
+              flush=True)
         return
     if args.workload == "ablation":
         out = {w: run_ablation(w) for w in args.ablation_workloads}
@@ -454,16 +558,26 @@ def main():
               flush=True)
         return
 
-    cfg = wl.WORKLOADS["clustered_n10000"]
-    n, nb = cfg["n"], cfg["nev"] + cfg["nex"]
-    lam = wl.spectrum_for("clustered_n10000")
-    log(f"bench: generating H (n={n}, {args.h_gen}) on the device")
-    dH = (wl.hermitian_torch(n, lam, seed=2001) if args.h_gen == "haar"
-          else wl.hermitian_torch_fast(n, lam, seed=2001))
-    V = wl.start_block(n, nb, 2500)
+    t_start = time.perf_counter()
+    sections = {}
+
+    def section(name, t0):
+        sections[name] = round(time.perf_counter() - t0, 1)
+        log(f"bench: {name} took {sections[name]} s")
+
+    # ---- headline: the FP64 filter at the order-20000 shape (nev 1000 + nex 200 columns) ----
+    t0 = time.perf_counter()
+    wname = "sequence_n20000"
+    c = wl.WORKLOADS[wname]
+    n, nb = c["n"], c["nev"] + c["nex"]
+    lam = wl.spectrum_for(wname)
+    log(f"bench: generating H (n={n}, structured unitary) on the device")
+    dH = wl.hermitian_torch_fast(n, lam, seed=3001)
+    V = wl.start_block(n, nb, 3500)
     deg = wl.optimized_degree_profile(nb, 36)
     b_sup, mu_1, mu_b = float(lam[-1]) + 0.05, float(lam[0]), float(lam[nb - 1])
     ctx = capi.Context(0)
+    stream = ctx.stream
     dV = capi.to_device(V)
     dW = torch.empty_like(dV)
     flops = 8.0 * n * n * float(deg.sum())
@@ -478,25 +592,13 @@ def main():
 
     for _ in range(args.warmup):
         step()
-    torch.cuda.synchronize()
-    stream = torch.cuda.current_stream()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ev0.record(stream)
-    for _ in range(args.steps):
-        step()
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ev_ms = ev0.elapsed_time(ev1)
+    wall, ev_ms = _timed(stream, args.steps, step)
     ms_per_step = wall * 1e3 / args.steps
     value = flops * args.steps / wall / 1e12
     avg_launch_ms = ev_ms / (args.steps * launches)
     achieved = (flops / launches) / (avg_launch_ms * 1e-3) / 1e12
-    log(f"bench: fp64 filter {value:.2f} TFLOP/s wall, {achieved:.2f} TFLOP/s by events, "
+    log(f"bench: fp64 filter n={n} {value:.2f} TFLOP/s wall, {achieved:.2f} TFLOP/s by events, "
         f"{ms_per_step:.3f} ms/step")
-
     out = {
         "metric": "filter TFLOP/s (% MFMA peak); solves/s + p99 latency at resid 1e-10",
         "value": round(value, 3),
@@ -511,9 +613,10 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": "chebyshev filter, isolated problem n=10000, nev=500, nex=100, "
-                        "complex128 Hermitian H = Q diag(lam) Q^H (Haar Q, clustered spectrum), "
-                        "sorted even degrees uniform over 2..36",
+            "workload": f"chebyshev filter, n={n}, nev=1000, nex=200 ({nb} columns), complex128 "
+                        "Hermitian H = Q diag(lam) Q^H (structured unitary Q, clustered spectrum "
+                        "of the order-20000 sequence), sorted even degrees uniform over 2..36, "
+                        "FP64 3M products on the planar copy of H",
             "n": n, "ncols": nb, "sum_degrees": int(deg.sum()), "launches_per_step": launches,
             "parallelism": "single GPU",
         },
@@ -526,9 +629,10 @@ def main():
             "peak": FP64_PEAK_TF,
             "unit": "TFLOP/s",
             "frac": round(achieved / FP64_PEAK_TF, 4),
-            "traffic": load_traffic("traffic_hemm_step_fp64_3m_n10000.json"),
+            "traffic": load_traffic("traffic_hemm_step_fp64_3m_n20000.json"),
             "per_launch": {"algorithmic_flops": flops / launches,
                            "executed_flops": 0.75 * flops / launches,
+                           "algorithmic_bytes": 16.0 * n * n + 48.0 * n * float(deg.sum()) / launches,
                            "avg_duration_ms": round(avg_launch_ms, 5)},
             "flop_convention": "algorithmic = 8 n^2 real flops per active column and product "
                                "(one complex multiply-add = 8 real flops, what the 4M scheme "
@@ -536,36 +640,38 @@ def main():
             "executed_frac": round(0.75 * achieved / FP64_PEAK_TF, 4),
         },
     }
+    section("headline", t0)
+    if args.headline_only:
+        print(json.dumps(out), flush=True)
+        ctx.close()
+        return
 
-    # the same filter with the 4M scheme on interleaved H (chase_config.filter_3m = 0)
-    reps4 = max(1, min(args.steps, 5))
-    ctx.chase_filter(capi.CHASE_FP64, dH, n, n, dV, dW, n, nb, deg, b_sup, mu_1, mu_b)
-    torch.cuda.synchronize()
-    ev0.record(stream)
-    for _ in range(reps4):
+    # ---- the same filter with the 4M scheme on interleaved H (chase_config.filter_3m = 0) ----
+    t0 = time.perf_counter()
+    reps = 3
+
+    def step4():
         ctx.chase_filter(capi.CHASE_FP64, dH, n, n, dV, dW, n, nb, deg, b_sup, mu_1, mu_b)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    tf4 = flops * reps4 / (ev0.elapsed_time(ev1) * 1e-3) / 1e12
+
+    step4()
+    _, ms = _timed(stream, reps, step4)
+    tf4 = flops * reps / (ms * 1e-3) / 1e12
     out["filter_4m"] = {"value": round(tf4, 3), "unit": "TFLOP/s", "peak": FP64_PEAK_TF,
-                        "frac": round(tf4 / FP64_PEAK_TF, 4), "steps": reps4,
+                        "frac": round(tf4 / FP64_PEAK_TF, 4), "steps": reps,
                         "workload": "the same filter, 4M products on interleaved complex128 H"}
     log(f"bench: fp64 filter with 4M products: {tf4:.2f} TFLOP/s")
 
     # thin blocks (the Lanczos block, a filter's last columns) are HBM-bound: H read per product
     thin = []
     for nc in (5, 16):
-        dX = dV[:nc]
-        dO = dW[:nc]
-        ctx.chase_hemm_step(capi.CHASE_FP64, dH, n, n, dX, n, dO, n, nc, 1.0, 0.0, 0.0)
-        torch.cuda.synchronize()
-        reps = 20
-        ev0.record(stream)
-        for _ in range(reps):
+        dX, dO = dV[:nc], dW[:nc]
+
+        def thin_step():
             ctx.chase_hemm_step(capi.CHASE_FP64, dH, n, n, dX, n, dO, n, nc, 1.0, 0.0, 0.0)
-        ev1.record(stream)
-        torch.cuda.synchronize()
-        ms = ev0.elapsed_time(ev1) / reps
+
+        thin_step()
+        _, ms = _timed(stream, 20, thin_step)
+        ms /= 20
         hbytes = 16.0 * n * n + 32.0 * n * nc   # H once, X read, OUT written
         thin.append({"ncols": nc, "ms_per_product": round(ms, 4),
                      "algorithmic_GBps": round(hbytes / (ms * 1e-3) / 1e9, 1),
@@ -574,64 +680,130 @@ def main():
     log(f"bench: thin products {thin}")
 
     if not args.no_fp32:
+        # the mixed solver's FP32 stage (3M on planar complex64 H) and the 4M FP32 filter
         h32 = torch.empty((n, n), dtype=torch.complex64, device="cuda")
         v32 = torch.empty((nb, n), dtype=torch.complex64, device="cuda")
         w32 = torch.empty_like(v32)
-        ctx.chase_convert_c128_to_c64(dH, n, h32, n, n, n)
-        ctx.chase_convert_c128_to_c64(dV, n, v32, n, n, nb)
         deg32 = wl.optimized_degree_profile(nb, 18)
         fl32 = 8.0 * n * n * float(deg32.sum())
-        for _ in range(2):
-            ctx.chase_filter(capi.CHASE_FP32, h32, n, n, v32, w32, n, nb, deg32, b_sup, mu_1, mu_b)
-        torch.cuda.synchronize()
-        ev0.record(stream)
-        for _ in range(args.steps):
-            ctx.chase_filter(capi.CHASE_FP32, h32, n, n, v32, w32, n, nb, deg32, b_sup, mu_1, mu_b)
-        ev1.record(stream)
-        torch.cuda.synchronize()
-        tf32 = fl32 * args.steps / (ev0.elapsed_time(ev1) * 1e-3) / 1e12
-        out["fp32_filter"] = {"value": round(tf32, 3), "unit": "TFLOP/s", "peak": FP32_PEAK_TF,
-                              "frac": round(tf32 / FP32_PEAK_TF, 4),
-                              "degrees": "sorted even, uniform over 2..18"}
-        log(f"bench: fp32 filter {tf32:.2f} TFLOP/s")
-        # the mixed solver's FP32 stage: 3M products on planar complex64 H
-        ctx.chase_convert_c128_to_planar32(dH, n, h32, n, n)   # h32 reused as two n x n planes
+        ctx.chase_convert_c128_to_planar32(dH, n, h32, n, n)   # two n x n float planes
         ctx.chase_convert_c128_to_c64(dV, n, v32, n, n, nb)
-        for _ in range(2):
-            ctx.chase_filter(capi.CHASE_FP32_3M, h32, n, n, v32, w32, n, nb, deg32, b_sup, mu_1,
-                             mu_b)
-        torch.cuda.synchronize()
-        ev0.record(stream)
-        for _ in range(args.steps):
-            ctx.chase_filter(capi.CHASE_FP32_3M, h32, n, n, v32, w32, n, nb, deg32, b_sup, mu_1,
-                             mu_b)
-        ev1.record(stream)
-        torch.cuda.synchronize()
-        tf3m = fl32 * args.steps / (ev0.elapsed_time(ev1) * 1e-3) / 1e12
-        out["fp32_3m_filter"] = {"value": round(tf3m, 3), "unit": "TFLOP/s (complex-equivalent, 8n^2 per column and product)",
-                                 "peak": FP32_PEAK_TF, "frac": round(tf3m / FP32_PEAK_TF, 4),
-                                 "degrees": "sorted even, uniform over 2..18",
-                                 "note": "3M executes 6n^2 real flops per column and product"}
-        log(f"bench: fp32 3M filter {tf3m:.2f} TFLOP/s complex-equivalent")
-        del h32, v32, w32
 
-    if not args.no_solve:
-        # time-to-solution of the same problem (cold start, FP64, per-vector degrees)
-        # The first solve in a process also pays rocBLAS/rocSOLVER's one-time kernel loading;
-        # the second (same inputs) is the steady state a sequence or a server sees.
-        cfgs = capi.config(n, cfg["nev"], cfg["nex"], optim=1, seed=2600)
+        def step3m():
+            ctx.chase_filter(capi.CHASE_FP32_3M, h32, n, n, v32, w32, n, nb, deg32, b_sup, mu_1,
+                             mu_b)
+
+        step3m()
+        _, ms = _timed(stream, 5, step3m)
+        tf3m = fl32 * 5 / (ms * 1e-3) / 1e12
+        out["fp32_3m_filter"] = {
+            "value": round(tf3m, 3),
+            "unit": "TFLOP/s (complex-equivalent, 8n^2 per column and product)",
+            "peak": FP32_PEAK_TF, "frac": round(tf3m / FP32_PEAK_TF, 4),
+            "executed_frac": round(0.75 * tf3m / FP32_PEAK_TF, 4), "steps": 5,
+            "workload": f"the mixed solver's FP32 stage: n={n}, {nb} columns, sorted even degrees "
+                        "uniform over 2..18, 3M products on planar complex64 H with FP64 sums "
+                        "across K stages"}
+        log(f"bench: fp32 3M filter {tf3m:.2f} TFLOP/s complex-equivalent")
+        ctx.chase_convert_c128_to_c64(dH, n, h32, n, n, n)     # interleaved complex64 H
+        ctx.chase_convert_c128_to_c64(dV, n, v32, n, n, nb)
+
+        def step32():
+            ctx.chase_filter(capi.CHASE_FP32, h32, n, n, v32, w32, n, nb, deg32, b_sup, mu_1, mu_b)
+
+        step32()
+        _, ms = _timed(stream, 3, step32)
+        tf32 = fl32 * 3 / (ms * 1e-3) / 1e12
+        out["fp32_filter"] = {"value": round(tf32, 3), "unit": "TFLOP/s", "peak": FP32_PEAK_TF,
+                              "frac": round(tf32 / FP32_PEAK_TF, 4), "steps": 3,
+                              "workload": "the same FP32 filter with 4M products on interleaved "
+                                          "complex64 H"}
+        log(f"bench: fp32 filter {tf32:.2f} TFLOP/s")
+        del h32, v32, w32
+    section("filter_variants", t0)
+
+    if not args.no_cpu_baseline:
+        t0 = time.perf_counter()
+        log("bench: cpu baseline (oracle on a column sample)")
+        H_host = np.asfortranarray(capi.from_device(dH))
+        out["cpu_baseline"] = cpu_baseline(H_host, V, deg, b_sup, mu_1, mu_b)
+        del H_host
+        section("cpu_baseline", t0)
+    del dHp, dH, dV, dW
+    torch.cuda.empty_cache()
+
+    # the real symmetric instance at the same shape: 2 n^2 flops per column and product
+    t0 = time.perf_counter()
+    dHr = wl.symmetric_torch_fast(n, lam, seed=3002)
+    dVr = capi.to_device(wl.rng(3501).standard_normal((n, nb)))
+    dWr = torch.empty_like(dVr)
+    flr = 2.0 * n * n * float(deg.sum())
+
+    def stepr():
+        ctx.chase_filter(capi.CHASE_REAL_FP64, dHr, n, n, dVr, dWr, n, nb, deg, b_sup, mu_1, mu_b)
+
+    stepr()
+    _, ms = _timed(stream, 3, stepr)
+    tfr = flr * 3 / (ms * 1e-3) / 1e12
+    out["filter_real"] = {
+        "value": round(tfr, 3), "unit": "TFLOP/s", "peak": FP64_PEAK_TF,
+        "frac": round(tfr / FP64_PEAK_TF, 4), "ms_per_step": round(ms / 3, 3), "steps": 3,
+        "workload": f"chebyshev filter, real symmetric float64 H (structured orthogonal Q), "
+                    f"n={n}, {nb} columns, degrees 2..36; 2 n^2 flops per column product"}
+    log(f"bench: real fp64 filter: {tfr:.2f} TFLOP/s")
+    del dHr, dVr, dWr
+    torch.cuda.empty_cache()
+    section("filter_real", t0)
+
+    if not args.no_n10000:
+        # ---- the order-10000 isolated problem: filter and time-to-solution ----
+        t0 = time.perf_counter()
+        c2 = wl.WORKLOADS["clustered_n10000"]
+        n2, nb2 = c2["n"], c2["nev"] + c2["nex"]
+        lam2 = wl.spectrum_for("clustered_n10000")
+        log(f"bench: generating H (n={n2}, Haar Q) on the device")
+        dH2 = wl.hermitian_torch(n2, lam2, seed=2001)
+        V2 = wl.start_block(n2, nb2, 2500)
+        deg2 = wl.optimized_degree_profile(nb2, 36)
+        b2, m12, mb2 = float(lam2[-1]) + 0.05, float(lam2[0]), float(lam2[nb2 - 1])
+        dV2 = capi.to_device(V2)
+        dW2 = torch.empty_like(dV2)
+        dHp2 = torch.empty(2 * n2 * n2, dtype=torch.float64, device="cuda")
+        ctx.chase_convert_c128_to_planar64(dH2, n2, dHp2, n2, n2)
+        fl2 = 8.0 * n2 * n2 * float(deg2.sum())
+
+        def step2():
+            ctx.chase_filter(capi.CHASE_FP64_3M, dHp2, n2, n2, dV2, dW2, n2, nb2, deg2, b2, m12,
+                             mb2)
+
+        step2()
+        _, ms = _timed(stream, 5, step2)
+        tf2 = fl2 * 5 / (ms * 1e-3) / 1e12
+        out["filter_n10000"] = {
+            "value": round(tf2, 3), "unit": "TFLOP/s", "peak": FP64_PEAK_TF,
+            "frac": round(tf2 / FP64_PEAK_TF, 4), "ms_per_step": round(ms / 5, 3), "steps": 5,
+            "avg_product_ms": round(ms / 5 / int(deg2.max()), 4),
+            "traffic": load_traffic("traffic_hemm_step_fp64_3m_n10000.json"),
+            "workload": f"chebyshev filter, isolated problem n={n2}, nev=500, nex=100, complex128 "
+                        "H = Q diag(lam) Q^H (Haar Q, clustered spectrum), degrees 2..36, FP64 3M"}
+        log(f"bench: fp64 filter n={n2}: {tf2:.2f} TFLOP/s")
+        del dHp2, dW2
+        # time-to-solution (cold start, FP64, per-vector degrees).  The first solve in a process
+        # also pays rocBLAS/rocSOLVER's one-time kernel loading; the second (same inputs) is the
+        # steady state a sequence or a server sees.
+        cfgs = capi.config(n2, c2["nev"], c2["nex"], optim=1, seed=2600)
         times = []
         for _ in range(2):
-            dV0 = capi.to_device(V)
-            ritzv, resid = np.zeros(nb), np.zeros(nb)
+            dV0 = capi.to_device(V2)
+            ritzv, resid = np.zeros(nb2), np.zeros(nb2)
             torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            rc, st = ctx.chase_solve(cfgs, dH, n, dV0, n, ritzv, resid)
-            times.append(time.perf_counter() - t0)
-        t_solve = times[1]
-        normH = float(np.max(np.abs(lam)))
-        out["solve"] = {
-            "status": rc, "time_s": round(t_solve, 4), "solves_per_s": round(1.0 / t_solve, 4),
+            t1 = time.perf_counter()
+            rc, st = ctx.chase_solve(cfgs, dH2, n2, dV0, n2, ritzv, resid)
+            times.append(time.perf_counter() - t1)
+        normH = float(np.max(np.abs(lam2)))
+        nev2 = c2["nev"]
+        out["solve_n10000"] = {
+            "status": rc, "time_s": round(times[1], 4), "solves_per_s": round(1.0 / times[1], 4),
             "first_solve_in_process_s": round(times[0], 4),
             "iterations": st.iterations, "matvecs": st.matvecs, "qr_fallbacks": st.qr_fallbacks,
             "filter_tflops": round(st.filter_flops / (st.filter_ms * 1e-3) / 1e12, 3),
@@ -640,110 +812,73 @@ def main():
                          "orthogonalize": round(st.ortho_ms, 1),
                          "rayleigh_ritz": round(st.rr_ms, 1), "residuals": round(st.resid_ms, 1),
                          "total": round(st.total_ms, 1)},
-            "max_eig_error_over_normH": float(np.max(np.abs(ritzv[:cfg["nev"]] - lam[:cfg["nev"]])) / normH),
-            "max_resid_over_normH": float(np.max(resid[:cfg["nev"]]) / normH),
-        }
-        log(f"bench: solve {t_solve:.3f} s, {st.iterations} iterations")
+            "max_eig_error_over_normH": float(np.max(np.abs(ritzv[:nev2] - lam2[:nev2])) / normH),
+            "max_resid_over_normH": float(np.max(resid[:nev2]) / normH),
+            "workload": "the order-10000 problem solved cold (Lanczos + DoS), FP64 filter, optim"}
+        log(f"bench: solve n={n2} {times[1]:.3f} s, {st.iterations} iterations")
         del dV0
-        # the same problem solved wholly in single precision (complex64 H and block) with
-        # Table 1's single-precision defaults (tol 1e-5, deg 10, deg_max 18, k 12)
-        h32 = torch.empty((n, n), dtype=torch.complex64, device="cuda")
-        ctx.chase_convert_c128_to_c64(dH, n, h32, n, n, n)
-        cfg32 = capi.config_fp32(n, cfg["nev"], cfg["nex"], optim=1, seed=2600)
-        times32 = []
-        for _ in range(2):
-            dV0 = capi.to_device(V).to(torch.complex64)
-            ritzv, resid = np.zeros(nb), np.zeros(nb)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            rc32, st32 = ctx.chase_solve(cfg32, h32, n, dV0, n, ritzv, resid)
-            times32.append(time.perf_counter() - t0)
-        out["solve_fp32"] = {
-            "status": rc32, "time_s": round(times32[1], 4),
-            "first_solve_in_process_s": round(times32[0], 4), "tol": cfg32.tol,
-            "iterations": st32.iterations, "matvecs": st32.matvecs,
-            "qr_fallbacks": st32.qr_fallbacks,
-            "filter_tflops": round(st32.filter_flops / (st32.filter_ms * 1e-3) / 1e12, 3),
-            "phase_ms": {"lanczos": round(st32.lanczos_ms, 1),
-                         "filter": round(st32.filter_ms, 1),
-                         "orthogonalize": round(st32.ortho_ms, 1),
-                         "rayleigh_ritz": round(st32.rr_ms, 1),
-                         "residuals": round(st32.resid_ms, 1), "total": round(st32.total_ms, 1)},
-            "max_eig_error_over_normH": float(np.max(np.abs(ritzv[:cfg["nev"]] - lam[:cfg["nev"]])) / normH),
-            "max_resid_over_normH": float(np.max(resid[:cfg["nev"]]) / normH),
-            "workload": "the solve above in complex64 with Table 1's single-precision defaults"}
-        log(f"bench: fp32 solve {times32[1]:.3f} s, {st32.iterations} iterations")
-        del dV0, h32
-
-    if not args.no_n20000:
-        # the same filter at the order-20000 shape (1200 columns, degrees 2..36)
-        n2, nb2 = 20000, 1200
-        lam2 = wl.spectrum_for("sequence_n20000")
-        dH2 = wl.hermitian_torch_fast(n2, lam2, seed=3001)
-        dV2 = capi.to_device(wl.start_block(n2, nb2, 3500))
-        dW2 = torch.empty_like(dV2)
-        deg2 = wl.optimized_degree_profile(nb2, 36)
-        b2, m12, mb2 = float(lam2[-1]) + 0.05, float(lam2[0]), float(lam2[nb2 - 1])
-        fl2 = 8.0 * n2 * n2 * float(deg2.sum())
-        dHp2 = torch.empty(2 * n2 * n2, dtype=torch.float64, device="cuda")
-        ctx.chase_convert_c128_to_planar64(dH2, n2, dHp2, n2, n2)
-        reps = 3
-        res2 = {}
-        for name, prec, h in (("3m", capi.CHASE_FP64_3M, dHp2), ("4m", capi.CHASE_FP64, dH2)):
-            ctx.chase_filter(prec, h, n2, n2, dV2, dW2, n2, nb2, deg2, b2, m12, mb2)
-            torch.cuda.synchronize()
-            ev0.record(stream)
-            for _ in range(reps):
-                ctx.chase_filter(prec, h, n2, n2, dV2, dW2, n2, nb2, deg2, b2, m12, mb2)
-            ev1.record(stream)
-            torch.cuda.synchronize()
-            res2[name] = ev0.elapsed_time(ev1) / reps
-        ms2 = res2["3m"]
-        tf2 = fl2 / (ms2 * 1e-3) / 1e12
-        tf2_4m = fl2 / (res2["4m"] * 1e-3) / 1e12
-        out["filter_n20000"] = {
-            "value": round(tf2, 3), "unit": "TFLOP/s", "peak": FP64_PEAK_TF,
-            "frac": round(tf2 / FP64_PEAK_TF, 4), "executed_frac": round(0.75 * tf2 / FP64_PEAK_TF, 4),
-            "ms_per_step": round(ms2, 3), "steps": reps,
-            "value_4m": round(tf2_4m, 3), "frac_4m": round(tf2_4m / FP64_PEAK_TF, 4),
-            "workload": "chebyshev filter, n=20000, 1200 columns, sorted even degrees uniform over "
-                        "2..36, complex128 H = Q diag(lam) Q^H (structured reflector Q, order-20000 "
-                        "spectrum); value: 3M products on planar H (the solver's default), "
-                        "value_4m: 4M products on interleaved H"}
-        log(f"bench: fp64 filter at n=20000: {tf2:.2f} TFLOP/s (3M), {tf2_4m:.2f} (4M)")
-        del dHp2
-        del dH2, dV2, dW2
-        torch.cuda.empty_cache()
-        # the real symmetric instance at the same shape: 2 n^2 flops per column and product
-        dH2 = wl.symmetric_torch_fast(n2, lam2, seed=3002)
-        dV2 = capi.to_device(wl.rng(3501).standard_normal((n2, nb2)))
-        dW2 = torch.empty_like(dV2)
-        flr = 2.0 * n2 * n2 * float(deg2.sum())
-        ctx.chase_filter(capi.CHASE_REAL_FP64, dH2, n2, n2, dV2, dW2, n2, nb2, deg2, b2, m12, mb2)
+        # the same problem in mixed precision and wholly in single precision (complex64 H and
+        # block, Table 1's single-precision defaults, tol 1e-5)
+        cfgm = capi.config(n2, c2["nev"], c2["nex"], optim=1, seed=2600,
+                           precision=capi.CHASE_MIXED)
+        dV0 = capi.to_device(V2)
+        ritzv, resid = np.zeros(nb2), np.zeros(nb2)
         torch.cuda.synchronize()
-        ev0.record(stream)
-        for _ in range(reps):
-            ctx.chase_filter(capi.CHASE_REAL_FP64, dH2, n2, n2, dV2, dW2, n2, nb2, deg2, b2, m12,
-                             mb2)
-        ev1.record(stream)
+        t1 = time.perf_counter()
+        rcm, stm = ctx.chase_solve(cfgm, dH2, n2, dV0, n2, ritzv, resid)
+        tm = time.perf_counter() - t1
+        out["solve_n10000_mixed"] = {
+            "status": rcm, "time_s": round(tm, 4), "iterations": stm.iterations,
+            "fp32_iterations": stm.fp32_iterations,
+            "speedup_vs_fp64": round(times[1] / tm, 3),
+            "max_eig_error_over_normH": float(np.max(np.abs(ritzv[:nev2] - lam2[:nev2])) / normH),
+            "max_resid_over_normH": float(np.max(resid[:nev2]) / normH)}
+        log(f"bench: mixed solve n={n2} {tm:.3f} s, {stm.iterations} iterations")
+        del dV0
+        h32 = torch.empty((n2, n2), dtype=torch.complex64, device="cuda")
+        ctx.chase_convert_c128_to_c64(dH2, n2, h32, n2, n2, n2)
+        cfg32 = capi.config_fp32(n2, c2["nev"], c2["nex"], optim=1, seed=2600)
+        dV0 = capi.to_device(V2).to(torch.complex64)
+        ritzv, resid = np.zeros(nb2), np.zeros(nb2)
         torch.cuda.synchronize()
-        msr = ev0.elapsed_time(ev1) / reps
-        tfr = flr / (msr * 1e-3) / 1e12
-        out["filter_real_n20000"] = {
-            "value": round(tfr, 3), "unit": "TFLOP/s", "peak": FP64_PEAK_TF,
-            "frac": round(tfr / FP64_PEAK_TF, 4), "ms_per_step": round(msr, 3), "steps": reps,
-            "workload": "chebyshev filter, real symmetric float64 H (structured reflector Q), "
-                        "n=20000, 1200 columns, degrees 2..36; 2 n^2 flops per column product"}
-        log(f"bench: real fp64 filter at n=20000: {tfr:.2f} TFLOP/s")
-        del dH2, dV2, dW2
+        t1 = time.perf_counter()
+        rc32, st32 = ctx.chase_solve(cfg32, h32, n2, dV0, n2, ritzv, resid)
+        t32 = time.perf_counter() - t1
+        out["solve_n10000_fp32"] = {
+            "status": rc32, "time_s": round(t32, 4), "tol": cfg32.tol,
+            "iterations": st32.iterations, "qr_fallbacks": st32.qr_fallbacks,
+            "max_eig_error_over_normH": float(np.max(np.abs(ritzv[:nev2] - lam2[:nev2])) / normH),
+            "max_resid_over_normH": float(np.max(resid[:nev2]) / normH),
+            "workload": "the same problem in complex64 with Table 1's single-precision defaults"}
+        log(f"bench: fp32 solve n={n2} {t32:.3f} s, {st32.iterations} iterations")
+        del dV0, h32, dH2, dV2
         torch.cuda.empty_cache()
+        section("n10000", t0)
 
     if not args.no_cpu_baseline:
-        log("bench: cpu baseline (oracle on a column sample)")
-        H_host = capi.from_device(dH)
-        out["cpu_baseline"] = cpu_baseline(np.asfortranarray(H_host), V, deg, b_sup, mu_1, mu_b)
-    print(json.dumps(out), flush=True)
+        t0 = time.perf_counter()
+        out["cpu_baseline"]["solve"] = oracle_solve_baseline(ctx)
+        log(f"bench: oracle solve baseline {out['cpu_baseline']['solve']}")
+        section("oracle_solve", t0)
     ctx.close()
+
+    if not args.no_sequence:
+        t0 = time.perf_counter()
+        seq = run_sequence("n20000", verbose=False)
+        out["sequence_n20000"] = seq
+        log(f"bench: sequence totals {seq['total_s']}, speed-up {seq.get('speedup_vs_fp64')}")
+        section("sequence", t0)
+
+    if not args.no_serving:
+        t0 = time.perf_counter()
+        out["serving"] = run_serving(problems=args.problems or 8, workers=args.serving_workers,
+                                     rates=tuple(args.serving_rates),
+                                     precision_name=args.serving_precision)
+        section("serving", t0)
+
+    sections["total"] = round(time.perf_counter() - t_start, 1)
+    out["section_s"] = sections
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

@@ -14,7 +14,7 @@ measured on (``bench.py`` reports null once the source differs).
 
 Usage (from the repository root):
   python -m paper_1805_10121_amd.pmc_traffic FETCH_DIR WRITE_DIR COPY_FETCH_DIR COPY_WRITE_DIR \\
-      --select Tile3M --out profiles/traffic_hemm_step_fp64_3m_n10000.json
+      --select Tile3M --out profiles/traffic_hemm_step_fp64_3m_n20000.json
 """
 
 import argparse
@@ -28,8 +28,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1805_10121_amd", "csrc", "filter_kernels.hip")
 THIN_TILE = "Tile<double, 128, 16"  # the bench's thin-product dispatches, not filter products
 COPY_BYTES = 1 << 30
-BENCH_RUN = ("--steps 1 --warmup 0 --no-cpu-baseline --no-solve --no-fp32 --no-n20000 "
-             "--h-gen structured")
+BENCH_RUN = "--headline-only --steps 1 --warmup 0"
 COMMANDS = [
     "cd /tmp && rocprofv3 --pmc FETCH_SIZE --kernel-include-regex hemm -f csv -d "
     "<repo>/gpurun_out/pmc_fetch -o fetch -- python3 <repo>/bench.py " + BENCH_RUN,
@@ -118,8 +117,8 @@ def main(argv=None):
     ap.add_argument("--select", default="", help="keep kernels whose name contains this")
     ap.add_argument("--exclude", default="", help="drop kernels whose name contains this")
     ap.add_argument("--kernel", default="", help="description stored with the record")
-    ap.add_argument("--n", type=int, default=10000)
-    ap.add_argument("--sum-degrees", type=int, default=11388,
+    ap.add_argument("--n", type=int, default=20000)
+    ap.add_argument("--sum-degrees", type=int, default=22788,
                     help="sum of the filter's degrees (active columns summed over its products)")
     ap.add_argument("--products", type=int, default=36, help="products of one filter call")
     ap.add_argument("--command", action="append", default=None,
