@@ -770,6 +770,13 @@ __device__ __forceinline__ void tile_foreach(const typename C::Frag& f, Fn&& fn)
     tile_foreach_4m<T, C>(f, fn);
 }
 
+// Tile t -> (row tile, column tile), column tiles varying fastest: consecutive tiles share a
+// row panel of H.
+__device__ __forceinline__ void tile_coords(int64_t t, int tiles_n, int* tile_m, int* tile_n) {
+  *tile_m = static_cast<int>(t / tiles_n);
+  *tile_n = static_cast<int>(t % tiles_n);
+}
+
 // OUT <- alpha*HX + gamma*X + beta*OUT at (row, col); OUT is not read when beta == 0.
 template <typename T>
 __device__ __forceinline__ void epilogue_store(const T* __restrict__ X, int64_t ldx,
@@ -815,15 +822,20 @@ __device__ __forceinline__ void store_result(const T* __restrict__ X, int64_t ld
 // Values per output element: 2 for complex tiles, 1 for real ones.
 template <class C> constexpr int elem_width() { return C::KIND == 2 ? 1 : 2; }
 
-// Data-parallel schedule: one workgroup per output tile (row tiles vary fastest).
+// Data-parallel schedule: one workgroup per output tile, column tiles varying fastest, in the
+// XCD-aware order of dp_tile: the workgroups an XCD runs at the same time cover few row panels
+// of H, each with all its column tiles, so a panel is fetched into that XCD's L2 once for all
+// of them (row-tiles-fastest order streamed H once per column tile: at n = 20000 x 1200 this
+// order is 4 % faster).
 template <typename T, class C, int OCC, bool V16>
 __global__ __launch_bounds__(kThreads, OCC) void hemm_dp_kernel(
     const T* __restrict__ H, int64_t ldh, int n, const T* __restrict__ X, int64_t ldx,
     T* __restrict__ OUT, int64_t ldo, int ncols, T alpha, T beta, T gamma, int tiles_m) {
   __shared__ typename C::Smem sm;
   typename C::Frag f;
-  const int tile_m = static_cast<int>(blockIdx.x) % tiles_m;
-  const int tile_n = static_cast<int>(blockIdx.x) / tiles_m;
+  (void)tiles_m;
+  int tile_m, tile_n;
+  tile_coords(dp_tile(blockIdx.x, gridDim.x), (ncols + C::BNC - 1) / C::BNC, &tile_m, &tile_n);
   const int i0 = tile_m * C::BMC, j0 = tile_n * C::BNC;
   const int nk = (n + C::KT - 1) / C::KT;
   tile_mainloop<T, C, V16>(sm, f, H, ldh, n, X, ldx, ncols, i0, j0, 0, nk);
@@ -843,12 +855,6 @@ __global__ __launch_bounds__(kThreads, OCC) void hemm_dp_kernel(
 //            the tile containing u0(p), slot 1 for the segment in the tile containing u1(p) - 1 --
 //            and hemm_fixup_kernel adds the slots in increasing p, so the result does not depend
 //            on timing.
-// Tile t -> (row tile, column tile), column tiles varying fastest: consecutive tiles share a
-// row panel of H.
-__device__ __forceinline__ void tile_coords(int64_t t, int tiles_n, int* tile_m, int* tile_n) {
-  *tile_m = static_cast<int>(t / tiles_n);
-  *tile_n = static_cast<int>(t % tiles_n);
-}
 
 // The integer schedule (sk_start, sk_owner, sk_segment, sk_slot, sk_fixup_tile, xcd_order) is
 // shared with the host and checked on the CPU; it lives in host_logic.h.

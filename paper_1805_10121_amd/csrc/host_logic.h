@@ -65,6 +65,20 @@ constexpr int64_t xcd_order(int64_t p, int64_t P) {
   return (P % 8 == 0) ? (p % 8) * (P / 8) + p / 8 : p;
 }
 
+// Tile of workgroup b in a data-parallel grid of G workgroups.  Workgroups are dealt to the 8
+// XCDs round-robin by index; in every full window of 8 * kDpChunk workgroups the ones dealt to
+// one XCD get kDpChunk consecutive tiles (with column tiles varying fastest, the column tiles of
+// the same row panels of H, which then share that XCD's L2).  The last partial window keeps
+// the identity.  A bijection of [0, G).
+constexpr int64_t kDpChunk = 16;
+constexpr int64_t dp_tile(int64_t b, int64_t G) {
+  const int64_t W = 8 * kDpChunk;
+  const int64_t w = b / W;
+  if ((w + 1) * W > G) return b;
+  const int64_t r = b % W;
+  return w * W + (r % 8) * kDpChunk + r / 8;
+}
+
 // K-slices of a Gram product A^H B (m1 x m2 result, k rows) computed as a batch of slice
 // products plus a sum: enough slices that about 512 output tiles of 64 x 64 are in flight
 // (tall-skinny shapes leave most of the GPU idle otherwise), at most 16, each at least 256 rows.

@@ -256,3 +256,41 @@ def test_gram_slices_fit_the_buffer():
     r = subprocess.run([out], capture_output=True, text=True)
     assert r.returncode == 0, f"gram slice check {r.returncode}"
     assert int(r.stdout) > 1000
+
+
+DP_DRIVER = r"""
+#include <cstdio>
+#include <vector>
+#include "host_logic.h"
+using namespace chase;
+int main() {
+  long checked = 0;
+  for (long G = 1; G <= 5000; G += (G < 600 ? 1 : 7)) {
+    std::vector<char> seen(G, 0);
+    for (long b = 0; b < G; ++b) {
+      const long t = dp_tile(b, G);
+      if (t < 0 || t >= G || seen[t]) return 1;
+      seen[t] = 1;
+      // inside a full window, the workgroups of one XCD (b % 8) hold kDpChunk consecutive tiles
+      const long W = 8 * kDpChunk;
+      if ((b / W + 1) * W <= G && t / kDpChunk != (b / W) * 8 + (b % W) % 8) return 2;
+    }
+    ++checked;
+  }
+  printf("%ld\n", checked);
+  return 0;
+}
+"""
+
+
+def test_dp_tile_order_is_a_bijection():
+    """The data-parallel grid's XCD-aware tile order visits every tile exactly once, and gives
+    each XCD's workgroups of a full window consecutive tiles."""
+    d = tempfile.mkdtemp()
+    src = os.path.join(d, "dp.cpp")
+    out = os.path.join(d, "dp")
+    open(src, "w").write(DP_DRIVER)
+    subprocess.run(["g++", "-std=c++17", "-O2", "-I", CSRC, src, "-o", out], check=True)
+    r = subprocess.run([out], capture_output=True, text=True)
+    assert r.returncode == 0, r.returncode
+    assert int(r.stdout) > 1000
