@@ -55,11 +55,16 @@ typedef enum {
   CHASE_REAL_FP64 = 4, /* chase_filter / chase_hemm_step: real symmetric H and real blocks, all
                        float64 (the paper's real "D" instance, Sec. 5.1), FP64 MFMA            */
   CHASE_REAL_FP32 = 5, /* the same with float32 H and blocks, FP32 MFMA with FP32 accumulation */
-  CHASE_FP64_3M = 6  /* chase_filter / chase_hemm_step: H is "planar complex128" -- two real
+  CHASE_FP64_3M = 6, /* chase_filter / chase_hemm_step: H is "planar complex128" -- two real
                        n x n float64 planes, Re H then Im H at an offset of ldh * n doubles --
                        and the products use three real FP64 MFMA products per complex product
                        (3M, 6 instead of 8 real flops per complex multiply-add) with FP64
                        accumulation; the blocks are complex128 as for CHASE_FP64 */
+  CHASE_FP64_LOWER = 7 /* chase_hemm_step only, at most 8 columns: complex128 H of which only
+                       the lower triangle and the diagonal are read (the Hermitian product of
+                       Sec. 5.1.1 that uses one triangle; the upper triangle may hold anything),
+                       FP64 arithmetic on the vector units; half the HBM bytes of a full read
+                       for the thin blocks where the product is bound by reading H */
 } chase_precision;
 
 /*
@@ -208,7 +213,10 @@ int chase_filter_noalloc(int device, void* hip_stream, int precision, const void
  * With beta == 0 the old OUT is not read (it may hold NaN).  Also serves the other products of
  * the outer loop: H Q for Rayleigh-Ritz (Alg. 2) and the Lanczos block (Alg. 6).
  * X and OUT: device, n x ncols, leading dimensions ldx, ldo >= n; must not overlap each other
- * or H.  Types as in chase_filter.  Enqueues only.
+ * or H.  Types as in chase_filter; CHASE_FP64_LOWER as CHASE_FP64 but reading only the lower
+ * triangle of H, for ncols <= 8 (CHASE_EINVAL above that, or when its partial sums, about
+ * n^2 ncols / 16 to n^2 ncols / 4 bytes, exceed the context's product scratch: orders above
+ * about 28000 at 5 columns, 60000 at 1).  Results are bitwise reproducible.  Enqueues only.
  */
 int chase_hemm_step(chase_ctx* ctx, int precision, const void* H, int64_t ldh, int64_t n,
                     const void* X, int64_t ldx, void* OUT, int64_t ldo, int64_t ncols,

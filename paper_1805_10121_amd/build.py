@@ -16,7 +16,7 @@ CSRC = os.path.join(PKG, "csrc")
 OBJ = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libchase.so")
 SOURCES = ["capi.hip", "filter.hip", "filter_kernels.hip", "loop_kernels.hip", "solver.hip", "serving.hip",
-           "noalloc.hip"]
+           "noalloc.hip", "thin_tri.hip", "chol.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

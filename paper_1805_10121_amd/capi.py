@@ -29,6 +29,7 @@ CHASE_FP32_3M = 3
 CHASE_REAL_FP64 = 4
 CHASE_REAL_FP32 = 5
 CHASE_FP64_3M = 6
+CHASE_FP64_LOWER = 7
 
 _i64, _i32, _f64, _u64, _vp = ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_uint64, ctypes.c_void_p
 

@@ -66,10 +66,10 @@ int check_bounds(chase_ctx* ctx, double b_sup, double mu_1, double mu_nevnex) {
 
 int check_product_args(chase_ctx* ctx, int precision, const void* H, int64_t ldh, int64_t n,
                        const void* X, int64_t ldx, const void* OUT, int64_t ldo, int64_t ncols) {
-  if (precision < CHASE_FP64 || precision > CHASE_FP64_3M || precision == CHASE_MIXED)
+  if (precision < CHASE_FP64 || precision > CHASE_FP64_LOWER || precision == CHASE_MIXED)
     return set_error(ctx, CHASE_EINVAL,
                      "precision must be CHASE_FP64, CHASE_FP32, CHASE_FP32_3M, CHASE_REAL_FP64, "
-                     "CHASE_REAL_FP32 or CHASE_FP64_3M");
+                     "CHASE_REAL_FP32, CHASE_FP64_3M or (products only) CHASE_FP64_LOWER");
   if (n < 0 || ncols < 0) return set_error(ctx, CHASE_EINVAL, "negative size");
   if (n > 0x7fffffffLL || ncols > 0x7fffffffLL)
     return set_error(ctx, CHASE_EINVAL, "n and ncols must fit in int32");
@@ -77,9 +77,10 @@ int check_product_args(chase_ctx* ctx, int precision, const void* H, int64_t ldh
   if (!H || !X || !OUT) return set_error(ctx, CHASE_EINVAL, "NULL buffer");
   if (ldh < n || ldx < n || ldo < n)
     return set_error(ctx, CHASE_EINVAL, "leading dimension smaller than n");
-  const size_t elem = (precision == CHASE_FP64 || precision == CHASE_FP64_3M) ? 16
-                      : precision == CHASE_REAL_FP32                        ? 4
-                                                                            : 8;
+  const size_t elem =
+      (precision == CHASE_FP64 || precision == CHASE_FP64_3M || precision == CHASE_FP64_LOWER) ? 16
+      : precision == CHASE_REAL_FP32 ? 4
+                                       : 8;
   // planar H: two ldh x n planes of floats (FP32_3M) or doubles (FP64_3M)
   const size_t hb = precision == CHASE_FP32_3M   ? static_cast<size_t>(ldh) * n * 8
                     : precision == CHASE_FP64_3M ? static_cast<size_t>(ldh) * n * 16
@@ -198,8 +199,12 @@ int chase_create(chase_ctx** out, int device, void* hip_stream) {
     delete ctx;
     return CHASE_ENOMEM;
   }
+  // rocBLAS may pick kernels that add partial results with atomics (summation order then
+  // depends on timing); they are refused so that results are bitwise reproducible, also when
+  // other work shares the device.
   if (rocblas_create_handle(&ctx->blas) != rocblas_status_success ||
-      rocblas_set_stream(ctx->blas, ctx->stream) != rocblas_status_success) {
+      rocblas_set_stream(ctx->blas, ctx->stream) != rocblas_status_success ||
+      rocblas_set_atomics_mode(ctx->blas, rocblas_atomics_not_allowed) != rocblas_status_success) {
     if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
     (void)hipFree(ctx->prod.ptr);
     delete ctx;
@@ -229,6 +234,8 @@ int chase_filter(chase_ctx* ctx, int precision, const void* H, int64_t ldh, int6
                  double mu_1, double mu_nevnex) {
   if (!ctx) return CHASE_EINVAL;
   ctx->last_error.clear();
+  if (precision == CHASE_FP64_LOWER)
+    return set_error(ctx, CHASE_EINVAL, "CHASE_FP64_LOWER applies to chase_hemm_step only");
   int rc = check_product_args(ctx, precision, H, ldh, n, V, ld, W, ld, ncols);
   if (rc) return rc;
   if (n == 0 || ncols == 0) return CHASE_OK;
@@ -254,7 +261,21 @@ int chase_hemm_step(chase_ctx* ctx, int precision, const void* H, int64_t ldh, i
   if (n == 0 || ncols == 0) return CHASE_OK;
   CHASE_HIP_TRY(ctx, hipSetDevice(ctx->device));
   hipError_t e;
-  if (precision == CHASE_FP64)
+  if (precision == CHASE_FP64_LOWER) {
+    if (ncols > kTriMaxCols)
+      return set_error(ctx, CHASE_EINVAL, "CHASE_FP64_LOWER takes at most 8 columns");
+    if (tri_scratch_bytes(n, ncols) > ctx->prod.bytes)
+      return set_error(ctx, CHASE_EINVAL,
+                       "CHASE_FP64_LOWER at this order and width needs " +
+                           std::to_string(tri_scratch_bytes(n, ncols)) +
+                           " bytes of partial sums; the context's scratch holds " +
+                           std::to_string(ctx->prod.bytes));
+  }
+  if (precision == CHASE_FP64_LOWER)
+    e = launch_hemm_tri(static_cast<const double*>(H), ldh, n, static_cast<const double*>(X), ldx,
+                        static_cast<double*>(OUT), ldo, ncols, alpha, beta, gamma, ctx->prod,
+                        ctx->stream);
+  else if (precision == CHASE_FP64)
     e = launch_hemm_step<double>(static_cast<const double*>(H), ldh, n,
                                  static_cast<const double*>(X), ldx, static_cast<double*>(OUT),
                                  ldo, ncols, alpha, beta, gamma, ctx->prod, ctx->stream);

@@ -34,6 +34,18 @@ hipError_t launch_hemm_step(const T* H, int64_t ldh, int64_t n, const T* X, int6
                             int64_t ldo, int64_t ncols, T alpha, T beta, T gamma,
                             const ProductScratch& ps, hipStream_t stream);
 
+// One-triangle product for thin blocks (complex128, at most kTriMaxCols columns): the same
+// product reading only the lower triangle of H, with partial sums in ps (tri_scratch_bytes).
+// Returns hipErrorInvalidValue without launching when ps is too small; with ps.sk_need set it
+// only raises *ps.sk_need to the bytes it needs.
+constexpr int kTriMaxCols = 8;
+// Order from which the solver's thin products (the Lanczos block) read one triangle: below it
+// the two launches cost more than the halved read saves.
+constexpr int64_t kTriMinOrder = 4096;
+size_t tri_scratch_bytes(int64_t n, int64_t ncols);
+hipError_t launch_hemm_tri(const double* H, int64_t ldh, int64_t n, const double* X, int64_t ldx,
+                           double* OUT, int64_t ldo, int64_t ncols, double alpha, double beta,
+                           double gamma, const ProductScratch& ps, hipStream_t stream);
 // The same product for real symmetric H and real X, OUT (T = double or float); leading
 // dimensions count real elements.
 template <typename T>
@@ -109,7 +121,7 @@ hipError_t launch_convert_f64_to_f32(const double* src, int64_t lds, float* dst,
 hipError_t launch_convert_f32_to_f64(const float* src, int64_t lds, double* dst, int64_t ldd,
                                      int64_t rows, int64_t cols, hipStream_t stream);
 
-// Outer-loop helpers (loop_kernels.hip), for double (complex128 / float64) and float (complex64
+// Outer-loop helpers (loop_kernels.hip; the Cholesky factorisation in chol.hip), for double (complex128 / float64) and float (complex64
 // / float32) vectors.  w = values per element: 2 for interleaved complex data, 1 for real data;
 // leading dimensions count elements.  Scalars (Lanczos coefficients, residual norms) are double.
 #define CHASE_LOOP_DECL(R)                                                                      \
@@ -127,7 +139,9 @@ hipError_t launch_convert_f32_to_f64(const float* src, int64_t lds, double* dst,
   hipError_t launch_sum_slices(const R* P, int64_t m1, int64_t m2, int64_t stride, int p, R* G,  \
                               int64_t ldg, hipStream_t s, int w = 2);                           \
   hipError_t launch_gaussian(R* X, int64_t n, int64_t ld, int64_t cols, uint64_t seed,          \
-                             hipStream_t s, int w = 2);
+                             hipStream_t s, int w = 2);                                         \
+  hipError_t launch_potrf_upper(R* G, int64_t ld, int64_t m, int* info, hipStream_t s,          \
+                                int w = 2);
 CHASE_LOOP_DECL(double)
 CHASE_LOOP_DECL(float)
 // Interleaved complex64 H (ld lds) -> planar complex64 (Re plane, Im plane at dst + ldd * n).

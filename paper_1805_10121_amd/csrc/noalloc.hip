@@ -73,6 +73,8 @@ int filter_noalloc(chase_ctx* ctx, int device, hipStream_t stream, int precision
   }
   if (device < 0 || device >= count || device >= kMaxDevices)
     return set_error(ctx, CHASE_EINVAL, "device index out of range");
+  if (precision == CHASE_FP64_LOWER)
+    return set_error(ctx, CHASE_EINVAL, "CHASE_FP64_LOWER applies to chase_hemm_step only");
   int rc = check_product_args(ctx, precision, H, ldh, n, V, ld, W, ld, ncols);
   if (rc) return rc;
   CHASE_HIP_TRY(ctx, hipSetDevice(device));

@@ -237,10 +237,15 @@ class Solver {
     if (real_)
       return launch_hemm_step_real<R>(H, ldh, n_, X, ldx, OUT, ldo, ncols, a, b, g, ctx_->prod, s_);
     if constexpr (kF64) {
-      // 3M on the planar copy for wide blocks (Rayleigh-Ritz); thin Lanczos blocks stay 4M
+      // 3M on the planar copy for wide blocks (Rayleigh-Ritz); thin Lanczos blocks read one
+      // triangle of H where that pays and its partial sums fit the product scratch, else 4M
       if (planar64_ && ncols > 16)
         return launch_hemm_step_3m_f64(at<double>(L_.H64), n_, n_, X, ldx, OUT, ldo, ncols, alpha,
                                        beta, gamma, ctx_->prod, s_);
+      if (ncols <= kTriMaxCols && n_ >= kTriMinOrder &&
+          tri_scratch_bytes(n_, ncols) <= ctx_->prod.bytes)
+        return launch_hemm_tri(H, ldh, n_, X, ldx, OUT, ldo, ncols, alpha, beta, gamma, ctx_->prod,
+                               s_);
     }
     return launch_hemm_step<R>(H, ldh, n_, X, ldx, OUT, ldo, ncols, a, b, g, ctx_->prod, s_);
   }
@@ -352,8 +357,12 @@ int Solver<R>::cgs(int64_t nlock, int64_t nact) {
 }
 
 // One (optionally shifted) Cholesky QR pass on the active block: G = A^H A (+ s I) = R^H R,
-// A <- A R^-1.  Shift as in shifted CholeskyQR3 (Fukaya et al.) with ||A||_2^2 <= nact for
-// unit columns.
+// A <- A R^-1.  Shift as in shifted CholeskyQR3 (Fukaya et al.), 11 (n m + m (m + 1)) u ||A||^2
+// with ||A||_2^2 <= m = nact for unit columns, capped at 1e-2 m.  The cap only acts in single
+// precision at large n (at n = 1e4, m = 600 the FP32 bound is about 4 m): a shift above
+// ||A||_2^2 would make the pass a mere rescaling of the block, while 1e-2 m still exceeds the
+// Gram matrix's rounding error (about sqrt(n) u m) and bounds the pass's output condition
+// number by about sqrt(1e-2 m) / sigma_min(A).
 template <typename R>
 int Solver<R>::cholqr(int64_t nact, bool shift, int slot) {
   R* A = col(L_.V, n_ == 0 ? 0 : (nb_ - nact));
@@ -362,23 +371,17 @@ int Solver<R>::cholqr(int64_t nact, bool shift, int slot) {
   int rc = gram(nact, nact, A, A, G, nb_);
   if (rc) return rc;
   if (shift) {
-    const double s = 11.0 * (static_cast<double>(n_) * nact + static_cast<double>(nact) * (nact + 1)) *
-                     kU * static_cast<double>(nact);
+    const double m = static_cast<double>(nact);
+    const double s =
+        std::min(11.0 * (static_cast<double>(n_) * m + m * (m + 1.0)) * kU * m, 1e-2 * m);
     if ((rc = hip(launch_add_diag(G, nb_, nact, s, s_, w_), "add_diag"))) return rc;
   }
   rocblas_int* info = at<rocblas_int>(L_.info) + slot;
   const rocblas_int ia = static_cast<rocblas_int>(nact), ig = static_cast<rocblas_int>(nb_),
                     in = static_cast<rocblas_int>(n_);
-  if constexpr (kF64)
-    rc = real_ ? blas(rocsolver_dpotrf(ctx_->blas, rocblas_fill_upper, ia, G, ig, info), "dpotrf")
-               : blas(rocsolver_zpotrf(ctx_->blas, rocblas_fill_upper, ia,
-                                       reinterpret_cast<rocblas_double_complex*>(G), ig, info),
-                      "zpotrf");
-  else
-    rc = real_ ? blas(rocsolver_spotrf(ctx_->blas, rocblas_fill_upper, ia, G, ig, info), "spotrf")
-               : blas(rocsolver_cpotrf(ctx_->blas, rocblas_fill_upper, ia,
-                                       reinterpret_cast<rocblas_float_complex*>(G), ig, info),
-                      "cpotrf");
+  // own factorisation: its summation order is fixed, so the factor does not depend on what
+  // else runs on the device
+  rc = hip(launch_potrf_upper(G, nb_, nact, info, s_, w_), "potrf");
   if (rc) return rc;
   // The factorisation status is read once per orthonormalisation (see orthogonalize); a failed
   // factorisation makes this solve produce garbage that is then discarded.

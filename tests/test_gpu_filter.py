@@ -527,3 +527,85 @@ def test_filter_fp64_3m_parity(ctx, n, ld):
     err = _relerr(capi.from_device(dV), ref)
     print(f"fp64 3M n={n} ld={ld} block-relative error {err:.3e}")
     assert err <= 1e-12
+
+
+@pytest.mark.parametrize("n,nb,pad", [(1, 1, 0), (63, 3, 1), (64, 8, 0), (65, 5, 2), (200, 5, 0),
+                                      (777, 1, 3), (1000, 8, 1), (3000, 5, 0), (4500, 2, 1)])
+def test_hemm_step_lower_triangle(ctx, n, nb, pad):
+    """CHASE_FP64_LOWER (one-triangle product for thin blocks) against the oracle's product: the
+    upper triangle of H and the padding rows are NaN, so any read of them would show; ragged
+    orders cover partial tiles, orders up to 4500 every super-tile edge the launcher picks
+    (1 and 2 here, 4 and 8 in the order-10000/20000 test); beta = 0 with a NaN-filled OUT that
+    must not be read; a repeat is bitwise equal."""
+    import torch
+    from paper_1805_10121_amd import capi
+
+    print(f"lower-triangle product n={n} ncols={nb}", flush=True)
+    g = wl.rng(9000 + n)
+    A = wl.complex_gaussian(g, n, n)
+    H = 0.5 * (A + A.conj().T)
+    X, Y = wl.complex_gaussian(g, n, nb), wl.complex_gaussian(g, n, nb)
+    Hp = np.full((n + pad, n), np.nan + 1j * np.nan, dtype=np.complex128)
+    Hp[:n] = np.tril(H)
+    Hp[:n][np.triu_indices(n, 1)] = np.nan
+    dH = capi.to_device(Hp)
+    Xp = np.full((n + pad, nb), np.nan, dtype=np.complex128)
+    Xp[:n] = X
+    dX = capi.to_device(Xp)
+    for alpha, beta, gamma in ((1.0, 0.0, 0.0), (0.7, -0.4, 0.3)):
+        ref = ch.product(H, X, Y, alpha, beta, gamma)
+        Op = np.full((n + pad, nb), 7.0, dtype=np.complex128)
+        Op[:n] = Y if beta != 0.0 else np.nan
+        outs = []
+        for _ in range(2):
+            dO = capi.to_device(Op)
+            ctx.chase_hemm_step(capi.CHASE_FP64_LOWER, dH, n + pad, n, dX, n + pad, dO, n + pad, nb,
+                                alpha, beta, gamma)
+            torch.cuda.synchronize()
+            outs.append(capi.from_device(dO))
+        got = outs[0]
+        assert np.array_equal(outs[0], outs[1])
+        assert np.all(got[n:] == 7.0)
+        err = np.max(np.abs(got[:n] - ref)) / np.max(np.abs(ref))
+        assert err <= 1e-13, (n, nb, alpha, beta, err)
+
+
+def test_hemm_step_lower_triangle_large_orders(ctx):
+    """CHASE_FP64_LOWER at orders 10000 and 20000 (super-tiles of 4 x 4 and 8 x 8 tiles), 5 and
+    1 columns, against the oracle's product on a host copy of H."""
+    import torch
+    from paper_1805_10121_amd import capi
+
+    for n, seed in ((10000, 41), (20000, 42)):
+        lam = wl.spectrum_for("sequence_n20000", n=n)
+        dH = wl.hermitian_torch_fast(n, lam, seed=seed)
+        H = capi.from_device(dH)
+        for nb in (5, 1):
+            print(f"lower-triangle product n={n} ncols={nb}", flush=True)
+            X = wl.start_block(n, nb, seed + nb)
+            dX = capi.to_device(X)
+            dO = torch.full((nb, n), float("nan"), dtype=torch.complex128, device="cuda")
+            ctx.chase_hemm_step(capi.CHASE_FP64_LOWER, dH, n, n, dX, n, dO, n, nb, 1.0, 0.0, 0.0)
+            torch.cuda.synchronize()
+            ref = ch.product(H, X, None, 1.0, 0.0, 0.0)
+            err = np.max(np.abs(capi.from_device(dO) - ref)) / np.max(np.abs(ref))
+            print(f"  max error {err:.2e} of max |OUT|")
+            assert err <= 1e-13
+        del dH, H
+        torch.cuda.empty_cache()
+
+
+def test_lower_triangle_argument_errors(ctx):
+    import torch
+    from paper_1805_10121_amd import capi
+
+    n = 64
+    dH = torch.zeros((n, n), dtype=torch.complex128, device="cuda")
+    dX = torch.zeros((9, n), dtype=torch.complex128, device="cuda")
+    dO = torch.zeros((9, n), dtype=torch.complex128, device="cuda")
+    with pytest.raises(capi.ChaseError) as ei:           # more than 8 columns
+        ctx.chase_hemm_step(capi.CHASE_FP64_LOWER, dH, n, n, dX, n, dO, n, 9, 1.0, 0.0, 0.0)
+    assert ei.value.code == capi.CHASE_EINVAL
+    with pytest.raises(capi.ChaseError) as ei:           # products only, not the filter
+        ctx.chase_filter(capi.CHASE_FP64_LOWER, dH, n, n, dX, dO, n, 2, [2, 2], 2.0, -1.0, 0.0)
+    assert ei.value.code == capi.CHASE_EINVAL
