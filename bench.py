@@ -461,6 +461,58 @@ def run_ablation(name="uniform_n1000", degrees=(8, 12, 16, 20, 24, 28, 32, 36)):
             "rows": rows}
 
 
+def thin_products(ctx, dH, n, dX, dO, widths, reps=20):
+    """Thin products OUT = H X (complex128) with the full read of H and, up to 8 columns, with
+    the one-triangle read (CHASE_FP64_LOWER); ms per product by HIP events, and the HBM rate of
+    the algorithmic bytes (H or its lower triangle once, X read, OUT written)."""
+    from paper_1805_10121_amd import capi
+    rows = []
+    for nc in widths:
+        X, O = dX[:nc], dO[:nc]
+        row = {"ncols": nc}
+        for key, prec, hb in (("full", capi.CHASE_FP64, 16.0 * n * n),
+                              ("one_triangle", capi.CHASE_FP64_LOWER, 8.0 * n * n + 8.0 * 64 * n)):
+            if prec == capi.CHASE_FP64_LOWER and nc > 8:
+                continue
+
+            def step():
+                ctx.chase_hemm_step(prec, dH, n, n, X, n, O, n, nc, 1.0, 0.0, 0.0)
+
+            try:
+                step()
+            except capi.ChaseError as e:   # partial sums beyond the product scratch
+                row[key] = {"error": str(e)[:120]}
+                continue
+            _, ms = _timed(ctx.stream, reps, step)
+            ms /= reps
+            b = hb + 32.0 * n * nc
+            row[key] = {"ms_per_product": round(ms, 4),
+                        "algorithmic_GBps": round(b / (ms * 1e-3) / 1e9, 1),
+                        "frac_of_hbm_peak": round(b / (ms * 1e-3) / 8e12, 4)}
+        if "ms_per_product" in row.get("one_triangle", {}):
+            row["one_triangle_speedup"] = round(row["full"]["ms_per_product"] /
+                                                row["one_triangle"]["ms_per_product"], 3)
+        rows.append(row)
+    return rows
+
+
+def run_thin(order=None):
+    """Thin products at one order: full read against one-triangle read, 1 to 16 columns."""
+    import torch
+    from paper_1805_10121_amd import capi
+    from paper_1805_10121_amd import workloads as wl
+    n = order or 10000
+    lam = wl.spectrum_for("clustered_n10000", n=n)
+    dH = wl.hermitian_torch_fast(n, lam, seed=2001)
+    dX = capi.to_device(wl.start_block(n, 16, 2500))
+    dO = torch.empty_like(dX)
+    ctx = capi.Context(0)
+    rows = thin_products(ctx, dH, n, dX, dO, (1, 2, 3, 4, 5, 6, 8, 16))
+    ctx.close()
+    return {"workload": f"thin products H X, complex128 H of order {n} (clustered spectrum, "
+                        "structured unitary Q)", "n": n, "products": rows}
+
+
 def _timed(stream, reps, fn):
     """Run fn reps times between two HIP events on ``stream`` (the library's stream); returns
     (wall seconds, event milliseconds)."""
@@ -491,10 +543,11 @@ def main():
     ap.add_argument("--no-sequence", action="store_true",
                     help="skip the order-20000 sequence leg (FP64 against mixed time-to-solution)")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
-    ap.add_argument("--workload", choices=["filter", "sequence", "serving", "ablation"],
+    ap.add_argument("--workload", choices=["filter", "sequence", "serving", "ablation", "thin"],
                     default="filter",
                     help="filter: the hot-path benchmark with its sequence and serving legs "
-                         "(default); sequence, serving, ablation: one of the other workloads alone")
+                         "(default); sequence, serving, ablation, thin: one of the other "
+                         "workloads alone")
     ap.add_argument("--problems", type=int, default=None,
                     help="sequence: problems (default: the config's); serving: per sequence (8)")
     ap.add_argument("--sequence", choices=sorted(SEQUENCES), default="n20000",
@@ -518,7 +571,8 @@ def main():
     ap.add_argument("--serving-precision", choices=["mixed", "fp64"], default="mixed",
                     help="serving: filter precision of the served solves")
     ap.add_argument("--order", type=int, default=None,
-                    help="sequence workload: order (default: the config's)")
+                    help="sequence workload: order (default: the config's); thin: order "
+                         "(default 10000)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy three times (counter calibration)")
     args = ap.parse_args()
@@ -546,6 +600,9 @@ def main():
         print(json.dumps(run_sequence(args.sequence, args.order, args.problems, tuple(args.modes),
                                       tuple(args.switch_resid), tuple(args.deg_max_fp32))),
               flush=True)
+        return
+    if args.workload == "thin":
+        print(json.dumps(run_thin(args.order)), flush=True)
         return
     if args.workload == "ablation":
         out = {w: run_ablation(w) for w in args.ablation_workloads}
@@ -662,22 +719,8 @@ def main():
     log(f"bench: fp64 filter with 4M products: {tf4:.2f} TFLOP/s")
 
     # thin blocks (the Lanczos block, a filter's last columns) are HBM-bound: H read per product
-    thin = []
-    for nc in (5, 16):
-        dX, dO = dV[:nc], dW[:nc]
-
-        def thin_step():
-            ctx.chase_hemm_step(capi.CHASE_FP64, dH, n, n, dX, n, dO, n, nc, 1.0, 0.0, 0.0)
-
-        thin_step()
-        _, ms = _timed(stream, 20, thin_step)
-        ms /= 20
-        hbytes = 16.0 * n * n + 32.0 * n * nc   # H once, X read, OUT written
-        thin.append({"ncols": nc, "ms_per_product": round(ms, 4),
-                     "algorithmic_GBps": round(hbytes / (ms * 1e-3) / 1e9, 1),
-                     "frac_of_hbm_peak": round(hbytes / (ms * 1e-3) / 8e12, 4)})
-    out["thin_products"] = thin
-    log(f"bench: thin products {thin}")
+    out["thin_products"] = thin_products(ctx, dH, n, dV, dW, (1, 5, 16))
+    log(f"bench: thin products {out['thin_products']}")
 
     if not args.no_fp32:
         # the mixed solver's FP32 stage (3M on planar complex64 H) and the 4M FP32 filter

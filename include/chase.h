@@ -215,8 +215,9 @@ int chase_filter_noalloc(int device, void* hip_stream, int precision, const void
  * X and OUT: device, n x ncols, leading dimensions ldx, ldo >= n; must not overlap each other
  * or H.  Types as in chase_filter; CHASE_FP64_LOWER as CHASE_FP64 but reading only the lower
  * triangle of H, for ncols <= 8 (CHASE_EINVAL above that, or when its partial sums, about
- * n^2 ncols / 16 to n^2 ncols / 4 bytes, exceed the context's product scratch: orders above
- * about 28000 at 5 columns, 60000 at 1).  Results are bitwise reproducible.  Enqueues only.
+ * n^2 ncols / (4 S) bytes with S = 8, 4, 2 for 1-2, 3-5, 6-8 columns at large n, exceed the
+ * context's product scratch of 128 MiB: orders above about 11500 at 8 columns, 20700 at 5,
+ * 46000 at 2, 65000 at 1).  Results are bitwise reproducible.  Enqueues only.
  */
 int chase_hemm_step(chase_ctx* ctx, int precision, const void* H, int64_t ldh, int64_t n,
                     const void* X, int64_t ldx, void* OUT, int64_t ldo, int64_t ncols,

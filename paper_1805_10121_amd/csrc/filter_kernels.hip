@@ -770,11 +770,13 @@ __device__ __forceinline__ void tile_foreach(const typename C::Frag& f, Fn&& fn)
     tile_foreach_4m<T, C>(f, fn);
 }
 
-// Tile t -> (row tile, column tile), column tiles varying fastest: consecutive tiles share a
-// row panel of H.
-__device__ __forceinline__ void tile_coords(int64_t t, int tiles_n, int* tile_m, int* tile_n) {
-  *tile_m = static_cast<int>(t / tiles_n);
-  *tile_n = static_cast<int>(t % tiles_n);
+// Tile t -> (row tile, column tile) in the grouped order of grouped_tile (blocks of 8 row tiles,
+// walked column tile by column tile).
+__device__ __forceinline__ void tile_coords(int64_t t, int tiles_m, int tiles_n, int* tile_m,
+                                            int* tile_n) {
+  const TileMN c = grouped_tile(t, tiles_m, tiles_n);
+  *tile_m = static_cast<int>(c.m);
+  *tile_n = static_cast<int>(c.n);
 }
 
 // OUT <- alpha*HX + gamma*X + beta*OUT at (row, col); OUT is not read when beta == 0.
@@ -822,20 +824,18 @@ __device__ __forceinline__ void store_result(const T* __restrict__ X, int64_t ld
 // Values per output element: 2 for complex tiles, 1 for real ones.
 template <class C> constexpr int elem_width() { return C::KIND == 2 ? 1 : 2; }
 
-// Data-parallel schedule: one workgroup per output tile, column tiles varying fastest, in the
-// XCD-aware order of dp_tile: the workgroups an XCD runs at the same time cover few row panels
-// of H, each with all its column tiles, so a panel is fetched into that XCD's L2 once for all
-// of them (row-tiles-fastest order streamed H once per column tile: at n = 20000 x 1200 this
-// order is 4 % faster).
+// Data-parallel schedule: one workgroup per output tile, in the XCD-aware order of dp_tile over
+// the grouped tile order: the 16 workgroups an XCD starts together cover 8 row panels of H and
+// 2 column panels of X, which they stream through that XCD's L2 at about the same time.
 template <typename T, class C, int OCC, bool V16>
 __global__ __launch_bounds__(kThreads, OCC) void hemm_dp_kernel(
     const T* __restrict__ H, int64_t ldh, int n, const T* __restrict__ X, int64_t ldx,
     T* __restrict__ OUT, int64_t ldo, int ncols, T alpha, T beta, T gamma, int tiles_m) {
   __shared__ typename C::Smem sm;
   typename C::Frag f;
-  (void)tiles_m;
   int tile_m, tile_n;
-  tile_coords(dp_tile(blockIdx.x, gridDim.x), (ncols + C::BNC - 1) / C::BNC, &tile_m, &tile_n);
+  tile_coords(dp_tile(blockIdx.x, gridDim.x), tiles_m, (ncols + C::BNC - 1) / C::BNC, &tile_m,
+              &tile_n);
   const int i0 = tile_m * C::BMC, j0 = tile_n * C::BNC;
   const int nk = (n + C::KT - 1) / C::KT;
   tile_mainloop<T, C, V16>(sm, f, H, ldh, n, X, ldx, ncols, i0, j0, 0, nk);
@@ -869,12 +869,13 @@ __global__ __launch_bounds__(kThreads, OCC) void hemm_sk_kernel(
   const int64_t P = gridDim.x, p = blockIdx.x;
   const int tiles_n = (ncols + C::BNC - 1) / C::BNC;
   // Workgroups are dealt round-robin to the 8 XCDs (each with its own L2); q renumbers them so
-  // that the workgroups of one XCD hold consecutive tiles, i.e. the column tiles of the same
-  // row panels, which then stream the same H stages through that XCD's L2 at the same time.
+  // that the workgroups of one XCD hold consecutive positions of the grouped tile order, i.e. a
+  // block of few row panels of H and column panels of X, which they stream through that XCD's
+  // L2 at the same time.
   const int64_t q = xcd_order(p, P);
   for (int64_t t = q; t < dp_tiles; t += P) {
     int tile_m, tile_n;
-    tile_coords(t, tiles_n, &tile_m, &tile_n);
+    tile_coords(t, tiles_m, tiles_n, &tile_m, &tile_n);
     const int i0 = tile_m * C::BMC, j0 = tile_n * C::BNC;
     tile_mainloop<T, C, V16>(sm, f, H, ldh, n, X, ldx, ncols, i0, j0, 0, nk);
     tile_foreach<T, C>(f, [&](int r, int c, T hre, T him) {
@@ -892,7 +893,7 @@ __global__ __launch_bounds__(kThreads, OCC) void hemm_sk_kernel(
     const int ka = sg.ka, kb = sg.kb;
     const int64_t t = dp_tiles + tr;
     int tile_m, tile_n;
-    tile_coords(t, tiles_n, &tile_m, &tile_n);
+    tile_coords(t, tiles_m, tiles_n, &tile_m, &tile_n);
     const int i0 = tile_m * C::BMC, j0 = tile_n * C::BNC;
     tile_mainloop<T, C, V16>(sm, f, H, ldh, n, X, ldx, ncols, i0, j0, ka, kb);
     if (ka == 0 && kb == nk) {
@@ -931,7 +932,7 @@ __global__ __launch_bounds__(kThreads) void hemm_fixup_kernel(
   const int64_t pf = sk_owner(tr * nk, units, P), pl = sk_owner((tr + 1) * nk - 1, units, P);
   const int64_t t = dp_tiles + tr;
   int tile_m, tile_n;
-  tile_coords(t, (ncols + C::BNC - 1) / C::BNC, &tile_m, &tile_n);
+  tile_coords(t, tiles_m, (ncols + C::BNC - 1) / C::BNC, &tile_m, &tile_n);
   const int i0 = tile_m * C::BMC, j0 = tile_n * C::BNC;
   constexpr int TE = C::BMC * C::BNC;
   constexpr int SL = fixup_slices<C>();

@@ -79,6 +79,25 @@ constexpr int64_t dp_tile(int64_t b, int64_t G) {
   return w * W + (r % 8) * kDpChunk + r / 8;
 }
 
+// Output tile at position t of the product kernels' tile order: groups of kTileGroupRows row
+// tiles (the last group may be shorter), each walked column tile by column tile, row tiles
+// fastest.  The workgroups one XCD runs together take consecutive positions (xcd_order,
+// dp_tile), so they cover a block of few row panels of H and few column panels of X (16
+// positions: 8 x 2 tiles, 96: 8 x 12) instead of all column tiles of one or two row panels,
+// and fetch fewer distinct panels into that XCD's L2.  A bijection of [0, tiles_m tiles_n).
+constexpr int64_t kTileGroupRows = 8;
+struct TileMN {
+  int64_t m, n;
+};
+constexpr TileMN grouped_tile(int64_t t, int64_t tiles_m, int64_t tiles_n) {
+  const int64_t per_group = kTileGroupRows * tiles_n;
+  const int64_t g = t / per_group;
+  const int64_t first = g * kTileGroupRows;
+  const int64_t rows = tiles_m - first < kTileGroupRows ? tiles_m - first : kTileGroupRows;
+  const int64_t r = t - g * per_group;
+  return {first + r % rows, r / rows};
+}
+
 // K-slices of a Gram product A^H B (m1 x m2 result, k rows) computed as a batch of slice
 // products plus a sum: enough slices that about 512 output tiles of 64 x 64 are in flight
 // (tall-skinny shapes leave most of the GPU idle otherwise), at most 16, each at least 256 rows.

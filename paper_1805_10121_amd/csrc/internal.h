@@ -39,9 +39,12 @@ hipError_t launch_hemm_step(const T* H, int64_t ldh, int64_t n, const T* X, int6
 // Returns hipErrorInvalidValue without launching when ps is too small; with ps.sk_need set it
 // only raises *ps.sk_need to the bytes it needs.
 constexpr int kTriMaxCols = 8;
-// Order from which the solver's thin products (the Lanczos block) read one triangle: below it
-// the two launches cost more than the halved read saves.
-constexpr int64_t kTriMinOrder = 4096;
+// The solver's thin products (the Lanczos block) read one triangle from order kTriMinOrder and
+// up to kTriSolverCols columns: measured at orders 2000 to 20000 it takes 0.5 to 0.75 of the
+// full-read thin tile's time up to 3 columns, 0.7 to 0.95 at 4, 0.8 to 1.0 at 5, and longer
+// than the thin tile from 6 columns.
+constexpr int kTriSolverCols = 5;
+constexpr int64_t kTriMinOrder = 2000;
 size_t tri_scratch_bytes(int64_t n, int64_t ncols);
 hipError_t launch_hemm_tri(const double* H, int64_t ldh, int64_t n, const double* X, int64_t ldx,
                            double* OUT, int64_t ldo, int64_t ncols, double alpha, double beta,

@@ -242,7 +242,7 @@ class Solver {
       if (planar64_ && ncols > 16)
         return launch_hemm_step_3m_f64(at<double>(L_.H64), n_, n_, X, ldx, OUT, ldo, ncols, alpha,
                                        beta, gamma, ctx_->prod, s_);
-      if (ncols <= kTriMaxCols && n_ >= kTriMinOrder &&
+      if (ncols <= kTriSolverCols && n_ >= kTriMinOrder &&
           tri_scratch_bytes(n_, ncols) <= ctx_->prod.bytes)
         return launch_hemm_tri(H, ldh, n_, X, ldx, OUT, ldo, ncols, alpha, beta, gamma, ctx_->prod,
                                s_);

@@ -294,3 +294,45 @@ def test_dp_tile_order_is_a_bijection():
     r = subprocess.run([out], capture_output=True, text=True)
     assert r.returncode == 0, r.returncode
     assert int(r.stdout) > 1000
+
+
+GROUP_DRIVER = r"""
+#include <cstdio>
+#include <vector>
+#include "host_logic.h"
+using namespace chase;
+int main() {
+  long checked = 0;
+  for (long tm = 1; tm <= 70; ++tm)
+    for (long tn = 1; tn <= 40; tn += (tn < 20 ? 1 : 3)) {
+      std::vector<char> seen(tm * tn, 0);
+      for (long t = 0; t < tm * tn; ++t) {
+        const TileMN c = grouped_tile(t, tm, tn);
+        if (c.m < 0 || c.m >= tm || c.n < 0 || c.n >= tn || seen[c.m * tn + c.n]) return 1;
+        seen[c.m * tn + c.n] = 1;
+        // inside a full group, kTileGroupRows consecutive positions are one column tile
+        const long g = t / (kTileGroupRows * tn);
+        if ((g + 1) * kTileGroupRows <= tm &&
+            (c.n != (t % (kTileGroupRows * tn)) / kTileGroupRows ||
+             c.m != g * kTileGroupRows + t % kTileGroupRows))
+          return 2;
+      }
+      ++checked;
+    }
+  printf("%ld\n", checked);
+  return 0;
+}
+"""
+
+
+def test_grouped_tile_order_is_a_bijection():
+    """The product kernels' grouped tile order visits every output tile once, ragged last group
+    included, and walks a full group column by column."""
+    d = tempfile.mkdtemp()
+    src = os.path.join(d, "grp.cpp")
+    out = os.path.join(d, "grp")
+    open(src, "w").write(GROUP_DRIVER)
+    subprocess.run(["g++", "-std=c++17", "-O2", "-I", CSRC, src, "-o", out], check=True)
+    r = subprocess.run([out], capture_output=True, text=True)
+    assert r.returncode == 0, r.returncode
+    assert int(r.stdout) > 1000
