@@ -826,7 +826,6 @@ def main():
             "value": round(tf2, 3), "unit": "TFLOP/s", "peak": FP64_PEAK_TF,
             "frac": round(tf2 / FP64_PEAK_TF, 4), "ms_per_step": round(ms / 5, 3), "steps": 5,
             "avg_product_ms": round(ms / 5 / int(deg2.max()), 4),
-            "traffic": load_traffic("traffic_hemm_step_fp64_3m_n10000.json"),
             "workload": f"chebyshev filter, isolated problem n={n2}, nev=500, nex=100, complex128 "
                         "H = Q diag(lam) Q^H (Haar Q, clustered spectrum), degrees 2..36, FP64 3M"}
         log(f"bench: fp64 filter n={n2}: {tf2:.2f} TFLOP/s")
