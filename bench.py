@@ -75,7 +75,7 @@ def host_record():
             "blas_threads": int(b.get("num_threads", 1))}
 
 
-def cpu_baseline(H_host, V_host, deg, b_sup, mu_1, mu_b, budget_s=15.0):
+def cpu_baseline(H_host, V_host, deg, b_sup, mu_1, mu_b, budget_s=10.0):
     """Time the oracle's per-column filter on a bounded sample of columns (stops after the
     column that crosses ``budget_s`` seconds)."""
     import numpy as np
