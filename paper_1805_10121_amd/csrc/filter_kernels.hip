@@ -1166,12 +1166,13 @@ template <typename T> using RealTile = TileR<T, 128, 128, 16, 2, 2, sizeof(T) ==
 template <typename T> using RealThinTile = TileR<T, 256, 16, 16, 4, 1, sizeof(T) == 4 ? 4 : 2>;
 constexpr double kSlimCost = 1.10;
 
-// 3M tile for the planar FP32 products: FP64 promotion every four stages (64 K terms), three
+// 3M tile for the planar FP32 products: FP64 promotion every eight stages (128 K terms), three
 // workgroups per CU (the combined promotion keeps it at 163 VGPRs).  Each promotion waits for
-// the MFMA pipeline to drain, so promoting every 4 stages instead of 2 runs about 9 % faster;
-// the FP32 part of the error grows like sqrt(64) units of FP32 roundoff, well below the 1e-6
-// residual at which the mixed solver leaves FP32.
-using Wide3M = Tile3M<64, 64, 16, 2, 2, 4, 4, float, 3>;
+// the MFMA pipeline to drain: promoting every 4 stages instead of 2 ran about 9 % faster, every
+// 8 instead of 4 another 2-3 % (orders 10000-20000).  The FP32 part of the error grows like
+// sqrt(128) units of FP32 roundoff within a chunk, far below the rounding of the inputs to FP32
+// and the 1e-6 residual at which the mixed solver leaves FP32.
+using Wide3M = Tile3M<64, 64, 16, 2, 2, 4, 8, float, 3>;
 // The same 3M scheme on FP64 MFMA for complex128 data stored as two float64 planes: three
 // real products instead of four per complex product.  No promotion (FP64 accumulators);
 // 8-byte loads (measured faster than 16-byte ones for this tile); K stages of 8 with three

@@ -162,8 +162,12 @@ def test_fp32_config2_full_size(ctx):
     ritzv, resid = np.zeros(nev + nex), np.zeros(nev + nex)
     print("fp32 config2: solving", flush=True)
     rc, st = ctx.chase_solve(cfg, dH, n, dV, n, ritzv, resid)
-    print(f"fp32 config2: rc={rc} it={st.iterations} total_ms={st.total_ms:.1f}", flush=True)
+    print(f"fp32 config2: rc={rc} it={st.iterations} total_ms={st.total_ms:.1f} "
+          f"qr_fallbacks={st.qr_fallbacks}", flush=True)
     assert rc == 0
+    # the shifted CholeskyQR pass (shift capped at 1e-2 m in single precision) keeps the block
+    # orthonormalisable without the Householder fallback
+    assert st.qr_fallbacks == 0
     normH = np.max(np.abs(lam))
     assert np.max(resid[:nev]) <= TOL * st.norm_est * 1.0001
     assert np.max(np.abs(ritzv[:nev] - lam[:nev])) <= 2 * TOL * normH
