@@ -17,8 +17,10 @@ lanczos   : Alg. 6 (k-step Lanczos, upper bound b_sup, DoS estimate of mu_1 and 
 chase     : Alg. 1 driver with Alg. 2 (Rayleigh-Ritz), Alg. 3 (deflation & locking),
             Alg. 5 (degrees), plus the sequence driver (warm start, Sec. 3.3).
 
-Parity status per function is stated in each module header; the only function without a pin
-is the DoS estimate of mu_{nev+nex} (``lanczos.dos_estimates``): "parity unpinned".
+Parity status per function is stated in each module header.  Every function has a pin; for
+the DoS estimate of mu_{nev+nex} (``lanczos.dos_estimates``) the pins are the cases the
+mathematics fixes (Gauss quadrature, the counting function at full length), while how well a
+few short runs estimate a large spectrum remains a heuristic.
 """
 
 from . import chebyshev, lanczos, chase  # noqa: F401

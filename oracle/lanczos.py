@@ -16,8 +16,15 @@ Readings where the paper is silent or garbled:
 
 Pins: ``lanczos_run`` -- the Lanczos relation A U = U T + f e_k^T and U^H U = I at small k,
 exact eigenvalues for k = n on a small diagonal matrix, b_sup >= lambda_max (the invariant the
-algorithm needs).  ``dos_estimates`` -- parity unpinned (a heuristic): only the weights sum to
-one and mu_1 <= every Ritz value are checked.
+algorithm needs).  ``dos_measure`` -- the k-point Gauss quadrature property of Lanczos: its
+weights and Ritz values reproduce the moments v^H A^p v / v^H v for p < 2k, and at k = n they
+are the eigenvalues and the squared spectral components of the start vector.
+``dos_estimates`` -- at k = n with start vectors of equal spectral weights and a narrow
+Gaussian, the smoothed density integrates to the eigenvalue counting function, so mu_1 is
+lambda_1 and mu_{nev+nex} lies just above lambda_{nev+nex}.  ``ritz_vectors_below`` -- the
+Galerkin condition U^H (A Y - Y Theta) = 0 and the count of Ritz values below the bound; exact
+eigenpairs at k = n.  How well the smoothed density of a few short runs estimates the spectrum
+of a large matrix is a heuristic that no closed form fixes.
 """
 
 from __future__ import annotations
@@ -78,18 +85,25 @@ def _phi_cdf(x):
     return 0.5 * (1.0 + np.vectorize(math.erf)(np.asarray(x) / math.sqrt(2.0)))
 
 
+def dos_measure(alpha, beta):
+    """Ritz values and weights of one DoS run: the eigenvalues of T_k and the squared moduli of
+    the first components of its eigenvectors (the discrete measure behind Eq. (10))."""
+    lam, S = np.linalg.eigh(tridiagonal(alpha, beta))
+    return lam, np.abs(S[0, :]) ** 2
+
+
 def dos_estimates(runs, b_sup: float, nev: int, nex: int, n: int, sigma: float = 0.25):
     """mu_1 and mu_{nev+nex} from the averaged spectral density of Eq. (10) (Alg. 6, the DoS estimate).
 
     ``runs`` is a list of (alpha, beta) pairs, one per DoS Lanczos run.  The integral of the
     Gaussian-smoothed density is a sum of normal CDFs; t with integral (nev+nex)/n is found by
-    bisection.  Parity unpinned (heuristic).
+    bisection.
     """
     ritz_all, w_all = [], []
     for alpha, beta in runs:
-        lam, S = np.linalg.eigh(tridiagonal(alpha, beta))
+        lam, w = dos_measure(alpha, beta)
         ritz_all.append(lam)
-        w_all.append(np.abs(S[0, :]) ** 2)
+        w_all.append(w)
     lo = min(float(r.min()) for r in ritz_all)
     mu_1 = lo
     half = 0.5 * (b_sup - lo) if b_sup > lo else 1.0
