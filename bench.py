@@ -540,6 +540,8 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-n10000", action="store_true",
                     help="skip the order-10000 isolated problem (filter and solves)")
+    ap.add_argument("--no-n60000", action="store_true",
+                    help="skip the FP64 filter at the order-60000 shape")
     ap.add_argument("--no-sequence", action="store_true",
                     help="skip the order-20000 sequence leg (FP64 against mixed time-to-solution)")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
@@ -797,6 +799,43 @@ def main():
     del dHr, dVr, dWr
     torch.cuda.empty_cache()
     section("filter_real", t0)
+
+    if not args.no_n60000:
+        # ---- the FP64 3M filter at the order-60000 shape (nev 2000 + nex 400 columns) ----
+        t0 = time.perf_counter()
+        w6 = wl.WORKLOADS["sequence_n60000"]
+        n6, nb6 = w6["n"], w6["nev"] + w6["nex"]
+        lam6 = wl.spectrum_for("sequence_n60000")
+        log(f"bench: generating H (n={n6}, structured unitary) on the device")
+        dH6 = wl.hermitian_torch_fast(n6, lam6, seed=5001)
+        dHp6 = torch.empty(2 * n6 * n6, dtype=torch.float64, device="cuda")
+        ctx.chase_convert_c128_to_planar64(dH6, n6, dHp6, n6, n6)
+        del dH6
+        torch.cuda.empty_cache()
+        dV6 = capi.to_device(wl.start_block(n6, nb6, 5500))
+        dW6 = torch.empty_like(dV6)
+        deg6 = wl.optimized_degree_profile(nb6, 36)
+        b6, m16, mb6 = float(lam6[-1]) + 0.05, float(lam6[0]), float(lam6[nb6 - 1])
+        fl6 = 8.0 * n6 * n6 * float(deg6.sum())
+
+        def step6():
+            ctx.chase_filter(capi.CHASE_FP64_3M, dHp6, n6, n6, dV6, dW6, n6, nb6, deg6, b6, m16,
+                             mb6)
+
+        _, ms = _timed(stream, 1, step6)
+        tf6 = fl6 / (ms * 1e-3) / 1e12
+        out["filter_n60000"] = {
+            "value": round(tf6, 3), "unit": "TFLOP/s", "peak": FP64_PEAK_TF,
+            "frac": round(tf6 / FP64_PEAK_TF, 4), "ms_per_step": round(ms, 1), "steps": 1,
+            "avg_product_ms": round(ms / int(deg6.max()), 3),
+            "workload": f"chebyshev filter, n={n6}, nev=2000, nex=400 ({nb6} columns), "
+                        "complex128 H = Q diag(lam) Q^H (structured unitary Q, clustered "
+                        "spectrum of the order-60000 sequence), sorted even degrees uniform over "
+                        "2..36, FP64 3M products on the planar copy of H (one call, no warm-up)"}
+        log(f"bench: fp64 filter n={n6}: {tf6:.2f} TFLOP/s")
+        del dHp6, dV6, dW6
+        torch.cuda.empty_cache()
+        section("filter_n60000", t0)
 
     if not args.no_n10000:
         # ---- the order-10000 isolated problem: filter and time-to-solution ----
