@@ -366,6 +366,50 @@ def test_filter_large_orders_closed_form(ctx, n, nb, profile_max, mode):
     assert err <= 1e-12
 
 
+@pytest.mark.parametrize("n,nb", [(20000, 1200), (60000, 2400)])
+def test_fp32_3m_filter_large_orders_closed_form(ctx, n, nb):
+    """The mixed solver's FP32 stage (3M products on planar complex64 H, FP64 sums of the FP32
+    accumulators every 8 K stages) at the order-20000 and order-60000 shapes, degrees 2..18,
+    against the FP64 closed form Qbar diag(p_m(lam)) Qbar^H v.  Bar: each product's FP32 sums
+    run over 128 terms before they are added into FP64, an error of about sqrt(128) u_32, and at
+    most 18 products add up linearly: 18 sqrt(128) u_32 = 1.2e-5, independent of n.  Without the
+    promotion (FP32 sums over K = n) the same bound would be 18 sqrt(n) u_32, 1.5e-4 at
+    n = 20000, which this bar rejects; measured 6.8e-7 and 7.4e-7."""
+    import torch
+    from paper_1805_10121_amd import capi
+
+    print(f"fp32 3M large-order filter n={n} nb={nb}: generating", flush=True)
+    lam = wl.spectrum_for({60000: "sequence_n60000", 20000: "sequence_n20000"}[n], n=n)
+    dH = wl.hermitian_torch_fast(n, lam, seed=7300 + n)
+    U, d = wl.structured_unitary(n, 7300 + n)
+    V = wl.start_block(n, nb, 7400)
+    deg = wl.optimized_degree_profile(nb, 18)
+    b_sup, mu_1, mu_b = float(lam[-1]) + 0.05, float(lam[0]), float(lam[nb - 1])
+    planes = torch.empty(2 * n * n, dtype=torch.float32, device="cuda")
+    ctx.chase_convert_c128_to_planar32(dH, n, planes, n, n)
+    del dH
+    torch.cuda.empty_cache()
+    dV = capi.to_device(V).to(torch.complex64)
+    dW = torch.empty_like(dV)
+    print("fp32 3M large-order filter: running", flush=True)
+    ctx.chase_filter(capi.CHASE_FP32_3M, planes, n, n, dV, dW, n, nb, deg, b_sup, mu_1, mu_b)
+    torch.cuda.synchronize()
+    del planes, dW
+    got = capi.from_device(dV).astype(np.complex128)
+    del dV
+    torch.cuda.empty_cache()
+    print("fp32 3M large-order filter: closed form", flush=True)
+    Wq = wl.apply_colmajor_qh(U, d, V)
+    for m in np.unique(deg):
+        cols = deg == m
+        Wq[:, cols] *= ch.p_closed(lam, int(m), b_sup, mu_1, mu_b)[:, None]
+    ref = wl.apply_colmajor_q(U, d, Wq)
+    err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    bar = 18 * np.sqrt(128.0) * 2.0 ** -24
+    print(f"fp32 3M large-order filter n={n}: block-relative error {err:.3e} (bar {bar:.2e})")
+    assert err <= bar
+
+
 @pytest.mark.parametrize("n,ld", [(333, 334), (333, 333), (1001, 1002)])
 def test_filter_fp32_ragged_rows_and_leading_dimension(ctx, n, ld):
     """FP32 products use 16-byte loads when pointers and leading dimensions allow it; odd n
