@@ -288,13 +288,11 @@ void chase_seq_destroy(chase_seq* seq);
  * what is already held.  What is held includes the server's fixed allocations, charged at
  * creation: the batchers' partial-sum scratch and, per worker, the product scratch of its
  * context plus a 64 MiB allowance for its rocBLAS/rocSOLVER handle.  Up to `workers` requests
- * run at once, each on its own stream; with 4 or more workers, a quarter of them (rounded down)
- * take only requests of order below 6000 and the others any request, in arrival order, so that
- * small solves do not wait for a worker behind large ones.  The filter products of complex FP64
- * and MIXED requests in flight are grouped into shared launches, one batcher (thread and stream)
- * per size class of n (below 3000, 6000, 12000, and the rest), so a small solve's products
- * never wait behind a much larger one's (real and FP32 requests run theirs on their worker's
- * stream).  A request's results are bitwise the same whatever else runs beside it.
+ * run at once, each on its own stream; the filter products of complex FP64 and MIXED requests
+ * in flight are grouped into shared launches, one batcher (thread and stream) per size class
+ * of n (below 3000, 6000, 12000, and the rest), so a small solve's products never wait behind
+ * a much larger one's (real and FP32 requests run theirs on their worker's stream).  A request's
+ * results are bitwise the same whatever else runs beside it.
  *
  * H: device, the solve's element type, n x n, ldh >= n, owned by the caller and kept valid and
  * unchanged until the request's ticket reports done.  n, nev and nex must stay the same within a

@@ -264,12 +264,6 @@ struct chase_server {
     const int c = n < 3000 ? 0 : n < 6000 ? 1 : n < 12000 ? 2 : 3;
     return batchers[c].get();
   }
-  // With four or more workers, a quarter of them take only requests of order below
-  // kSmallOrder, so that small solves (tens of milliseconds) do not queue for a worker behind
-  // large ones (seconds): the others take any request, in arrival order.
-  static constexpr int64_t kSmallOrder = 6000;
-  int small_workers = 0;
-  bool accepts(int w, int64_t n) const { return w >= small_workers || n < kSmallOrder; }
 
   struct Req {
     uint64_t seq = 0;
@@ -334,11 +328,9 @@ void chase_server::worker(int w) {
           chase_destroy(ctx);
           return;
         }
-        // first queued request whose sequence is idle, whose order this worker takes and whose
-        // memory fits
+        // first queued request whose sequence is idle and whose memory fits
         for (auto it = queue.begin(); it != queue.end(); ++it) {
           Req& r = reqs[*it];
-          if (!accepts(w, r.cfg.n)) continue;
           auto sit = seqs.find(r.seq);
           const bool exists = sit != seqs.end();
           if (exists && sit->second.busy) continue;
@@ -464,7 +456,6 @@ int chase_server_create(chase_server** out, int device, size_t mem_budget_bytes,
     }
   }
   s->worker_ws.assign(workers, 0);
-  s->small_workers = workers >= 4 ? workers / 4 : 0;
   for (int w = 0; w < workers; ++w) s->workers.emplace_back([s, w] { s->worker(w); });
   *out = s;
   return CHASE_OK;
