@@ -810,6 +810,10 @@ def main():
         dH6 = wl.hermitian_torch_fast(n6, lam6, seed=5001)
         dHp6 = torch.empty(2 * n6 * n6, dtype=torch.float64, device="cuda")
         ctx.chase_convert_c128_to_planar64(dH6, n6, dHp6, n6, n6)
+        h32_6 = None
+        if not args.no_fp32:
+            h32_6 = torch.empty((n6, n6), dtype=torch.complex64, device="cuda")
+            ctx.chase_convert_c128_to_planar32(dH6, n6, h32_6, n6, n6)   # two n x n float planes
         del dH6
         torch.cuda.empty_cache()
         dV6 = capi.to_device(wl.start_block(n6, nb6, 5500))
@@ -833,7 +837,34 @@ def main():
                         "spectrum of the order-60000 sequence), sorted even degrees uniform over "
                         "2..36, FP64 3M products on the planar copy of H (one call, no warm-up)"}
         log(f"bench: fp64 filter n={n6}: {tf6:.2f} TFLOP/s")
-        del dHp6, dV6, dW6
+        del dHp6
+        if h32_6 is not None:
+            # the mixed solver's FP32 stage at the same shape (degrees 2..18, 3M on planar
+            # complex64 H): the FP32 side of the mixed-versus-FP64 comparison
+            v32_6 = torch.empty((nb6, n6), dtype=torch.complex64, device="cuda")
+            w32_6 = torch.empty_like(v32_6)
+            ctx.chase_convert_c128_to_c64(dV6, n6, v32_6, n6, n6, nb6)
+            deg6_32 = wl.optimized_degree_profile(nb6, 18)
+            fl6_32 = 8.0 * n6 * n6 * float(deg6_32.sum())
+
+            def step6_32():
+                ctx.chase_filter(capi.CHASE_FP32_3M, h32_6, n6, n6, v32_6, w32_6, n6, nb6,
+                                 deg6_32, b6, m16, mb6)
+
+            _, ms = _timed(stream, 1, step6_32)
+            tf6_32 = fl6_32 / (ms * 1e-3) / 1e12
+            out["fp32_3m_filter_n60000"] = {
+                "value": round(tf6_32, 3),
+                "unit": "TFLOP/s (complex-equivalent, 8n^2 per column and product)",
+                "peak": FP32_PEAK_TF, "frac": round(tf6_32 / FP32_PEAK_TF, 4),
+                "executed_frac": round(0.75 * tf6_32 / FP32_PEAK_TF, 4),
+                "ms_per_step": round(ms, 1), "steps": 1,
+                "workload": f"the mixed solver's FP32 stage at n={n6}, {nb6} columns: sorted even "
+                            "degrees uniform over 2..18, 3M products on planar complex64 H with "
+                            "FP64 sums across K stages (one call, no warm-up)"}
+            log(f"bench: fp32 3M filter n={n6}: {tf6_32:.2f} TFLOP/s complex-equivalent")
+            del h32_6, v32_6, w32_6
+        del dV6, dW6
         torch.cuda.empty_cache()
         section("filter_n60000", t0)
 
