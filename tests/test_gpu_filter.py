@@ -649,6 +649,40 @@ def test_hemm_step_lower_triangle_large_orders(ctx):
         torch.cuda.empty_cache()
 
 
+def test_hemm_step_lower_triangle_order_60000(ctx):
+    """CHASE_FP64_LOWER at order 60000 with one column, the widest block whose partial sums fit
+    the context's product scratch at this order (two columns are refused).  H holds 7.2e9
+    doubles, so element offsets pass 2^31.  Checked against the structured generator's closed
+    form H x = Qbar diag(lam) Qbar^H x (no host copy of H)."""
+    import torch
+    from paper_1805_10121_amd import capi
+
+    n = 60000
+    print(f"lower-triangle product n={n}: generating", flush=True)
+    lam = wl.spectrum_for("sequence_n60000", n=n)
+    dH = wl.hermitian_torch_fast(n, lam, seed=7300)
+    U, d = wl.structured_unitary(n, 7300)
+    dX2 = torch.zeros((2, n), dtype=torch.complex128, device="cuda")
+    dO2 = torch.zeros((2, n), dtype=torch.complex128, device="cuda")
+    with pytest.raises(capi.ChaseError) as ei:
+        ctx.chase_hemm_step(capi.CHASE_FP64_LOWER, dH, n, n, dX2, n, dO2, n, 2, 1.0, 0.0, 0.0)
+    assert ei.value.code == capi.CHASE_EINVAL
+    del dX2, dO2
+    X = wl.start_block(n, 1, 7301)
+    dX = capi.to_device(X)
+    dO = torch.full((1, n), float("nan"), dtype=torch.complex128, device="cuda")
+    print(f"lower-triangle product n={n} ncols=1", flush=True)
+    ctx.chase_hemm_step(capi.CHASE_FP64_LOWER, dH, n, n, dX, n, dO, n, 1, 1.0, 0.0, 0.0)
+    torch.cuda.synchronize()
+    got = capi.from_device(dO)
+    del dH, dX, dO
+    torch.cuda.empty_cache()
+    ref = wl.apply_colmajor_q(U, d, lam[:, None] * wl.apply_colmajor_qh(U, d, X))
+    err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+    print(f"  max error {err:.2e} of max |OUT|")
+    assert err <= 1e-13
+
+
 def test_lower_triangle_argument_errors(ctx):
     import torch
     from paper_1805_10121_amd import capi
