@@ -217,17 +217,44 @@ def hermitian_torch_fast(n: int, lam: np.ndarray, seed: int, device: str = "cuda
     return H
 
 
-def symmetric_torch_fast(n: int, lam: np.ndarray, seed: int, device: str = "cuda",
-                         reflectors: int = 4):
-    """Real symmetric counterpart of ``hermitian_torch_fast``: Q = D P_r ... P_1 with real unit
-    Gaussian reflector vectors and random signs D, built in place (one n x n float64 buffer).
-    Symmetric, so the row-major tensor read column-major is the same matrix."""
-    import torch
-
+def structured_orthogonal(n: int, seed: int, reflectors: int = 4):
+    """Host-drawn factors of the real Q = D P_r ... P_1 (P_j = I - 2 u_j u_j^T, D = diag(d)):
+    unit Gaussian u_j (rows of U) and random signs d."""
     g = rng(seed)
     U = g.standard_normal((reflectors, n))
     U /= np.linalg.norm(U, axis=1, keepdims=True)
     d = np.where(g.standard_normal(n) < 0, -1.0, 1.0)
+    return U, d
+
+
+def apply_real_qt(U, d, v):
+    """Q^T v for the Q of ``structured_orthogonal`` (symmetric_torch_fast's matrix is
+    Q diag(lam) Q^T); v: (n,) or (n, k)."""
+    w = d.reshape(-1, *([1] * (np.ndim(v) - 1))) * v
+    for j in range(U.shape[0] - 1, -1, -1):
+        u = U[j]
+        w = w - 2.0 * np.multiply.outer(u, u @ w) if np.ndim(v) > 1 else w - 2.0 * u * (u @ w)
+    return w
+
+
+def apply_real_q(U, d, z):
+    """Q z (inverse of apply_real_qt)."""
+    w = np.array(z, dtype=np.float64, copy=True)
+    for j in range(U.shape[0]):
+        u = U[j]
+        w = w - 2.0 * np.multiply.outer(u, u @ w) if np.ndim(z) > 1 else w - 2.0 * u * (u @ w)
+    return d.reshape(-1, *([1] * (np.ndim(z) - 1))) * w
+
+
+def symmetric_torch_fast(n: int, lam: np.ndarray, seed: int, device: str = "cuda",
+                         reflectors: int = 4):
+    """Real symmetric counterpart of ``hermitian_torch_fast``: Q = D P_r ... P_1 with real unit
+    Gaussian reflector vectors and random signs D (``structured_orthogonal``), built in place
+    (one n x n float64 buffer).  Symmetric up to rounding of the two rank-one updates per
+    reflector, so the row-major tensor read column-major is the same matrix to that accuracy."""
+    import torch
+
+    U, d = structured_orthogonal(n, seed, reflectors)
     H = torch.diag(torch.as_tensor(lam, device=device, dtype=torch.float64))
     for j in range(reflectors):
         u = torch.as_tensor(U[j], device=device)

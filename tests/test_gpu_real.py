@@ -99,6 +99,39 @@ def test_real_filter_fp64_vs_oracle(ctx, n, nb):
     assert _relerr(capi.from_device(dV), ref.real) <= 1e-12
 
 
+@pytest.mark.parametrize("n,nb", [(20000, 1200), (60000, 2400)])
+def test_real_filter_large_orders_closed_form(ctx, n, nb):
+    """The real FP64 filter at the bench's order-20000 shape and at order 60000 (sorted even
+    degrees spread over 2..36) on the structured orthogonal generator: the whole filtered block
+    against the closed form Q diag(p_m(lam)) Q^T V of Eq. (5), block-relative 1e-12."""
+    import torch
+    from paper_1805_10121_amd import capi
+
+    print(f"real large-order filter n={n} nb={nb}: generating", flush=True)
+    lam = wl.spectrum_for({60000: "sequence_n60000"}.get(n, "sequence_n20000"), n=n)
+    dH = wl.symmetric_torch_fast(n, lam, seed=7400 + n)
+    U, d = wl.structured_orthogonal(n, 7400 + n)
+    V = wl.rng(7401).standard_normal((n, nb))
+    deg = wl.optimized_degree_profile(nb, 36)
+    b_sup, mu_1, mu_b = float(lam[-1]) + 0.05, float(lam[0]), float(lam[nb - 1])
+    dV = capi.to_device(V)
+    dW = torch.empty_like(dV)
+    print("real large-order filter: running", flush=True)
+    ctx.chase_filter(capi.CHASE_REAL_FP64, dH, n, n, dV, dW, n, nb, deg, b_sup, mu_1, mu_b)
+    torch.cuda.synchronize()
+    got = capi.from_device(dV)
+    del dH, dV, dW
+    torch.cuda.empty_cache()
+    Wq = wl.apply_real_qt(U, d, V)
+    for m in np.unique(deg):
+        cols = deg == m
+        Wq[:, cols] *= ch.p_closed(lam, int(m), b_sup, mu_1, mu_b)[:, None]
+    ref = wl.apply_real_q(U, d, Wq)
+    err = _relerr(got, ref)
+    print(f"real large-order filter n={n}: block-relative error {err:.3e}")
+    assert err <= 1e-12
+
+
 def test_real_filter_fp32_vs_oracle(ctx):
     import torch
     from paper_1805_10121_amd import capi

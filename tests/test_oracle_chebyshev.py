@@ -147,6 +147,27 @@ def test_structured_generator_closed_form():
     assert np.linalg.norm(got - ref) <= 1e-12 * np.linalg.norm(ref)
 
 
+def test_structured_orthogonal_generator_closed_form():
+    # The real device generator's matrix is Q diag(lam) Q^T with the host-reproducible factors
+    # of structured_orthogonal; the filter on it has the closed form of Eq. (5).
+    n, nb = 150, 4
+    lam = wl.spectrum_uniform(n, wl.rng(18))
+    A = wl.symmetric_torch_fast(n, lam, 23, device="cpu").numpy()
+    assert np.max(np.abs(A - A.T)) <= 1e-15
+    U, d = wl.structured_orthogonal(n, 23)
+    Q = wl.apply_real_q(U, d, np.eye(n))
+    assert np.linalg.norm(Q.T @ Q - np.eye(n)) <= 1e-13
+    assert np.linalg.norm(A - (Q * lam) @ Q.T) <= 1e-13 * n
+    V = wl.rng(19).standard_normal((n, nb))
+    deg = np.array([2, 6, 14, 36])
+    got = ch.filter_columns(A, V, deg, 1.1, lam[0], lam[12])
+    W = wl.apply_real_qt(U, d, V)
+    for a in range(nb):
+        W[:, a] *= p_lib(lam, int(deg[a]), 1.1, lam[0], lam[12])
+    ref = wl.apply_real_q(U, d, W)
+    assert np.linalg.norm(got - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
 def test_filter_on_real_symmetric_matrix():
     # Real symmetric H (the real instance of the method): the oracle's filter of a real block
     # is real and equals Q diag(p_m(lam)) Q^T V.
