@@ -410,6 +410,46 @@ def test_fp32_3m_filter_large_orders_closed_form(ctx, n, nb):
     assert err <= bar
 
 
+def test_fp32_4m_filter_large_order_closed_form(ctx):
+    """The single-precision 4M filter (CHASE_FP32 on interleaved complex64 H) at the bench's
+    order-20000 shape, degrees 2..18, against the FP64 closed form Qbar diag(p_m(lam)) Qbar^H v.
+    This tile keeps its FP32 sums over the whole K = n, so each product's error is about
+    sqrt(n) u_32 and at most 18 products add up linearly: bar 18 sqrt(n) u_32 = 1.5e-4."""
+    import torch
+    from paper_1805_10121_amd import capi
+
+    n, nb = 20000, 1200
+    print(f"fp32 4M large-order filter n={n} nb={nb}: generating", flush=True)
+    lam = wl.spectrum_for("sequence_n20000", n=n)
+    dH = wl.hermitian_torch_fast(n, lam, seed=7500 + n)
+    U, d = wl.structured_unitary(n, 7500 + n)
+    V = wl.start_block(n, nb, 7501)
+    deg = wl.optimized_degree_profile(nb, 18)
+    b_sup, mu_1, mu_b = float(lam[-1]) + 0.05, float(lam[0]), float(lam[nb - 1])
+    h32 = torch.empty((n, n), dtype=torch.complex64, device="cuda")
+    ctx.chase_convert_c128_to_c64(dH, n, h32, n, n, n)
+    del dH
+    torch.cuda.empty_cache()
+    dV = capi.to_device(V).to(torch.complex64)
+    dW = torch.empty_like(dV)
+    print("fp32 4M large-order filter: running", flush=True)
+    ctx.chase_filter(capi.CHASE_FP32, h32, n, n, dV, dW, n, nb, deg, b_sup, mu_1, mu_b)
+    torch.cuda.synchronize()
+    del h32, dW
+    got = capi.from_device(dV).astype(np.complex128)
+    del dV
+    torch.cuda.empty_cache()
+    Wq = wl.apply_colmajor_qh(U, d, V)
+    for m in np.unique(deg):
+        cols = deg == m
+        Wq[:, cols] *= ch.p_closed(lam, int(m), b_sup, mu_1, mu_b)[:, None]
+    ref = wl.apply_colmajor_q(U, d, Wq)
+    err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    bar = 18 * np.sqrt(float(n)) * 2.0 ** -24
+    print(f"fp32 4M large-order filter n={n}: block-relative error {err:.3e} (bar {bar:.2e})")
+    assert err <= bar
+
+
 @pytest.mark.parametrize("n,ld", [(333, 334), (333, 333), (1001, 1002)])
 def test_filter_fp32_ragged_rows_and_leading_dimension(ctx, n, ld):
     """FP32 products use 16-byte loads when pointers and leading dimensions allow it; odd n
