@@ -302,7 +302,7 @@ class _SeqSource:
 
 
 def run_serving(n_seq=16, problems=8, rates=(0.8,), sizes=(2000, 4000, 8000, 16000),
-                workers=8, precision_name="mixed", seed=4000):
+                workers=4, precision_name="mixed", seed=4000):
     """Continuous-batching serving of n_seq sequences: a closed-loop run (each sequence submits
     its next problem when the previous finishes) measures the saturated throughput X; then
     Poisson arrivals at r = f * X for f in rates.  The arrivals form one Poisson process of rate
@@ -566,7 +566,7 @@ def main():
                     help="sequence workload: mixed-mode switch thresholds to run")
     ap.add_argument("--deg-max-fp32", type=int, nargs="*", default=[18],
                     help="sequence workload: mixed-mode FP32 degree caps to run")
-    ap.add_argument("--serving-workers", type=int, default=8,
+    ap.add_argument("--serving-workers", type=int, default=4,
                     help="serving: concurrent solves in the server")
     ap.add_argument("--serving-rates", type=float, nargs="*", default=[0.8],
                     help="serving: Poisson rates as fractions of the closed-loop rate")
