@@ -1327,6 +1327,25 @@ int64_t group_partial_values(int64_t n, int64_t ncols) {
 template <typename T, class C, bool V16>
 hipError_t launch_group(const GroupDesc<T>* descs, int count, const GroupScratch& gs,
                         hipStream_t stream) {
+  // Products that fill the device by themselves run alone on the single-product schedule; the
+  // choice depends only on their own shape, so a product is computed the same way whatever else
+  // is in the tick.
+  auto alone = [&](const GroupDesc<T>& d) {
+    const int64_t t = ((d.n + C::BMC - 1) / C::BMC) *
+                      static_cast<int64_t>((d.ncols + C::BNC - 1) / C::BNC);
+    return gs.cus > 0 && gs.ptr && 2 * t > kGroupSlots;
+  };
+  for (int q = 0; q < count; ++q) {
+    const GroupDesc<T>& d = descs[q];
+    if (d.n <= 0 || d.ncols <= 0 || !alone(d)) continue;
+    ProductScratch ps;
+    ps.ptr = gs.ptr;
+    ps.bytes = gs.bytes;
+    ps.cus = gs.cus;
+    const hipError_t e = launch_sched<T, C>(d.H, d.ldh, d.n, d.X, d.ldx, d.OUT, d.ldo, d.ncols,
+                                            d.alpha, d.beta, d.gamma, ps, stream, V16);
+    if (e != hipSuccess) return e;
+  }
   const int64_t cap = static_cast<int64_t>(gs.bytes / sizeof(T));
   int q0 = 0;
   while (q0 < count) {
@@ -1336,6 +1355,7 @@ hipError_t launch_group(const GroupDesc<T>* descs, int count, const GroupScratch
     int q = q0;
     for (; q < count && a.count < kMaxGroup; ++q) {
       const GroupDesc<T>& src = descs[q];
+      if (src.n > 0 && src.ncols > 0 && alone(src)) continue;   // launched above
       const int64_t pv = group_partial_values<T, C>(src.n, src.ncols);
       if (pv > 0 && (!gs.ptr || pv > cap)) return hipErrorInvalidValue;   // scratch too small
       if (part + pv > cap) break;                                        // next launch

@@ -82,6 +82,7 @@ struct GroupArgs {
 struct GroupScratch {
   void* ptr = nullptr;
   size_t bytes = 0;
+  int cus = 0;  // compute units of the device (0: every product stays in a grouped launch)
 };
 // Bytes the largest single K-sliced product can need; a scratch of at least this size lets the
 // launchers run any group (in several launches when one does not fit).
@@ -90,7 +91,10 @@ size_t group_scratch_min_bytes();
 // grouped launch: its K split (ksplit) is a function of its own order and width only, its tiles
 // keep a fixed K order, and the slices of a split tile are added in slice order by a second
 // (fixup) launch.  Results therefore do not depend on the grouping.  A product with few tiles
-// is split along K so that a lone small product still occupies the whole device.
+// is split along K so that a lone small product still occupies the whole device.  A product
+// with more tiles than half the grouped launch's target (it fills the device by itself) runs
+// on its own with the single-product schedule (data-parallel or stream-K, chosen from its
+// shape and the device), using the group scratch for its partial sums when gs.cus is set.
 template <typename T>
 hipError_t launch_hemm_group(const GroupDesc<T>* descs, int count, const GroupScratch& gs,
                              hipStream_t stream);

@@ -77,6 +77,8 @@ Batcher::Batcher(int device) {
   if (hipSetDevice(device) != hipSuccess || hipStreamCreate(&impl_->stream) != hipSuccess ||
       hipEventCreateWithFlags(&impl_->tick_ev[0], hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&impl_->tick_ev[1], hipEventDisableTiming) != hipSuccess ||
+      hipDeviceGetAttribute(&impl_->gs.cus, hipDeviceAttributeMultiprocessorCount, device) !=
+          hipSuccess ||
       hipMalloc(&impl_->gs.ptr, impl_->gs.bytes) != hipSuccess) {
     impl_->gs.ptr = nullptr;
     (void)hipGetLastError();
